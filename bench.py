@@ -1,0 +1,190 @@
+"""Throughput of the event-manifold reconstruction on one MI355X.
+
+Workload: 240x180 sensor, rotating + translating Gaussian-blob texture at
+~1e6 signal events/s plus 1 % uniform noise events, a 2 s stream cut into
+blocks of 1000 events; every step pushes one block (events already resident
+in device memory) and solves it with 50 primal-dual iterations (lambda 90,
+contrast threshold 0.2).  Prints one JSON line.
+
+  value        PD iter*Mpix/s = steps * 50 * 240*180 / timed seconds / 1e6
+  events_per_s events consumed per timed second
+  roofline     the primal-dual kernel: algorithmic bytes (44 B per pixel-
+               iteration: read u, p, f, tx, ty; write u, p) per second of
+               kernel time, against 8 TB/s HBM
+  cpu_baseline the FP64 C oracle, single thread, on the first blocks of the
+               same stream (about 10 s of CPU work)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PD iter*Mpix/s and events/s at 50 it/batch; fwd+bwd vs plain; %HBM BW"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_PX_ITER = 44  # u 4 + p 12 + f 4 + tx/ty 8 read, u 4 + p 12 written
+W_, H_ = 240, 180
+EVENTS_PER_BATCH = 1000
+ITERS = 50
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def load_stream(n_batches: int):
+    """The calibrated 240x180 stream, long enough for n_batches blocks (cached in /tmp)."""
+    import evgen
+
+    duration = max(2_000_000, int(math.ceil(n_batches * EVENTS_PER_BATCH / 1e6 * 1e6 * 1.02)))
+    key = hashlib.sha1(f"davis240-seed2-{duration}".encode()).hexdigest()[:12]
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"evrec_stream_{key}.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        return evgen.Events(z["t"], z["x"], z["y"], z["p"], z["n"])
+    s, _, _, _ = evgen.davis240(seed=2, duration_us=duration)
+    ev = s.events
+    try:
+        np.savez(path, t=ev.t, x=ev.x, y=ev.y, p=ev.p, n=ev.is_noise)
+    except OSError:
+        pass
+    return ev
+
+
+def run_gpu(ev, steps, warmup, fuse, profile):
+    import torch
+    from paper_1607_06283_amd import rec
+
+    dev = torch.device("cuda", 0)
+    t = torch.from_numpy(ev.t).to(dev)
+    x = torch.from_numpy(ev.x.view(np.int16)).to(dev)
+    y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
+    p = torch.from_numpy(ev.p).to(dev)
+    r = rec.Reconstructor(W_, H_, fuse_iters=fuse)
+    B = EVENTS_PER_BATCH
+
+    def step(i):
+        a = i * B
+        rc = rec.rec_push_events(r.ctx, t.data_ptr() + 8 * a, x.data_ptr() + 2 * a,
+                                 y.data_ptr() + 2 * a, p.data_ptr() + a, B, 1)
+        if rc:
+            raise rec.RecError(rc, "rec_push_events")
+        rc, _ = rec.rec_solve(r.ctx, ITERS, False)
+        if rc:
+            raise rec.RecError(rc, "rec_solve")
+
+    for i in range(warmup):
+        step(i)
+    r.sync()
+    torch.cuda.synchronize()
+    if profile:
+        rec.rec_profile(r.ctx, True)
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + steps):
+        step(i)
+    torch.cuda.synchronize()
+    r.sync()
+    dt = time.perf_counter() - t0
+    prof = rec.rec_profile_read(r.ctx) if profile else None
+    u = r.image(rec.REC_U)
+    r.close()
+    return dt, prof, u
+
+
+def cpu_baseline(ev, budget_s=10.0):
+    import oracle
+
+    o = oracle.Oracle(oracle.Params(W_, H_))
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        b = ev.slice(n * EVENTS_PER_BATCH, (n + 1) * EVENTS_PER_BATCH)
+        o.push_events(b)
+        o.solve(ITERS)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or (n + 1) * EVENTS_PER_BATCH > len(ev):
+            break
+    rate = n * ITERS * W_ * H_ / el / 1e6
+    return {"value": round(rate, 3), "unit": "PD iter*Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} blocks of the same stream ({n * EVENTS_PER_BATCH} events, "
+                      f"{n * ITERS} iterations of 240x180) in {el:.1f} s, FP64 C, one thread",
+            "events_per_s": round(n * EVENTS_PER_BATCH / el, 1)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1980)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fuse", type=int, default=8, help="iterations per fused launch (0: unfused)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the reconstruction of one event stream runs on "
+              "a single MI355X here (--gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    need = args.warmup + args.steps
+    log(f"bench: generating 240x180 stream for {need} blocks")
+    ev = load_stream(need)
+    if len(ev) < need * EVENTS_PER_BATCH:
+        raise SystemExit("stream too short")
+    log("bench: timed pass")
+    dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False)
+    px_iters = args.steps * ITERS * W_ * H_
+    value = px_iters / dt / 1e6
+    ev_rate = args.steps * EVENTS_PER_BATCH / dt
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "240x180 sensor, rotating+translating texture, ~1e6 signal "
+                               "events/s + 1% noise, blocks of 1000 events, 50 FP32 primal-dual "
+                               "iterations per block, lambda 90, threshold 0.2",
+                   "width": W_, "height": H_, "events_per_batch": EVENTS_PER_BATCH,
+                   "iters_per_batch": ITERS, "fuse_iters": args.fuse},
+        "events_per_s": round(ev_rate, 1),
+        "realtime_factor": round(ev_rate / 1e6, 3),
+    }
+    if not args.no_profile:
+        log("bench: per-kernel timing pass")
+        _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True)
+        pd_ms = prof.ms[2]
+        pd_launches = int(prof.launches[2])
+        achieved = BYTES_PER_PX_ITER * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
+        out["roofline"] = {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_pd_fused" if args.fuse else "k_primal+k_dual",
+            "avg_launch_us": round(pd_ms / pd_launches * 1e3, 3),
+            "launches": pd_launches,
+            "bytes_per_px_iter": BYTES_PER_PX_ITER,
+        }
+        out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),
+                            "pd": round(pd_ms, 3)}
+    if not args.no_cpu:
+        log("bench: oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(ev)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

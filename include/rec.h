@@ -1,0 +1,197 @@
+/*
+ * rec.h - C ABI of the MI355X (gfx950) intensity-image reconstruction for
+ * event cameras on the event manifold (Reinbacher, Graber, Pock, BMVC 2016).
+ *
+ * For each block of events the library
+ *   1. scatters the events into per-pixel polarity counts and the latest
+ *      timestamp of every pixel (Section 3: e^n = (x^n, y^n, theta^n, t^n)),
+ *   2. forms the data image f = u_prev * exp(Delta+ n+ - Delta- n-)
+ *      (eqn. intensity_update applied for every event of the block),
+ *   3. forms the time surface tau = (t_ref - t_last) / T_s and its forward
+ *      differences, which define the metric g = I + grad tau grad tau^T
+ *      (Section 3.1, eqns. 1-2; discrete operator L_g of eqn. 3),
+ *   4. runs Chambolle-Pock primal-dual iterations for eqn. (5), the
+ *      manifold TV with the generalised Kullback-Leibler data term on
+ *      [u_min, u_max], with the closed-form proximal maps of Section 3.2,
+ *      warm-started from the previous block's (u, p).
+ *
+ * Conventions
+ *   - Images are H x W, row-major, x = column index (fast), y = row index.
+ *   - Timestamps are int64 microseconds and must not decrease (ties allowed),
+ *     also across pushes.  Relative times are formed from exact int64
+ *     differences, divided in FP64, and only then rounded to FP32.
+ *   - The primal image u, the data image f, the dual field p (3 planes) and
+ *     the time differences are FP32 in device memory; the primal-dual gap is
+ *     accumulated in FP64.
+ *   - Every function returns an int status: REC_OK (0) or a negative REC_E*
+ *     code.  No C++ exception crosses this interface.
+ *
+ * Ownership
+ *   - The caller allocates the device workspace (rec_workspace_bytes) and
+ *     keeps it alive until rec_destroy; the library never allocates device
+ *     memory.  It allocates the host-side context and a pinned host staging
+ *     buffer for host-pointer pushes, both released by rec_destroy.
+ *   - Event arrays and output buffers belong to the caller; they only need
+ *     to stay valid for the duration of the call (device-pointer pushes:
+ *     until the stream has executed the push, i.e. until the next
+ *     synchronising call or a stream synchronisation by the caller).
+ *
+ * Streams and synchronisation
+ *   - All device work is enqueued on the hipStream_t given to rec_init
+ *     (NULL = the default stream).  rec_push_events (device pointers) and
+ *     rec_solve without stats do not synchronise.  rec_solve with stats,
+ *     rec_get_image, rec_gap_history, rec_profile_read and rec_sync do.
+ *   - Errors found on the device (device-pointer pushes) are reported by the
+ *     next synchronising call; the rejected push changes no state.
+ *
+ * Threading: a context must not be used from two threads at once; distinct
+ * contexts are independent.  The library has no global mutable state.
+ */
+#ifndef REC_H
+#define REC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes. */
+enum {
+    REC_OK = 0,
+    REC_EINVAL = -1,   /* bad argument or parameter, polarity not in {-1, +1} */
+    REC_ERANGE = -2,   /* event coordinate outside the image */
+    REC_EORDER = -3,   /* timestamp lower than the previous one */
+    REC_EDEVICE = -4,  /* a HIP runtime call failed */
+    REC_ENUMERIC = -5, /* non-finite gap or energy */
+    REC_ESTATE = -6,   /* call not valid in the context's state */
+    REC_ENOMEM = -7    /* workspace too small or host allocation failed */
+};
+
+/* Planes readable with rec_get_image. */
+enum {
+    REC_U = 0,         /* float[H*W]  reconstructed image u */
+    REC_F = 1,         /* float[H*W]  data image f of the last solved block */
+    REC_TIME = 2,      /* float[H*W]  tau = (t_ref - t_last) / T_s, now */
+    REC_METRIC_G = 3,  /* float[H*W]  G = 1 + tx^2 + ty^2 of the last block */
+    REC_STATE_P = 4,   /* float[3*H*W] dual field p, planes p1, p2, p3 */
+    REC_TX = 5,        /* float[H*W]  tau(x+1, y) - tau(x, y), 0 on the last column */
+    REC_TY = 6,        /* float[H*W]  tau(x, y+1) - tau(x, y), 0 on the last row */
+    REC_COUNT_POS = 7, /* int32[H*W]  positive events of the pending block */
+    REC_COUNT_NEG = 8, /* int32[H*W]  negative events of the pending block */
+    REC_T_LAST = 9     /* int64[H*W]  latest timestamp (first stream timestamp if none) */
+};
+
+typedef struct rec_ctx rec_ctx;
+
+/* Method and launch parameters.  rec_default_params fills every field. */
+typedef struct {
+    int32_t width, height;   /* image size, 1 .. 65535 each */
+    double lambda;           /* data-term weight lambda (eqn. 5); default 90 */
+    double delta_pos;        /* contrast thresholds Delta+, Delta- (Section 3); */
+    double delta_neg;        /*   default 0.2 each */
+    double u_min, u_max;     /* intensity range (eqn. data_term); default 1, e */
+    double tau, sigma;       /* primal / dual steps; tau*sigma*(8 + 4 sqrt 2) <= 1
+                                (Section 3.2); default (8 + 4 sqrt 2)^(-1/2) each */
+    double time_unit_us;     /* T_s: microseconds per unit of tau; default 1000;
+                                0 switches the manifold off (t = const, Section 4.2) */
+    double u_init;           /* constant initial image if rec_init gets no u0;
+                                default sqrt(u_min * u_max) */
+    int32_t iters;           /* iterations per rec_solve when called with 0; default 50 */
+    int32_t gap_every;       /* gap / energy every this many iterations; 0 = never */
+    int32_t fuse_iters;      /* iterations per fused launch; 0 = unfused two-kernel loop;
+                                default 8 */
+    int32_t max_events;      /* largest host-pointer push handled in one piece (larger
+                                pushes are split); sizes the device staging; default 65536 */
+    int32_t tile_rows;       /* rows per lane in the fused kernel (1..16); 0 = automatic */
+    int32_t tile_waves;      /* wavefronts per fused workgroup (1..16); 0 = automatic */
+    int32_t reserved[6];     /* must be 0 */
+} rec_params;
+
+/* Statistics of one rec_solve (filled when stats are requested). */
+typedef struct {
+    double gap;              /* last sampled primal-dual gap (NaN if none sampled) */
+    double energy;           /* energy of eqn. (5) at the same iterate */
+    int32_t iters_run;
+    int32_t gap_samples;
+    int64_t t_ref_us;        /* timestamp of the last event pushed so far */
+    int64_t events_in_batch; /* events consumed by this solve */
+} rec_stats;
+
+/* Per-kernel-class device time, collected when profiling is on. */
+typedef struct {
+    double ms[4];            /* 0 push, 1 build, 2 primal-dual, 3 gap */
+    int64_t launches[4];
+    int64_t pd_pixel_iters;  /* pixel-iterations done by the primal-dual launches */
+} rec_profile_t;
+
+/* Fill *prm with the defaults for a width x height sensor. */
+void rec_default_params(rec_params* prm, int32_t width, int32_t height);
+
+/* Validate parameters on the host; REC_OK or REC_EINVAL.  No device call. */
+int rec_check_params(const rec_params* prm);
+
+/* Device workspace bytes needed for prm (0 if prm is invalid). */
+size_t rec_workspace_bytes(const rec_params* prm);
+
+/* Host validation of an event array (no device call): polarity in {-1, +1}
+ * (REC_EINVAL), x < width and y < height (REC_ERANGE), t non-decreasing and
+ * t[0] >= t_prev (REC_EORDER; pass INT64_MIN for no previous timestamp).
+ * The first failing event decides the code. */
+int rec_check_events(const int64_t* t_us, const uint16_t* x, const uint16_t* y,
+                     const int8_t* polarity, int64_t n, int32_t width, int32_t height,
+                     int64_t t_prev);
+
+/* Create a context on the current HIP device.  dev_workspace: device memory of
+ * at least rec_workspace_bytes(prm) bytes, 256-byte aligned.  hip_stream: a
+ * hipStream_t or NULL.  u0: optional host image (H*W floats, each in
+ * (0, inf)) used as the initial u instead of prm->u_init.  On success *out
+ * holds the context; the workspace is initialised asynchronously on the stream. */
+int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+             const float* u0, rec_ctx** out);
+
+/* Add n events to the pending block (SoA arrays; host memory if on_device == 0,
+ * device memory otherwise).  All-or-nothing.  Host pointers are validated on
+ * the host before anything is enqueued (errors returned directly); device
+ * pointers are validated on the device (errors reported by the next
+ * synchronising call).  n == 0 is a no-op. */
+int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const uint16_t* y,
+                    const int8_t* polarity, int64_t n, int on_device);
+
+/* Solve the pending block: build f, tau and the metric, then run `iters`
+ * primal-dual iterations (prm->iters if iters <= 0) warm-started from the
+ * previous (u, p).  With stats != NULL the call synchronises and fills it;
+ * a non-finite gap or energy returns REC_ENUMERIC. */
+int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats);
+
+/* Copy a plane (see the REC_U.. list) into out: host memory if on_device == 0
+ * (synchronises), device memory otherwise (enqueued, then synchronises so
+ * pending device errors are reported). */
+int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device);
+
+/* Gap and energy samples of the last rec_solve, in order; returns the number
+ * of samples (>= 0) or an error.  At most cap values are written. */
+int rec_gap_history(rec_ctx* c, double* gap, double* energy, int32_t cap);
+
+/* Wait for the context's stream and report deferred device errors. */
+int rec_sync(rec_ctx* c);
+
+/* Turn per-launch device timing on (1) or off (0); turning it on clears the
+ * totals.  Timing adds an event pair around every launch. */
+int rec_profile(rec_ctx* c, int enable);
+
+/* Read the timing totals collected since profiling was turned on (synchronises). */
+int rec_profile_read(rec_ctx* c, rec_profile_t* out);
+
+/* Release the context (after synchronising its stream).  NULL is a no-op. */
+int rec_destroy(rec_ctx* c);
+
+/* Static description of a status code. */
+const char* rec_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REC_H */

@@ -1,0 +1,578 @@
+// Device kernels for event-manifold intensity reconstruction on gfx950.
+//
+//   k_init          workspace initialisation
+//   k_push_small    validate + scatter one push in a single workgroup
+//   k_validate / k_scatter / k_push_finalize   the same for large pushes
+//   k_build         data image f, time differences tx/ty, reset counts
+//   k_primal, k_dual    one primal-dual iteration as two plain kernels
+//   k_pd_fused      several iterations per HBM round trip on a register tile
+//   k_gap, k_gap_final  primal-dual gap and energy (FP64 accumulation)
+//   k_time_plane, k_metric_plane   readback helpers
+#include "kernels.h"
+#include "pd_math.h"
+
+namespace rec {
+
+namespace {
+
+__device__ __forceinline__ int32_t event_error(int64_t t, int64_t prev, uint16_t x, uint16_t y,
+                                               int8_t pol, int32_t W, int32_t H) {
+    if (pol != 1 && pol != -1) return kErrInval;
+    if (x >= W || y >= H) return kErrRange;
+    if (t < prev) return kErrOrder;
+    return 0;
+}
+
+__device__ __forceinline__ int64_t resolved_last(int64_t tl, int64_t t_first) {
+    return tl == kNever ? t_first : tl;
+}
+
+// blockIdx -> tile such that each of the 8 XCDs (which receive blocks
+// round-robin) works on one contiguous run of tiles, so halo rows shared by
+// neighbouring tiles are fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd * q + min(xcd, rem) + idx;
+}
+
+// ---------------------------------------------------------------- init
+
+__global__ void k_init(Planes P, size_t np, float u_init, int keep_u) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) {
+        DevState* st = P.st;
+        st->t_ref = 0;
+        st->t_first = 0;
+        st->first_bad = kNoBad;
+        st->batch_events = 0;
+        st->last_events = 0;
+        st->started = 0;
+        st->err = 0;
+    }
+    if (k >= np) return;
+    float u = keep_u ? P.u[0][k] : u_init;
+    P.u[0][k] = u;
+    P.f[k] = u;
+    P.p[0][k] = 0.0f;
+    P.p[0][np + k] = 0.0f;
+    P.p[0][2 * np + k] = 0.0f;
+    P.tx[k] = 0.0f;
+    P.ty[k] = 0.0f;
+    P.t_last[k] = kNever;
+    P.npos[k] = 0;
+    P.nneg[k] = 0;
+}
+
+// ---------------------------------------------------------------- push
+
+__device__ __forceinline__ void scatter_one(const Planes& P, int32_t W, int64_t t, uint16_t x,
+                                            uint16_t y, int8_t pol) {
+    const size_t k = (size_t)y * W + x;
+    if (pol > 0)
+        atomicAdd(P.npos + k, 1);
+    else
+        atomicAdd(P.nneg + k, 1);
+    atomicMax((long long*)(P.t_last + k), (long long)t);
+}
+
+__device__ __forceinline__ void accept_push(DevState* st, int64_t t0, int64_t tn, int64_t n) {
+    if (!st->started) {
+        st->started = 1;
+        st->t_first = t0;
+    }
+    st->t_ref = tn;
+    st->batch_events += n;
+}
+
+__device__ __forceinline__ void reject_push(DevState* st, int32_t code) {
+    if (st->err == 0) st->err = code;
+}
+
+__global__ __launch_bounds__(1024) void k_push_small(Planes P, Frame fr, const int64_t* t,
+                                                     const uint16_t* x, const uint16_t* y,
+                                                     const int8_t* pol, int64_t n) {
+    __shared__ unsigned long long first_bad;
+    DevState* st = P.st;
+    if (threadIdx.x == 0) first_bad = (unsigned long long)kNoBad;
+    __syncthreads();
+    const int64_t prev0 = st->started ? st->t_ref : INT64_MIN;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int64_t prev = i ? t[i - 1] : prev0;
+        if (event_error(t[i], prev, x[i], y[i], pol[i], fr.W, fr.H))
+            atomicMin(&first_bad, (unsigned long long)i);
+    }
+    __syncthreads();
+    const int64_t fb = (int64_t)first_bad;
+    if (fb != kNoBad) {
+        if (threadIdx.x == 0) {
+            const int64_t prev = fb ? t[fb - 1] : prev0;
+            reject_push(st, event_error(t[fb], prev, x[fb], y[fb], pol[fb], fr.W, fr.H));
+        }
+        return;
+    }
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) scatter_one(P, fr.W, t[i], x[i], y[i], pol[i]);
+    if (threadIdx.x == 0) accept_push(st, t[0], t[n - 1], n);
+}
+
+__global__ void k_validate(Planes P, Frame fr, const int64_t* t, const uint16_t* x,
+                           const uint16_t* y, const int8_t* pol, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    DevState* st = P.st;
+    const int64_t prev = i ? t[i - 1] : (st->started ? st->t_ref : INT64_MIN);
+    if (event_error(t[i], prev, x[i], y[i], pol[i], fr.W, fr.H))
+        atomicMin((unsigned long long*)&st->first_bad, (unsigned long long)i);
+}
+
+__global__ void k_scatter(Planes P, Frame fr, const int64_t* t, const uint16_t* x,
+                          const uint16_t* y, const int8_t* pol, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (P.st->first_bad != kNoBad) return;
+    scatter_one(P, fr.W, t[i], x[i], y[i], pol[i]);
+}
+
+__global__ void k_push_finalize(Planes P, Frame fr, const int64_t* t, const uint16_t* x,
+                                const uint16_t* y, const int8_t* pol, int64_t n) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    DevState* st = P.st;
+    const int64_t fb = st->first_bad;
+    if (fb != kNoBad) {
+        const int64_t prev = fb ? t[fb - 1] : (st->started ? st->t_ref : INT64_MIN);
+        reject_push(st, event_error(t[fb], prev, x[fb], y[fb], pol[fb], fr.W, fr.H));
+        st->first_bad = kNoBad;
+        return;
+    }
+    accept_push(st, t[0], t[n - 1], n);
+}
+
+// ---------------------------------------------------------------- build
+
+// f = u_prev * exp(Delta+ n+ - Delta- n-), formed in FP64 and rounded once;
+// tx = (t_last(x) - t_last(x+1)) / T_s = tau(x+1) - tau(x) from the exact
+// int64 difference (0 on the last column), likewise ty; counts reset.
+__global__ void k_build(Planes P, Frame fr, int cur, double dpos, double dneg, double ts) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    DevState* st = P.st;
+    if (k == 0) {
+        st->last_events = st->batch_events;
+        st->batch_events = 0;
+    }
+    if (k >= np) return;
+    const int32_t j = (int32_t)(k % fr.W), i = (int32_t)(k / fr.W);
+    const int32_t a = P.npos[k], b = P.nneg[k];
+    const double e = dpos * (double)a - dneg * (double)b;
+    P.f[k] = (float)((double)P.u[cur][k] * exp(e));
+    P.npos[k] = 0;
+    P.nneg[k] = 0;
+    float dx = 0.0f, dy = 0.0f;
+    if (ts > 0.0) {
+        const int64_t t0 = st->t_first;
+        const int64_t tl = resolved_last(P.t_last[k], t0);
+        if (j < fr.W - 1) dx = (float)((double)(tl - resolved_last(P.t_last[k + 1], t0)) / ts);
+        if (i < fr.H - 1) dy = (float)((double)(tl - resolved_last(P.t_last[k + fr.W], t0)) / ts);
+    }
+    P.tx[k] = dx;
+    P.ty[k] = dy;
+}
+
+__global__ void k_time_plane(Planes P, Frame fr, double ts, float* out) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const DevState* st = P.st;
+    const int64_t tl = resolved_last(P.t_last[k], st->t_first);
+    out[k] = ts > 0.0 ? (float)((double)(st->t_ref - tl) / ts) : 0.0f;
+}
+
+__global__ void k_metric_plane(Planes P, Frame fr, float* out) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const float tx = P.tx[k], ty = P.ty[k];
+    out[k] = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, 1.0f));
+}
+
+// ---------------------------------------------------------------- plain loop
+
+// Primal half-step for every pixel: needs q = M^T p here, at the left and
+// at the upper neighbour.
+__global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts kc, int cur) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (j >= fr.W || i >= fr.H) return;
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)i * fr.W + j;
+    const float* p = P.p[cur];
+    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam);
+    const float qx = q_x(c, p[k], p[np + k], p[2 * np + k]);
+    const float qy = q_y(c, p[k], p[np + k], p[2 * np + k]);
+    float qxl = 0.0f, qyu = 0.0f;
+    if (j > 0) {
+        const size_t kl = k - 1;
+        const Coef cl = make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam);
+        qxl = q_x(cl, p[kl], p[np + kl], p[2 * np + kl]);
+    }
+    if (i > 0) {
+        const size_t ku = k - fr.W;
+        const Coef cu = make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam);
+        qyu = q_y(cu, p[ku], p[np + ku], p[2 * np + ku]);
+    }
+    P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, j < fr.W - 1, j > 0, i < fr.H - 1,
+                             i > 0, c, kc.tau, kc.umin, kc.umax);
+}
+
+// Dual half-step: needs the extrapolated primal here, right and below.
+__global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc, int cur) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (j >= fr.W || i >= fr.H) return;
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)i * fr.W + j;
+    const float* uo = P.u[cur];
+    const float* un = P.u[cur ^ 1];
+    const float ut = extrapolate(un[k], uo[k]);
+    float gx = 0.0f, gy = 0.0f;
+    if (j < fr.W - 1) gx = extrapolate(un[k + 1], uo[k + 1]) - ut;
+    if (i < fr.H - 1) gy = extrapolate(un[k + fr.W], uo[k + fr.W]) - ut;
+    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam);
+    const float* p = P.p[cur];
+    float p1 = p[k], p2 = p[np + k], p3 = p[2 * np + k];
+    dual(p1, p2, p3, gx, gy, c, kc.sigma);
+    float* po = P.p[cur ^ 1];
+    po[k] = p1;
+    po[np + k] = p2;
+    po[2 * np + k] = p3;
+}
+
+// ---------------------------------------------------------------- fused loop
+
+__device__ __forceinline__ float lane_from_left(float v) {   // value of lane - 1
+    return __shfl_up(v, 1, 64);
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 1
+    return __shfl_down(v, 1, 64);
+}
+
+// K primal-dual iterations per launch on a register tile.  A workgroup of
+// NW wavefronts covers a 64-column x (NW*R)-row region: lane = column, each
+// lane holds R consecutive rows in registers, wavefront w holds rows
+// [w*R, w*R + R).  Horizontal neighbours come from adjacent lanes, vertical
+// ones from the lane's own registers or, across wavefronts, through LDS.
+// Each iteration widens the dependency cone by one pixel, so after K
+// iterations the region minus a K-pixel border is exact; only that interior
+// is written.  Reads (u, p) from buffer `cur`, writes buffer `cur ^ 1`.
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
+                                                      int cur, int K, int tiles_x, int ntiles) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int OW = 64 - 2 * K, OH = NW * R - 2 * K;
+    const int gx = txi * OW - K + lane;
+    const int gy0 = tyi * OH - K + wave * R;
+    const size_t np = (size_t)fr.W * fr.H;
+    const float* __restrict__ uin = P.u[cur];
+    const float* __restrict__ pin = P.p[cur];
+
+    float u[R], p1[R], p2[R], p3[R];
+    Coef c[R];
+    const bool col_in = gx >= 0 && gx < fr.W;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = gy0 + r;
+        float uu = 1.0f, a = 0.0f, b = 0.0f, d = 0.0f, f = 1.0f, tx = 0.0f, ty = 0.0f;
+        if (col_in && gy >= 0 && gy < fr.H) {
+            const size_t k = (size_t)gy * fr.W + gx;
+            uu = uin[k];
+            a = pin[k];
+            b = pin[np + k];
+            d = pin[2 * np + k];
+            f = P.f[k];
+            tx = P.tx[k];
+            ty = P.ty[k];
+        }
+        u[r] = uu;
+        p1[r] = a;
+        p2[r] = b;
+        p3[r] = d;
+        c[r] = make_coef(tx, ty, f, kc.taulam);
+    }
+    const bool has_r = gx < fr.W - 1, has_l = gx > 0;
+
+    __shared__ float xq[NW > 1 ? NW : 1][64];
+    __shared__ float xu[NW > 1 ? NW : 1][64];
+
+    for (int it = 0; it < K; ++it) {
+        float qx[R], qy[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            qx[r] = q_x(c[r], p1[r], p2[r], p3[r]);
+            qy[r] = q_y(c[r], p1[r], p2[r], p3[r]);
+        }
+        float qy_top = 0.0f;
+        if constexpr (NW > 1) {
+            xq[wave][lane] = qy[R - 1];
+            __syncthreads();
+            if (wave > 0) qy_top = xq[wave - 1][lane];
+        }
+        float un[R], ut[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            const float qxl = lane_from_left(qx[r]);
+            const float qyu = r > 0 ? qy[r - 1] : qy_top;
+            un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, has_r, has_l, gy < fr.H - 1, gy > 0,
+                           c[r], kc.tau, kc.umin, kc.umax);
+            ut[r] = extrapolate(un[r], u[r]);
+        }
+        float ut_bot = 0.0f;
+        if constexpr (NW > 1) {
+            xu[wave][lane] = ut[0];
+            __syncthreads();
+            if (wave < NW - 1) ut_bot = xu[wave + 1][lane];
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            const float utr = lane_from_right(ut[r]);
+            const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
+            const float gxx = has_r ? utr - ut[r] : 0.0f;
+            const float gyy = gy < fr.H - 1 ? utd - ut[r] : 0.0f;
+            dual(p1[r], p2[r], p3[r], gxx, gyy, c[r], kc.sigma);
+            u[r] = un[r];
+        }
+    }
+
+    float* __restrict__ uout = P.u[cur ^ 1];
+    float* __restrict__ pout = P.p[cur ^ 1];
+    const bool col_out = col_in && lane >= K && lane < 64 - K;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = wave * R + r;
+        const int gy = gy0 + r;
+        if (col_out && row >= K && row < NW * R - K && gy >= 0 && gy < fr.H) {
+            const size_t k = (size_t)gy * fr.W + gx;
+            uout[k] = u[r];
+            pout[k] = p1[r];
+            pout[np + k] = p2[r];
+            pout[2 * np + k] = p3[r];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- gap
+
+__device__ __forceinline__ double warp_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Per-pixel gap terms and energy in FP64 from the FP32 state:
+//   term1 = s |A| - <A, p>,   A = L_g u
+//   term2 = (u - v)(b + d) - b f log(u / v),  d = L_g^* p, b = lambda s,
+//           v = clamp(b f / (b + d)) if b + d > 0 else u_max
+//   energy = s |A| + b (u - f log u)
+__global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double lambda,
+                                                   double umin, double umax, int cur) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double g = 0.0, e = 0.0;
+    if (k < np) {
+        const int j = (int)(k % fr.W), i = (int)(k / fr.W);
+        const float* u = P.u[cur];
+        const float* p = P.p[cur];
+        auto qxy = [&](size_t kk, double& qx, double& qy) {
+            const double tx = P.tx[kk], ty = P.ty[kk];
+            const double G = 1.0 + tx * tx + ty * ty;
+            const double a = p[kk], b = p[np + kk], d = p[2 * np + kk];
+            qx = ((1.0 + ty * ty) * a - tx * ty * b + tx * d) / G;
+            qy = (-tx * ty * a + (1.0 + tx * tx) * b + ty * d) / G;
+        };
+        const double tx = P.tx[k], ty = P.ty[k];
+        const double G = 1.0 + tx * tx + ty * ty;
+        const double s = sqrt(G);
+        const double uk = u[k];
+        const double ux = j < fr.W - 1 ? (double)u[k + 1] - uk : 0.0;
+        const double uy = i < fr.H - 1 ? (double)u[k + fr.W] - uk : 0.0;
+        const double A1 = ((1.0 + ty * ty) * ux - tx * ty * uy) / G;
+        const double A2 = ((1.0 + tx * tx) * uy - tx * ty * ux) / G;
+        const double A3 = (tx * ux + ty * uy) / G;
+        const double nA = sqrt(A1 * A1 + A2 * A2 + A3 * A3);
+        const double t1 = s * nA - (A1 * p[k] + A2 * p[np + k] + A3 * p[2 * np + k]);
+        double qx, qy, qxl = 0.0, qyu = 0.0, dummy;
+        qxy(k, qx, qy);
+        if (j > 0) qxy(k - 1, qxl, dummy);
+        if (i > 0) qxy(k - fr.W, dummy, qyu);
+        const double div = (j < fr.W - 1 ? qx : 0.0) - (j > 0 ? qxl : 0.0) +
+                           (i < fr.H - 1 ? qy : 0.0) - (i > 0 ? qyu : 0.0);
+        const double d = -div;
+        const double b = lambda * s;
+        const double f = P.f[k];
+        double v = umax;
+        if (b + d > 0.0) v = fmin(fmax(b * f / (b + d), umin), umax);
+        const double t2 = (uk - v) * (b + d) - b * f * log(uk / v);
+        g = t1 + t2;
+        e = s * nA + b * (uk - f * log(uk));
+    }
+    __shared__ double sg[kGapBlock / 64], se[kGapBlock / 64];
+    g = warp_sum(g);
+    e = warp_sum(e);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sg[w] = g;
+        se[w] = e;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int q = 0; q < kGapBlock / 64; ++q) {
+            a += sg[q];
+            b += se[q];
+        }
+        P.gap_part[2 * blockIdx.x] = a;
+        P.gap_part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// Fixed-order sum of the per-block partials into history slot `slot`.
+__global__ __launch_bounds__(256) void k_gap_final(Planes P, size_t nblocks, int slot) {
+    __shared__ double sg[256], se[256];
+    double a = 0.0, b = 0.0;
+    for (size_t q = threadIdx.x; q < nblocks; q += 256) {
+        a += P.gap_part[2 * q];
+        b += P.gap_part[2 * q + 1];
+    }
+    sg[threadIdx.x] = a;
+    se[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sg[threadIdx.x] += sg[threadIdx.x + w];
+            se[threadIdx.x] += se[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        P.gap_hist[2 * slot] = sg[0];
+        P.gap_hist[2 * slot + 1] = se[0];
+    }
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <int R, int NW>
+hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, int cur, int K, hipStream_t s) {
+    const int OW = 64 - 2 * K, OH = NW * R - 2 * K;
+    const int tiles_x = (fr.W + OW - 1) / OW;
+    const int tiles_y = (fr.H + OH - 1) / OH;
+    const int ntiles = tiles_x * tiles_y;
+    hipLaunchKernelGGL((k_pd_fused<R, NW>), dim3(ntiles), dim3(64 * NW), 0, s, P, fr, kc, cur, K,
+                       tiles_x, ntiles);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t gap_blocks(size_t np) { return (np + kGapBlock - 1) / kGapBlock; }
+
+hipError_t launch_init(const Planes& P, Frame fr, float u_init, bool keep_u, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    hipLaunchKernelGGL(k_init, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, np, u_init,
+                       keep_u ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_push(const Planes& P, Frame fr, const int64_t* t, const uint16_t* x,
+                       const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    if (n <= kSmallPush) {
+        hipLaunchKernelGGL(k_push_small, dim3(1), dim3(1024), 0, s, P, fr, t, x, y, pol, n);
+        return hipGetLastError();
+    }
+    const unsigned g = blocks_for((size_t)n, 256);
+    hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, P, fr, t, x, y, pol, n);
+    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, P, fr, t, x, y, pol, n);
+    hipLaunchKernelGGL(k_push_finalize, dim3(1), dim3(64), 0, s, P, fr, t, x, y, pol, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_build(const Planes& P, Frame fr, int cur, double dpos, double dneg,
+                        double time_unit_us, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    hipLaunchKernelGGL(k_build, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr, cur, dpos, dneg,
+                       time_unit_us);
+    return hipGetLastError();
+}
+
+hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hipStream_t s) {
+    const dim3 grid((fr.W + 63) / 64, (fr.H + 3) / 4);
+    hipLaunchKernelGGL(k_primal, grid, dim3(256), 0, s, P, fr, kc, cur);
+    hipLaunchKernelGGL(k_dual, grid, dim3(256), 0, s, P, fr, kc, cur);
+    return hipGetLastError();
+}
+
+bool fused_shape_supported(int rows, int waves) {
+    switch (rows * 100 + waves) {
+        case 202: case 204: case 208: case 216:
+        case 401: case 402: case 404: case 408: case 416:
+        case 801: case 802: case 804: case 808:
+        case 1601: case 1602: case 1604:
+            return true;
+        default:
+            return false;
+    }
+}
+
+hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, int cur, int iters,
+                           int rows, int waves, hipStream_t s) {
+    switch (rows * 100 + waves) {
+        case 202: return fused_launch<2, 2>(P, fr, kc, cur, iters, s);
+        case 204: return fused_launch<2, 4>(P, fr, kc, cur, iters, s);
+        case 208: return fused_launch<2, 8>(P, fr, kc, cur, iters, s);
+        case 216: return fused_launch<2, 16>(P, fr, kc, cur, iters, s);
+        case 401: return fused_launch<4, 1>(P, fr, kc, cur, iters, s);
+        case 402: return fused_launch<4, 2>(P, fr, kc, cur, iters, s);
+        case 404: return fused_launch<4, 4>(P, fr, kc, cur, iters, s);
+        case 408: return fused_launch<4, 8>(P, fr, kc, cur, iters, s);
+        case 416: return fused_launch<4, 16>(P, fr, kc, cur, iters, s);
+        case 801: return fused_launch<8, 1>(P, fr, kc, cur, iters, s);
+        case 802: return fused_launch<8, 2>(P, fr, kc, cur, iters, s);
+        case 804: return fused_launch<8, 4>(P, fr, kc, cur, iters, s);
+        case 808: return fused_launch<8, 8>(P, fr, kc, cur, iters, s);
+        case 1601: return fused_launch<16, 1>(P, fr, kc, cur, iters, s);
+        case 1602: return fused_launch<16, 2>(P, fr, kc, cur, iters, s);
+        case 1604: return fused_launch<16, 4>(P, fr, kc, cur, iters, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
+                      int cur, int slot, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t nb = gap_blocks(np);
+    hipLaunchKernelGGL(k_gap, dim3((unsigned)nb), dim3(kGapBlock), 0, s, P, fr, lambda, umin, umax,
+                       cur);
+    hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(256), 0, s, P, nb, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
+                             hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    hipLaunchKernelGGL(k_time_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr,
+                       time_unit_us, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_metric_plane(const Planes& P, Frame fr, float* out, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    hipLaunchKernelGGL(k_metric_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr, out);
+    return hipGetLastError();
+}
+
+}  // namespace rec

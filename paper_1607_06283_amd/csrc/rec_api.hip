@@ -1,0 +1,549 @@
+// C ABI of the reconstruction library: parameter and event validation,
+// workspace layout, context state and launch sequencing.  All arithmetic of
+// the method runs in the kernels of kernels.hip.
+#include <math.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "kernels.h"
+#include "rec.h"
+
+using rec::Planes;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kProfClasses = 4;  // push, build, primal-dual, gap
+constexpr size_t kProfFlush = 1u << 15;
+
+inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Lays the workspace out (base == nullptr: only sizes it).  Returns bytes.
+size_t carve(const rec_params* prm, char* base, Planes* P) {
+    const size_t np = (size_t)prm->width * (size_t)prm->height;
+    const size_t ne = (size_t)prm->max_events;
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = align_up(off);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    Planes q;
+    q.st = (rec::DevState*)take(sizeof(rec::DevState));
+    q.u[0] = (float*)take(np * 4);
+    q.u[1] = (float*)take(np * 4);
+    q.p[0] = (float*)take(3 * np * 4);
+    q.p[1] = (float*)take(3 * np * 4);
+    q.f = (float*)take(np * 4);
+    q.tx = (float*)take(np * 4);
+    q.ty = (float*)take(np * 4);
+    q.t_last = (int64_t*)take(np * 8);
+    q.npos = (int32_t*)take(np * 4);
+    q.nneg = (int32_t*)take(np * 4);
+    q.ev_t = (int64_t*)take(ne * 8);
+    q.ev_x = (uint16_t*)take(ne * 2);
+    q.ev_y = (uint16_t*)take(ne * 2);
+    q.ev_p = (int8_t*)take(ne);
+    q.gap_part = (double*)take(rec::gap_blocks(np) * 2 * sizeof(double));
+    q.gap_hist = (double*)take((size_t)rec::kGapHistCap * 2 * sizeof(double));
+    if (P) *P = q;
+    return align_up(off);
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+}  // namespace
+
+struct rec_ctx {
+    rec_params prm;
+    Planes P;
+    rec::Frame fr;
+    rec::IterConsts kc;
+    hipStream_t stream;
+    int device;
+    int cur;                 // which ping-pong buffers hold the current (u, p)
+    int rows, waves;         // fused tile shape
+    int kmax;                // largest iterations per fused launch for that shape
+    // host staging for host-pointer pushes
+    char* pinned;
+    int64_t* h_t;
+    uint16_t* h_x;
+    uint16_t* h_y;
+    int8_t* h_p;
+    hipEvent_t staging_done;
+    bool staging_busy;
+    // host mirror of the device stream state (valid while only host pushes ran)
+    bool mirror_known;
+    bool mirror_started;
+    int64_t mirror_tref;
+    int gap_samples;
+    // profiling
+    bool prof_on;
+    std::vector<hipEvent_t> prof_pool;
+    std::vector<int> prof_cls;   // class of each recorded (start, stop) pair
+    std::vector<int64_t> prof_work;
+    size_t prof_used;
+    double prof_ms[kProfClasses];
+    int64_t prof_launches[kProfClasses];
+    int64_t prof_pd_px_iters;
+};
+
+namespace {
+
+int dev_err(hipError_t e) { return e == hipSuccess ? REC_OK : REC_EDEVICE; }
+
+hipEvent_t prof_event(rec_ctx* c) {
+    if (c->prof_used == c->prof_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->prof_pool.push_back(e);
+    }
+    return c->prof_pool[c->prof_used++];
+}
+
+int prof_flush(rec_ctx* c) {
+    if (!c->prof_used) return REC_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return REC_EDEVICE;
+    for (size_t q = 0; q < c->prof_cls.size(); ++q) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, c->prof_pool[2 * q], c->prof_pool[2 * q + 1]) != hipSuccess)
+            return REC_EDEVICE;
+        const int k = c->prof_cls[q];
+        c->prof_ms[k] += ms;
+        c->prof_launches[k] += 1;
+        if (k == 2) c->prof_pd_px_iters += c->prof_work[q];
+    }
+    c->prof_cls.clear();
+    c->prof_work.clear();
+    c->prof_used = 0;
+    return REC_OK;
+}
+
+// Brackets one launch with a timing event pair when profiling is on.
+template <class F>
+int timed(rec_ctx* c, int cls, int64_t work, F&& launch) {
+    if (!c->prof_on) return dev_err(launch());
+    if (c->prof_used + 2 > kProfFlush) {
+        const int rc = prof_flush(c);
+        if (rc) return rc;
+    }
+    hipEvent_t a = prof_event(c);
+    hipEvent_t b = prof_event(c);
+    if (!a || !b) return REC_EDEVICE;
+    if (hipEventRecord(a, c->stream) != hipSuccess) return REC_EDEVICE;
+    const hipError_t e = launch();
+    if (e != hipSuccess) return REC_EDEVICE;
+    if (hipEventRecord(b, c->stream) != hipSuccess) return REC_EDEVICE;
+    c->prof_cls.push_back(cls);
+    c->prof_work.push_back(work);
+    return REC_OK;
+}
+
+// Reads the device state after synchronising; reports and clears a deferred
+// push error.
+int read_state(rec_ctx* c, rec::DevState* out) {
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return REC_EDEVICE;
+    rec::DevState st;
+    if (hipMemcpy(&st, c->P.st, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess) return REC_EDEVICE;
+    if (out) *out = st;
+    if (st.err != 0) {
+        const int32_t zero = 0;
+        if (hipMemcpy(&c->P.st->err, &zero, sizeof(zero), hipMemcpyHostToDevice) != hipSuccess)
+            return REC_EDEVICE;
+        return st.err;
+    }
+    return REC_OK;
+}
+
+void choose_shape(const rec_params* prm, int* rows, int* waves) {
+    int r = prm->tile_rows, w = prm->tile_waves;
+    if (r == 0 || w == 0) {
+        r = 8;
+        w = 4;
+    }
+    *rows = r;
+    *waves = w;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rec_default_params(rec_params* prm, int32_t width, int32_t height) {
+    if (!prm) return;
+    memset(prm, 0, sizeof(*prm));
+    prm->width = width;
+    prm->height = height;
+    prm->lambda = 90.0;
+    prm->delta_pos = 0.2;
+    prm->delta_neg = 0.2;
+    prm->u_min = 1.0;
+    prm->u_max = exp(1.0);
+    prm->tau = 1.0 / sqrt(8.0 + 4.0 * sqrt(2.0));
+    prm->sigma = prm->tau;
+    prm->time_unit_us = 1000.0;
+    prm->u_init = sqrt(prm->u_min * prm->u_max);
+    prm->iters = 50;
+    prm->gap_every = 0;
+    prm->fuse_iters = 8;
+    prm->max_events = 65536;
+    prm->tile_rows = 0;
+    prm->tile_waves = 0;
+}
+
+int rec_check_params(const rec_params* prm) {
+    if (!prm) return REC_EINVAL;
+    if (prm->width < 1 || prm->height < 1 || prm->width > 65535 || prm->height > 65535)
+        return REC_EINVAL;
+    if (!finite_pos(prm->lambda) || !finite_pos(prm->delta_pos) || !finite_pos(prm->delta_neg))
+        return REC_EINVAL;
+    if (!finite_pos(prm->u_min) || !isfinite(prm->u_max) || !(prm->u_max > prm->u_min))
+        return REC_EINVAL;
+    if (!finite_pos(prm->tau) || !finite_pos(prm->sigma)) return REC_EINVAL;
+    if (prm->tau * prm->sigma * (8.0 + 4.0 * sqrt(2.0)) > 1.0 + 1e-12) return REC_EINVAL;
+    if (!isfinite(prm->time_unit_us) || prm->time_unit_us < 0.0) return REC_EINVAL;
+    if (!finite_pos(prm->u_init)) return REC_EINVAL;
+    if (prm->iters < 0 || prm->gap_every < 0) return REC_EINVAL;
+    if (prm->fuse_iters < 0 || prm->fuse_iters > 31) return REC_EINVAL;
+    if (prm->max_events < 1 || prm->max_events > (1 << 28)) return REC_EINVAL;
+    if ((prm->tile_rows == 0) != (prm->tile_waves == 0)) return REC_EINVAL;
+    if (prm->tile_rows && !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves))
+        return REC_EINVAL;
+    for (int i = 0; i < 6; ++i)
+        if (prm->reserved[i] != 0) return REC_EINVAL;
+    return REC_OK;
+}
+
+size_t rec_workspace_bytes(const rec_params* prm) {
+    if (rec_check_params(prm) != REC_OK) return 0;
+    return carve(prm, nullptr, nullptr);
+}
+
+int rec_check_events(const int64_t* t_us, const uint16_t* x, const uint16_t* y,
+                     const int8_t* polarity, int64_t n, int32_t width, int32_t height,
+                     int64_t t_prev) {
+    if (n < 0 || width < 1 || height < 1) return REC_EINVAL;
+    if (n == 0) return REC_OK;
+    if (!t_us || !x || !y || !polarity) return REC_EINVAL;
+    int64_t prev = t_prev;
+    for (int64_t i = 0; i < n; ++i) {
+        if (polarity[i] != 1 && polarity[i] != -1) return REC_EINVAL;
+        if (x[i] >= width || y[i] >= height) return REC_ERANGE;
+        if (t_us[i] < prev) return REC_EORDER;
+        prev = t_us[i];
+    }
+    return REC_OK;
+}
+
+int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* hip_stream,
+             const float* u0, rec_ctx** out) {
+    if (!out) return REC_EINVAL;
+    *out = nullptr;
+    int rc = rec_check_params(prm);
+    if (rc) return rc;
+    if (!dev_workspace || ((uintptr_t)dev_workspace & (kAlign - 1))) return REC_EINVAL;
+    const size_t need = carve(prm, nullptr, nullptr);
+    if (ws_bytes < need) return REC_ENOMEM;
+    const size_t np = (size_t)prm->width * prm->height;
+    if (u0) {
+        for (size_t k = 0; k < np; ++k)
+            if (!(isfinite(u0[k]) && u0[k] > 0.0f)) return REC_EINVAL;
+    }
+    rec_ctx* c = new (std::nothrow) rec_ctx();
+    if (!c) return REC_ENOMEM;
+    c->prm = *prm;
+    carve(prm, (char*)dev_workspace, &c->P);
+    c->fr = {prm->width, prm->height};
+    c->kc.tau = (float)prm->tau;
+    c->kc.sigma = (float)prm->sigma;
+    c->kc.taulam = (float)(prm->tau * prm->lambda);
+    c->kc.umin = (float)prm->u_min;
+    c->kc.umax = (float)prm->u_max;
+    c->stream = (hipStream_t)hip_stream;
+    c->cur = 0;
+    choose_shape(prm, &c->rows, &c->waves);
+    c->kmax = (c->rows * c->waves - 1) / 2;
+    if (c->kmax > 31) c->kmax = 31;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return REC_EDEVICE;
+    }
+    const size_t ne = (size_t)prm->max_events;
+    const size_t pb = align_up(ne * 8) + align_up(ne * 2) * 2 + align_up(ne);
+    if (hipHostMalloc((void**)&c->pinned, pb, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return REC_ENOMEM;
+    }
+    c->h_t = (int64_t*)c->pinned;
+    c->h_x = (uint16_t*)(c->pinned + align_up(ne * 8));
+    c->h_y = (uint16_t*)(c->pinned + align_up(ne * 8) + align_up(ne * 2));
+    c->h_p = (int8_t*)(c->pinned + align_up(ne * 8) + 2 * align_up(ne * 2));
+    if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return REC_EDEVICE;
+    }
+    c->mirror_known = true;
+    c->mirror_started = false;
+    c->mirror_tref = 0;
+    if (u0) {
+        if (hipMemcpyAsync(c->P.u[0], u0, np * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            rec_destroy(c);
+            return REC_EDEVICE;
+        }
+    }
+    rc = dev_err(rec::launch_init(c->P, c->fr, (float)prm->u_init, u0 != nullptr, c->stream));
+    if (!rc && u0 && hipStreamSynchronize(c->stream) != hipSuccess) rc = REC_EDEVICE;
+    if (rc) {
+        rec_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return REC_OK;
+}
+
+int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const uint16_t* y,
+                    const int8_t* polarity, int64_t n, int on_device) {
+    if (!c || n < 0) return REC_EINVAL;
+    if (n == 0) return REC_OK;
+    if (!t_us || !x || !y || !polarity) return REC_EINVAL;
+    if (on_device) {
+        c->mirror_known = false;
+        return timed(c, 0, n, [&] {
+            return rec::launch_push(c->P, c->fr, t_us, x, y, polarity, n, c->stream);
+        });
+    }
+    if (!c->mirror_known) {
+        rec::DevState st;
+        const int rc = read_state(c, &st);
+        if (rc) return rc;
+        c->mirror_known = true;
+        c->mirror_started = st.started != 0;
+        c->mirror_tref = st.t_ref;
+    }
+    const int rc = rec_check_events(t_us, x, y, polarity, n, c->prm.width, c->prm.height,
+                                    c->mirror_started ? c->mirror_tref : INT64_MIN);
+    if (rc) return rc;
+    const int64_t cap = c->prm.max_events;
+    for (int64_t a = 0; a < n; a += cap) {
+        const int64_t m = (n - a < cap) ? n - a : cap;
+        if (c->staging_busy && hipEventSynchronize(c->staging_done) != hipSuccess) return REC_EDEVICE;
+        memcpy(c->h_t, t_us + a, (size_t)m * 8);
+        memcpy(c->h_x, x + a, (size_t)m * 2);
+        memcpy(c->h_y, y + a, (size_t)m * 2);
+        memcpy(c->h_p, polarity + a, (size_t)m);
+        hipError_t e = hipMemcpyAsync(c->P.ev_t, c->h_t, (size_t)m * 8, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->P.ev_x, c->h_x, (size_t)m * 2, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->P.ev_y, c->h_y, (size_t)m * 2, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->P.ev_p, c->h_p, (size_t)m, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return REC_EDEVICE;
+        const int r2 = timed(c, 0, m, [&] {
+            return rec::launch_push(c->P, c->fr, c->P.ev_t, c->P.ev_x, c->P.ev_y, c->P.ev_p, m,
+                                    c->stream);
+        });
+        if (r2) return r2;
+        if (hipEventRecord(c->staging_done, c->stream) != hipSuccess) return REC_EDEVICE;
+        c->staging_busy = true;
+    }
+    c->mirror_started = true;
+    c->mirror_tref = t_us[n - 1];
+    return REC_OK;
+}
+
+int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
+    if (!c) return REC_EINVAL;
+    if (iters <= 0) iters = c->prm.iters;
+    const int64_t np = (int64_t)c->fr.W * c->fr.H;
+    int rc = timed(c, 1, np, [&] {
+        return rec::launch_build(c->P, c->fr, c->cur, c->prm.delta_pos, c->prm.delta_neg,
+                                 c->prm.time_unit_us, c->stream);
+    });
+    if (rc) return rc;
+    const int ge = c->prm.gap_every;
+    const int fuse = c->prm.fuse_iters;
+    const int step = fuse > 0 ? (fuse < c->kmax ? fuse : c->kmax) : 1;
+    int samples = 0;
+    for (int it = 0; it < iters;) {
+        int m = iters - it < step ? iters - it : step;
+        if (ge > 0) {
+            const int to_gap = ge - it % ge;
+            if (m > to_gap) m = to_gap;
+        }
+        if (fuse > 0) {
+            rc = timed(c, 2, np * m, [&] {
+                return rec::launch_pd_fused(c->P, c->fr, c->kc, c->cur, m, c->rows, c->waves,
+                                            c->stream);
+            });
+        } else {
+            rc = timed(c, 2, np, [&] {
+                return rec::launch_pd_plain(c->P, c->fr, c->kc, c->cur, c->stream);
+            });
+        }
+        if (rc) return rc;
+        c->cur ^= 1;
+        it += m;
+        if (ge > 0 && it % ge == 0) {
+            const int slot = samples < rec::kGapHistCap ? samples : rec::kGapHistCap - 1;
+            rc = timed(c, 3, np, [&] {
+                return rec::launch_gap(c->P, c->fr, c->prm.lambda, c->prm.u_min, c->prm.u_max,
+                                       c->cur, slot, c->stream);
+            });
+            if (rc) return rc;
+            ++samples;
+        }
+    }
+    c->gap_samples = samples;
+    if (!stats) return REC_OK;
+    rec::DevState st;
+    rc = read_state(c, &st);
+    stats->iters_run = iters;
+    stats->gap_samples = samples;
+    stats->t_ref_us = st.t_ref;
+    stats->events_in_batch = st.last_events;
+    stats->gap = NAN;
+    stats->energy = NAN;
+    if (rc) return rc;
+    if (samples > 0) {
+        const int slot = samples < rec::kGapHistCap ? samples - 1 : rec::kGapHistCap - 1;
+        double ge2[2];
+        if (hipMemcpy(ge2, c->P.gap_hist + 2 * slot, sizeof(ge2), hipMemcpyDeviceToHost) != hipSuccess)
+            return REC_EDEVICE;
+        stats->gap = ge2[0];
+        stats->energy = ge2[1];
+        if (!isfinite(ge2[0]) || !isfinite(ge2[1])) return REC_ENUMERIC;
+    }
+    return REC_OK;
+}
+
+int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
+    if (!c || !out) return REC_EINVAL;
+    const size_t np = (size_t)c->fr.W * c->fr.H;
+    const void* src = nullptr;
+    size_t bytes = np * 4;
+    hipError_t e = hipSuccess;
+    // derived planes go through a spare ping-pong buffer unless written in place
+    float* spare = c->P.u[c->cur ^ 1];
+    switch (which) {
+        case REC_U: src = c->P.u[c->cur]; break;
+        case REC_F: src = c->P.f; break;
+        case REC_TX: src = c->P.tx; break;
+        case REC_TY: src = c->P.ty; break;
+        case REC_STATE_P: src = c->P.p[c->cur]; bytes = 3 * np * 4; break;
+        case REC_COUNT_POS: src = c->P.npos; break;
+        case REC_COUNT_NEG: src = c->P.nneg; break;
+        case REC_T_LAST: src = c->P.t_last; bytes = np * 8; break;
+        case REC_TIME: {
+            float* dst = on_device ? (float*)out : spare;
+            e = rec::launch_time_plane(c->P, c->fr, c->prm.time_unit_us, dst, c->stream);
+            src = on_device ? nullptr : spare;
+            break;
+        }
+        case REC_METRIC_G: {
+            float* dst = on_device ? (float*)out : spare;
+            e = rec::launch_metric_plane(c->P, c->fr, dst, c->stream);
+            src = on_device ? nullptr : spare;
+            break;
+        }
+        default: return REC_EINVAL;
+    }
+    if (e != hipSuccess) return REC_EDEVICE;
+    if (src) {
+        e = hipMemcpyAsync(out, src, bytes, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                           c->stream);
+        if (e != hipSuccess) return REC_EDEVICE;
+    }
+    rec::DevState st;
+    int rc = read_state(c, &st);
+    if (which == REC_T_LAST && !on_device) {
+        int64_t* o = (int64_t*)out;
+        for (size_t k = 0; k < np; ++k)
+            if (o[k] == rec::kNever) o[k] = st.t_first;
+    }
+    return rc;
+}
+
+int rec_gap_history(rec_ctx* c, double* gap, double* energy, int32_t cap) {
+    if (!c || cap < 0) return REC_EINVAL;
+    int rc = read_state(c, nullptr);
+    if (rc) return rc;
+    int n = c->gap_samples < rec::kGapHistCap ? c->gap_samples : rec::kGapHistCap;
+    if (n > cap) n = cap;
+    if (n > 0) {
+        std::vector<double> buf(2 * (size_t)n);
+        if (hipMemcpy(buf.data(), c->P.gap_hist, buf.size() * sizeof(double), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return REC_EDEVICE;
+        for (int i = 0; i < n; ++i) {
+            if (gap) gap[i] = buf[2 * i];
+            if (energy) energy[i] = buf[2 * i + 1];
+        }
+    }
+    return n;
+}
+
+int rec_sync(rec_ctx* c) {
+    if (!c) return REC_EINVAL;
+    return read_state(c, nullptr);
+}
+
+int rec_profile(rec_ctx* c, int enable) {
+    if (!c) return REC_EINVAL;
+    if (enable) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return REC_EDEVICE;
+        c->prof_cls.clear();
+        c->prof_work.clear();
+        c->prof_used = 0;
+        for (int k = 0; k < kProfClasses; ++k) {
+            c->prof_ms[k] = 0.0;
+            c->prof_launches[k] = 0;
+        }
+        c->prof_pd_px_iters = 0;
+    }
+    c->prof_on = enable != 0;
+    return REC_OK;
+}
+
+int rec_profile_read(rec_ctx* c, rec_profile_t* out) {
+    if (!c || !out) return REC_EINVAL;
+    const int rc = prof_flush(c);
+    if (rc) return rc;
+    for (int k = 0; k < kProfClasses; ++k) {
+        out->ms[k] = c->prof_ms[k];
+        out->launches[k] = c->prof_launches[k];
+    }
+    out->pd_pixel_iters = c->prof_pd_px_iters;
+    return REC_OK;
+}
+
+int rec_destroy(rec_ctx* c) {
+    if (!c) return REC_OK;
+    int rc = REC_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) rc = REC_EDEVICE;
+    for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return rc;
+}
+
+const char* rec_strerror(int code) {
+    switch (code) {
+        case REC_OK: return "success";
+        case REC_EINVAL: return "invalid argument, parameter or event polarity";
+        case REC_ERANGE: return "event coordinate outside the image";
+        case REC_EORDER: return "event timestamp lower than the previous one";
+        case REC_EDEVICE: return "HIP runtime error";
+        case REC_ENUMERIC: return "non-finite gap or energy";
+        case REC_ESTATE: return "call not valid in the current state";
+        case REC_ENOMEM: return "workspace too small or allocation failed";
+        default: return "unknown status code";
+    }
+}
+
+}  // extern "C"

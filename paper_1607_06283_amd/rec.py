@@ -1,0 +1,304 @@
+"""ctypes binding of ``librec.so`` (the C ABI declared in include/rec.h).
+
+The functions below carry the C names and only marshal arguments; every step
+of the reconstruction runs in the library's HIP kernels.  ``Reconstructor``
+adds the PyTorch plumbing: the device workspace is a ``torch.uint8`` tensor
+on the current CUDA (HIP) device and launches go to torch's current stream.
+
+The library must have been built (``paper_1607_06283_amd.build.build()``);
+importing this module without it raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librec.so")
+
+REC_OK, REC_EINVAL, REC_ERANGE, REC_EORDER, REC_EDEVICE, REC_ENUMERIC, REC_ESTATE, REC_ENOMEM = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+(REC_U, REC_F, REC_TIME, REC_METRIC_G, REC_STATE_P, REC_TX, REC_TY, REC_COUNT_POS,
+ REC_COUNT_NEG, REC_T_LAST) = range(10)
+
+_PLANE_DTYPE = {REC_COUNT_POS: np.int32, REC_COUNT_NEG: np.int32, REC_T_LAST: np.int64}
+
+
+class rec_params(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+        ("lambda_", ctypes.c_double),
+        ("delta_pos", ctypes.c_double), ("delta_neg", ctypes.c_double),
+        ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
+        ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("time_unit_us", ctypes.c_double),
+        ("u_init", ctypes.c_double),
+        ("iters", ctypes.c_int32),
+        ("gap_every", ctypes.c_int32),
+        ("fuse_iters", ctypes.c_int32),
+        ("max_events", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32),
+        ("tile_waves", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 6),
+    ]
+
+
+class rec_stats(ctypes.Structure):
+    _fields_ = [
+        ("gap", ctypes.c_double), ("energy", ctypes.c_double),
+        ("iters_run", ctypes.c_int32), ("gap_samples", ctypes.c_int32),
+        ("t_ref_us", ctypes.c_int64), ("events_in_batch", ctypes.c_int64),
+    ]
+
+
+class rec_profile_t(ctypes.Structure):
+    _fields_ = [
+        ("ms", ctypes.c_double * 4),
+        ("launches", ctypes.c_int64 * 4),
+        ("pd_pixel_iters", ctypes.c_int64),
+    ]
+
+
+EXPORTS = (
+    "rec_default_params", "rec_check_params", "rec_workspace_bytes", "rec_check_events",
+    "rec_init", "rec_push_events", "rec_solve", "rec_get_image", "rec_gap_history",
+    "rec_sync", "rec_profile", "rec_profile_read", "rec_destroy", "rec_strerror",
+)
+
+_lib = None
+_vp = ctypes.c_void_p
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1607_06283_amd.build.build()")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(rec_params)
+    lib.rec_default_params.restype = None
+    lib.rec_default_params.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.rec_check_params.restype = ctypes.c_int
+    lib.rec_check_params.argtypes = [P]
+    lib.rec_workspace_bytes.restype = ctypes.c_size_t
+    lib.rec_workspace_bytes.argtypes = [P]
+    lib.rec_check_events.restype = ctypes.c_int
+    lib.rec_check_events.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int32,
+                                     ctypes.c_int32, ctypes.c_int64]
+    lib.rec_init.restype = ctypes.c_int
+    lib.rec_init.argtypes = [P, _vp, ctypes.c_size_t, _vp, _vp, ctypes.POINTER(_vp)]
+    lib.rec_push_events.restype = ctypes.c_int
+    lib.rec_push_events.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
+    lib.rec_solve.restype = ctypes.c_int
+    lib.rec_solve.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(rec_stats)]
+    lib.rec_get_image.restype = ctypes.c_int
+    lib.rec_get_image.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int]
+    lib.rec_gap_history.restype = ctypes.c_int
+    lib.rec_gap_history.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+    lib.rec_sync.restype = ctypes.c_int
+    lib.rec_sync.argtypes = [_vp]
+    lib.rec_profile.restype = ctypes.c_int
+    lib.rec_profile.argtypes = [_vp, ctypes.c_int]
+    lib.rec_profile_read.restype = ctypes.c_int
+    lib.rec_profile_read.argtypes = [_vp, ctypes.POINTER(rec_profile_t)]
+    lib.rec_destroy.restype = ctypes.c_int
+    lib.rec_destroy.argtypes = [_vp]
+    lib.rec_strerror.restype = ctypes.c_char_p
+    lib.rec_strerror.argtypes = [ctypes.c_int]
+    _lib = lib
+    return lib
+
+
+class RecError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {rec_strerror(code)} ({code})")
+
+
+def _check(rc: int, where: str) -> int:
+    if rc < 0:
+        raise RecError(rc, where)
+    return rc
+
+
+def _addr(a) -> Optional[int]:
+    """Data pointer of a numpy array or torch tensor; ints pass through as
+    addresses and None as NULL."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+# ---------------------------------------------------------------------------
+# C functions, same names
+# ---------------------------------------------------------------------------
+
+def rec_default_params(width: int, height: int, **overrides) -> rec_params:
+    p = rec_params()
+    load().rec_default_params(ctypes.byref(p), int(width), int(height))
+    for k, v in overrides.items():
+        setattr(p, "lambda_" if k in ("lambda", "lam") else k, v)
+    return p
+
+
+def rec_check_params(prm: rec_params) -> int:
+    return load().rec_check_params(ctypes.byref(prm))
+
+
+def rec_workspace_bytes(prm: rec_params) -> int:
+    return load().rec_workspace_bytes(ctypes.byref(prm))
+
+
+def rec_check_events(t, x, y, p, width: int, height: int, t_prev: int = -(1 << 63)) -> int:
+    n = int(len(t))
+    return load().rec_check_events(_addr(t), _addr(x), _addr(y), _addr(p), n, int(width),
+                                   int(height), int(t_prev))
+
+
+def rec_init(prm: rec_params, workspace_ptr: int, workspace_bytes: int, stream_ptr: int,
+             u0: Optional[np.ndarray] = None) -> Tuple[int, Optional[int]]:
+    h = _vp()
+    u = None if u0 is None else np.ascontiguousarray(u0, dtype=np.float32)
+    rc = load().rec_init(ctypes.byref(prm), workspace_ptr, int(workspace_bytes), stream_ptr,
+                         _addr(u), ctypes.byref(h))
+    return rc, h.value
+
+
+def rec_push_events(ctx: int, t, x, y, p, n: int, on_device: int) -> int:
+    return load().rec_push_events(ctx, _addr(t), _addr(x), _addr(y), _addr(p), int(n),
+                                  int(on_device))
+
+
+def rec_solve(ctx: int, iters: int, want_stats: bool = False) -> Tuple[int, Optional[rec_stats]]:
+    st = rec_stats() if want_stats else None
+    rc = load().rec_solve(ctx, int(iters), ctypes.byref(st) if st is not None else None)
+    return rc, st
+
+
+def rec_get_image(ctx: int, which: int, out, on_device: int) -> int:
+    return load().rec_get_image(ctx, int(which), _addr(out), int(on_device))
+
+
+def rec_gap_history(ctx: int, cap: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
+    g = np.zeros(max(cap, 1))
+    e = np.zeros(max(cap, 1))
+    n = _check(load().rec_gap_history(ctx, g.ctypes.data, e.ctypes.data, int(cap)),
+               "rec_gap_history")
+    return g[:n], e[:n]
+
+
+def rec_sync(ctx: int) -> int:
+    return load().rec_sync(ctx)
+
+
+def rec_profile(ctx: int, enable: bool) -> int:
+    return load().rec_profile(ctx, 1 if enable else 0)
+
+
+def rec_profile_read(ctx: int) -> rec_profile_t:
+    out = rec_profile_t()
+    _check(load().rec_profile_read(ctx, ctypes.byref(out)), "rec_profile_read")
+    return out
+
+
+def rec_destroy(ctx: Optional[int]) -> int:
+    return load().rec_destroy(ctx)
+
+
+def rec_strerror(code: int) -> str:
+    return load().rec_strerror(int(code)).decode()
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper: torch provides the device memory and the stream
+# ---------------------------------------------------------------------------
+
+class Reconstructor:
+    """One event stream on one GPU.
+
+    ``params`` may be a ``rec_params`` or keyword overrides of the defaults.
+    """
+
+    def __init__(self, width: int, height: int, params: Optional[rec_params] = None,
+                 u0: Optional[np.ndarray] = None, device=None, stream=None, **overrides):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device available")
+        self.torch = torch
+        self.prm = params if params is not None else rec_default_params(width, height, **overrides)
+        if params is not None and overrides:
+            for k, v in overrides.items():
+                setattr(self.prm, "lambda_" if k in ("lambda", "lam") else k, v)
+        _check(rec_check_params(self.prm), "rec_check_params")
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else device
+        nbytes = rec_workspace_bytes(self.prm)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            rc, h = rec_init(self.prm, self.workspace.data_ptr(), nbytes,
+                             self.stream.cuda_stream, u0)
+        _check(rc, "rec_init")
+        self.ctx = h
+        self.shape = (self.prm.height, self.prm.width)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            rec_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def push(self, t, x, y, p, on_device: Optional[bool] = None) -> None:
+        """Push events given as numpy arrays (host) or torch tensors (device)."""
+        n = int(t.shape[0])
+        if on_device is None:
+            on_device = not isinstance(t, np.ndarray)
+        if not on_device:
+            t = np.ascontiguousarray(t, np.int64)
+            x = np.ascontiguousarray(x, np.uint16)
+            y = np.ascontiguousarray(y, np.uint16)
+            p = np.ascontiguousarray(p, np.int8)
+        _check(rec_push_events(self.ctx, t, x, y, p, n, 1 if on_device else 0), "rec_push_events")
+
+    def solve(self, iters: int = 0, stats: bool = False) -> Optional[rec_stats]:
+        rc, st = rec_solve(self.ctx, iters, stats)
+        _check(rc, "rec_solve")
+        return st
+
+    def image(self, which: int = REC_U, device: bool = False):
+        np_ = self.shape[0] * self.shape[1]
+        n = 3 * np_ if which == REC_STATE_P else np_
+        dt = _PLANE_DTYPE.get(which, np.float32)
+        shape = (3,) + self.shape if which == REC_STATE_P else self.shape
+        if device:
+            tdt = {np.int32: self.torch.int32, np.int64: self.torch.int64}.get(dt, self.torch.float32)
+            out = self.torch.empty(n, dtype=tdt, device=self.device)
+            _check(rec_get_image(self.ctx, which, out, 1), "rec_get_image")
+            return out.view(*shape)
+        out = np.empty(n, dtype=dt)
+        _check(rec_get_image(self.ctx, which, out, 0), "rec_get_image")
+        return out.reshape(shape)
+
+    def gap_history(self):
+        return rec_gap_history(self.ctx)
+
+    def sync(self) -> None:
+        _check(rec_sync(self.ctx), "rec_sync")
+
+
+DEFAULT_STEP = 1.0 / math.sqrt(8.0 + 4.0 * math.sqrt(2.0))

@@ -1,0 +1,120 @@
+"""The C-ABI library on the CPU: it loads, exports every declared symbol, and
+its host-side validation works without touching a GPU."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1607_06283_amd import rec
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rec.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rec_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_match_header():
+    lib = rec.load()
+    names = declared_functions()
+    assert set(names) == set(rec.EXPORTS)
+    for n in names:
+        getattr(lib, n)
+
+
+def test_struct_sizes_match_header_layout():
+    # rec_params: 2 int32, 9 double, 6 int32, 6 int32 reserved = 8 + 72 + 24 + 24
+    import ctypes
+    assert ctypes.sizeof(rec.rec_params) == 128
+    assert ctypes.sizeof(rec.rec_stats) == 40
+    assert ctypes.sizeof(rec.rec_profile_t) == 72
+
+
+def test_default_params():
+    p = rec.rec_default_params(128, 128)
+    assert p.width == 128 and p.height == 128
+    assert p.lambda_ == 90.0 and p.delta_pos == 0.2 and p.delta_neg == 0.2
+    assert p.u_min == 1.0 and abs(p.u_max - math.e) < 1e-15
+    assert abs(p.tau * p.sigma * (8 + 4 * math.sqrt(2)) - 1.0) < 1e-12
+    assert p.time_unit_us == 1000.0 and p.iters == 50
+    assert rec.rec_check_params(p) == rec.REC_OK
+    assert rec.rec_workspace_bytes(p) >= 128 * 128 * 60
+
+
+@pytest.mark.parametrize("field,value", [
+    ("width", 0), ("height", -3), ("width", 70000), ("lambda_", 0.0), ("lambda_", float("nan")),
+    ("delta_pos", -0.1), ("u_min", 0.0), ("u_max", 0.5), ("tau", 0.6), ("sigma", 0.0),
+    ("time_unit_us", -1.0), ("time_unit_us", float("inf")), ("u_init", 0.0), ("iters", -1),
+    ("gap_every", -2), ("fuse_iters", 40), ("max_events", 0), ("tile_rows", 3),
+])
+def test_bad_params_rejected(field, value):
+    p = rec.rec_default_params(64, 48)
+    setattr(p, field, value)
+    if field == "tile_rows":
+        p.tile_waves = 4
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
+    assert rec.rec_workspace_bytes(p) == 0
+
+
+def test_step_size_bound():
+    """tau sigma ||L_g||^2 <= 1 with ||L_g||^2 <= 8 + 4 sqrt 2 (Section 3.2)."""
+    p = rec.rec_default_params(8, 8)
+    p.tau = 0.2
+    p.sigma = 1.0 / (0.2 * (8 + 4 * math.sqrt(2)))
+    assert rec.rec_check_params(p) == rec.REC_OK
+    p.sigma *= 1.001
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
+
+
+def _ev(t, x, y, p):
+    return (np.array(t, np.int64), np.array(x, np.uint16), np.array(y, np.uint16),
+            np.array(p, np.int8))
+
+
+def test_event_validation_codes():
+    t, x, y, p = _ev([5, 6, 6, 9], [0, 3, 2, 1], [0, 1, 2, 2], [1, -1, 1, -1])
+    assert rec.rec_check_events(t, x, y, p, 4, 3) == rec.REC_OK
+    assert rec.rec_check_events(t, x, y, p, 4, 3, t_prev=5) == rec.REC_OK
+    assert rec.rec_check_events(t, x, y, p, 4, 3, t_prev=6) == rec.REC_EORDER
+    assert rec.rec_check_events(t, x, y, p, 3, 3) == rec.REC_ERANGE
+    assert rec.rec_check_events(t, x, y, p, 4, 2) == rec.REC_ERANGE
+    bad = p.copy()
+    bad[2] = 0
+    assert rec.rec_check_events(t, x, y, bad, 4, 3) == rec.REC_EINVAL
+    tt = t.copy()
+    tt[2] = 4
+    assert rec.rec_check_events(tt, x, y, p, 4, 3) == rec.REC_EORDER
+    assert rec.rec_check_events(t[:0], x[:0], y[:0], p[:0], 4, 3) == rec.REC_OK
+
+
+def test_strerror_covers_codes():
+    for c in range(0, -8, -1):
+        assert rec.rec_strerror(c) != "unknown status code"
+    assert rec.rec_strerror(-99) == "unknown status code"
+
+
+def test_init_rejects_without_touching_device():
+    """Invalid parameters, a NULL or misaligned workspace and a short workspace
+    are refused before any device call."""
+    p = rec.rec_default_params(16, 16)
+    rc, h = rec.rec_init(p, None, 0, None)
+    assert rc == rec.REC_EINVAL and h is None
+    rc, h = rec.rec_init(p, 0x1001, 1 << 20, None)
+    assert rc == rec.REC_EINVAL
+    rc, h = rec.rec_init(p, 0x10000, 16, None)
+    assert rc == rec.REC_ENOMEM
+    p.lambda_ = -1.0
+    rc, h = rec.rec_init(p, 0x10000, 1 << 30, None)
+    assert rc == rec.REC_EINVAL
+
+
+def test_null_context_calls():
+    assert rec.rec_push_events(None, None, None, None, None, 1, 0) == rec.REC_EINVAL
+    assert rec.rec_solve(None, 5)[0] == rec.REC_EINVAL
+    assert rec.rec_sync(None) == rec.REC_EINVAL
+    assert rec.rec_destroy(None) == rec.REC_OK

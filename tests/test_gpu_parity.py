@@ -1,0 +1,275 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Bars: integer and timestamp work (scatter counts, latest timestamps) and the
+FP32 time planes are bit-exact; the image u matches the oracle within
+max-abs 1e-4 after every block of 50 iterations; the primal-dual gap within
+1e-3 relative; the fused temporally-blocked loop is bit-identical to the
+two-kernel loop.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import evgen
+import oracle
+from paper_1607_06283_amd import rec
+
+pytestmark = pytest.mark.gpu
+
+U_TOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    s, bs, nb, it = evgen.dvs128(seed=1, n_batches=20)
+    return s
+
+
+def oracle_params(prm: rec.rec_params) -> oracle.Params:
+    return oracle.Params(prm.width, prm.height, lam=prm.lambda_, delta_pos=prm.delta_pos,
+                         delta_neg=prm.delta_neg, u_min=prm.u_min, u_max=prm.u_max, tau=prm.tau,
+                         sigma=prm.sigma, time_unit_us=prm.time_unit_us, u_init=prm.u_init)
+
+
+def make(W, H, u0=None, **kw):
+    prm = rec.rec_default_params(W, H, **kw)
+    r = rec.Reconstructor(W, H, params=prm, u0=u0)
+    o = oracle.Oracle(oracle_params(prm), u0=u0)
+    return r, o
+
+
+def device_events(ev):
+    import torch
+    return (torch.from_numpy(np.ascontiguousarray(ev.t)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ev.x).view(np.int16)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ev.y).view(np.int16)).cuda(),
+            torch.from_numpy(np.ascontiguousarray(ev.p)).cuda())
+
+
+# --------------------------------------------------------------------------
+# Bit-exact steps
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("on_device", [False, True])
+def test_scatter_bit_exact(c1, on_device):
+    r, o = make(128, 128)
+    for b in evgen.batches(c1.events, 500)[:3]:
+        if on_device:
+            r.push(*device_events(b), on_device=True)
+        else:
+            r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+    assert np.array_equal(r.image(rec.REC_COUNT_POS), o.get(oracle.NPOS))
+    assert np.array_equal(r.image(rec.REC_COUNT_NEG), o.get(oracle.NNEG))
+    assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
+    st = r.solve(50, stats=True)
+    assert st.t_ref_us == o.t_ref and st.events_in_batch == 1500
+    assert not r.image(rec.REC_COUNT_POS).any()
+
+
+@pytest.mark.parametrize("ts", [1000.0, 100.0, 10000.0, 0.0])
+def test_time_planes_bit_exact(c1, ts):
+    r, o = make(128, 128, time_unit_us=ts)
+    for b in evgen.batches(c1.events, 500)[:4]:
+        r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(5)
+        o.solve(5)
+        assert np.array_equal(r.image(rec.REC_TX), o.get(oracle.TX32))
+        assert np.array_equal(r.image(rec.REC_TY), o.get(oracle.TY32))
+        assert np.array_equal(r.image(rec.REC_TIME), o.get(oracle.TAU32))
+
+
+def test_large_push_path_bit_exact(c1):
+    """Pushes above the single-workgroup size use the multi-kernel path."""
+    r, o = make(128, 128)
+    ev = c1.events
+    r.push(*device_events(ev), on_device=True)
+    o.push_events(ev)
+    assert np.array_equal(r.image(rec.REC_COUNT_POS), o.get(oracle.NPOS))
+    assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
+
+
+# --------------------------------------------------------------------------
+# Reconstruction parity
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fuse", [0, 8])
+def test_dvs128_stream_parity(c1, fuse):
+    """128x128, 20 blocks of 500 events, 50 iterations each, lambda 90:
+    max |u_gpu - u_oracle| <= 1e-4 after every block."""
+    r, o = make(128, 128, fuse_iters=fuse)
+    worst = 0.0
+    for b in evgen.batches(c1.events, 500)[:20]:
+        r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(50)
+        o.solve(50)
+        d = np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max()
+        worst = max(worst, d)
+        assert d <= U_TOL, d
+    print(f"fuse={fuse} worst max-abs {worst:.3e}")
+
+
+def test_gap_parity(c1):
+    r, o = make(128, 128, gap_every=10)
+    for b in evgen.batches(c1.events, 500)[:3]:
+        r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        st = r.solve(50, stats=True)
+        g_o, e_o = o.solve(50, gap_every=10)
+        g, e = r.gap_history()
+        assert len(g) == 5 and st.gap_samples == 5
+        assert np.allclose(g, g_o, rtol=1e-3, atol=0)
+        assert np.allclose(e, e_o, rtol=1e-6, atol=0)
+        assert (g >= 0).all() and (np.diff(g) <= 0).all()
+        assert st.gap == g[-1]
+
+
+# --------------------------------------------------------------------------
+# Fused loop == two-kernel loop
+# --------------------------------------------------------------------------
+
+SHAPES = [(128, 128), (240, 180), (67, 45), (1, 1), (1, 37), (29, 1), (200, 7), (5, 130)]
+
+
+def _random_stream(W, H, n, seed):
+    rng = np.random.default_rng(seed)
+    t = evgen.T0_US + np.sort(rng.integers(0, 200_000, n)).astype(np.int64)
+    x = rng.integers(0, W, n).astype(np.uint16)
+    y = rng.integers(0, H, n).astype(np.uint16)
+    p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    return t, x, y, p
+
+
+@pytest.mark.parametrize("W,H", SHAPES)
+def test_fused_equals_plain_bitwise(W, H):
+    t, x, y, p = _random_stream(W, H, 4 * max(1, W * H // 8), seed=W * 1000 + H)
+    n = len(t)
+    runs = []
+    cfgs = [dict(fuse_iters=0), dict(fuse_iters=8), dict(fuse_iters=5, tile_rows=4, tile_waves=4),
+            dict(fuse_iters=3, tile_rows=2, tile_waves=8), dict(fuse_iters=1, tile_rows=8, tile_waves=1),
+            dict(fuse_iters=15, tile_rows=8, tile_waves=4)]
+    for cfg in cfgs:
+        r = rec.Reconstructor(W, H, **cfg)
+        for a in range(0, n, n // 4):
+            r.push(t[a:a + n // 4], x[a:a + n // 4], y[a:a + n // 4], p[a:a + n // 4])
+            r.solve(23)
+        runs.append((r.image(rec.REC_U), r.image(rec.REC_STATE_P)))
+        r.close()
+    for (u, pp), cfg in zip(runs[1:], cfgs[1:]):
+        assert np.array_equal(u, runs[0][0]), cfg
+        assert np.array_equal(pp, runs[0][1]), cfg
+
+
+def test_repeat_run_deterministic(c1):
+    outs = []
+    for _ in range(2):
+        r = rec.Reconstructor(128, 128)
+        for b in evgen.batches(c1.events, 500)[:5]:
+            r.push(b.t, b.x, b.y, b.p)
+            r.solve(50)
+        outs.append(r.image(rec.REC_U))
+        r.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 37), (29, 1), (67, 45)])
+def test_small_and_ragged_parity(W, H):
+    t, x, y, p = _random_stream(W, H, 3 * W * H + 5, seed=W + 7 * H)
+    r, o = make(W, H)
+    n = len(t)
+    for a in range(0, n, max(1, n // 3)):
+        sl = slice(a, a + max(1, n // 3))
+        r.push(t[sl], x[sl], y[sl], p[sl])
+        o.push(t[sl], x[sl], y[sl], p[sl])
+        r.solve(50)
+        o.solve(50)
+        assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
+
+
+def test_empty_block_and_known_initial_image(c1):
+    spec = c1.spec
+    u0 = np.exp(evgen.ref0(spec)).astype(np.float32)
+    r = rec.Reconstructor(128, 128, u0=u0)
+    o = oracle.Oracle(oracle.Params(128, 128), u0=u0.astype(np.float64))
+    r.solve(50)
+    o.solve(50)
+    assert np.abs(r.image(rec.REC_U) - o.u).max() <= U_TOL
+    b = c1.events.slice(0, 500)
+    u_prev = r.image(rec.REC_U).astype(np.float64)
+    r.push(b.t, b.x, b.y, b.p)
+    o.push_events(b)
+    r.solve(50)
+    o.solve(50)
+    assert np.abs(r.image(rec.REC_U) - o.u).max() <= U_TOL
+    # f is the GPU's own previous image times exp(Delta+ n+ - Delta- n-),
+    # formed in FP64 and rounded once (eqn. intensity_update)
+    n_pos = np.zeros((128, 128))
+    n_neg = np.zeros((128, 128))
+    np.add.at(n_pos, (b.y.astype(int), b.x.astype(int)), (b.p > 0).astype(float))
+    np.add.at(n_neg, (b.y.astype(int), b.x.astype(int)), (b.p < 0).astype(float))
+    f_ref = u_prev * np.exp(0.2 * n_pos - 0.2 * n_neg)
+    assert np.allclose(r.image(rec.REC_F), f_ref, rtol=1.2e-7, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Error handling through the ABI
+# --------------------------------------------------------------------------
+
+def test_host_push_errors_are_immediate_and_atomic():
+    r = rec.Reconstructor(8, 5)
+    t = np.array([10, 11, 11, 15], np.int64)
+    x = np.array([0, 7, 3, 2], np.uint16)
+    y = np.array([0, 4, 1, 2], np.uint16)
+    p = np.array([1, -1, 1, 1], np.int8)
+    with pytest.raises(rec.RecError) as e:
+        r.push(t, x, y, np.array([1, 2, 1, 1], np.int8))
+    assert e.value.code == rec.REC_EINVAL
+    with pytest.raises(rec.RecError) as e:
+        r.push(t, np.array([0, 8, 3, 2], np.uint16), y, p)
+    assert e.value.code == rec.REC_ERANGE
+    r.push(t, x, y, p)
+    with pytest.raises(rec.RecError) as e:
+        r.push(t[:1], x[:1], y[:1], p[:1])
+    assert e.value.code == rec.REC_EORDER
+    assert r.image(rec.REC_COUNT_POS).sum() == 3 and r.image(rec.REC_COUNT_NEG).sum() == 1
+
+
+def test_device_push_errors_are_deferred_and_atomic():
+    import torch
+    r = rec.Reconstructor(8, 5)
+    t = torch.tensor([10, 11, 11, 15], dtype=torch.int64, device="cuda")
+    x = torch.tensor([0, 7, 3, 2], dtype=torch.int16, device="cuda")
+    y = torch.tensor([0, 4, 1, 2], dtype=torch.int16, device="cuda")
+    p = torch.tensor([1, -1, 1, 1], dtype=torch.int8, device="cuda")
+    r.push(t, x, torch.tensor([0, 4, 9, 2], dtype=torch.int16, device="cuda"), p, on_device=True)
+    with pytest.raises(rec.RecError) as e:
+        r.sync()
+    assert e.value.code == rec.REC_ERANGE
+    r.sync()  # reported once
+    r.push(t, x, y, torch.tensor([1, -1, 0, 1], dtype=torch.int8, device="cuda"), on_device=True)
+    with pytest.raises(rec.RecError) as e:
+        r.sync()
+    assert e.value.code == rec.REC_EINVAL
+    assert not r.image(rec.REC_COUNT_POS).any()
+    r.push(t, x, y, p, on_device=True)
+    r.push(t[:2], x[:2], y[:2], p[:2], on_device=True)  # goes back in time
+    with pytest.raises(rec.RecError) as e:
+        r.sync()
+    assert e.value.code == rec.REC_EORDER
+    assert r.image(rec.REC_COUNT_POS).sum() == 3
+    # a later host push learns the device time and checks against it
+    with pytest.raises(rec.RecError) as e:
+        r.push(np.array([12], np.int64), np.array([1], np.uint16), np.array([1], np.uint16),
+               np.array([1], np.int8))
+    assert e.value.code == rec.REC_EORDER
