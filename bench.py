@@ -36,6 +36,17 @@ W_, H_ = 240, 180
 EVENTS_PER_BATCH = 1000
 ITERS = 50
 
+# Other shapes for kernel measurements (same JSON line format; the default
+# workload above is the one the headline figure is quoted on):
+#   hd720  1280x720 sensor, ~2e7 events/s, blocks of 20000 events, 100 iterations
+#   probe  5120x5760 frame (29.5 Mpx, ~1.8 GB of state: beyond the 256 MB
+#          Infinity Cache), uniform random events, blocks of 20000, 50 iterations
+WORKLOADS = {
+    "davis240": (240, 180, 1000, 50),
+    "hd720": (1280, 720, 20000, 100),
+    "probe": (5120, 5760, 20000, 50),
+}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -60,7 +71,38 @@ def load_stream(n_batches: int):
     return ev
 
 
-def run_gpu(ev, steps, warmup, fuse, profile):
+def random_stream(W, H, n, seed=7):
+    """Uniform random events (pixel, polarity), timestamps 1 us apart."""
+    import evgen
+
+    rng = np.random.default_rng(seed)
+    t = evgen.T0_US + np.arange(n, dtype=np.int64)
+    x = rng.integers(0, W, n).astype(np.uint16)
+    y = rng.integers(0, H, n).astype(np.uint16)
+    p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+    return evgen.Events(t, x, y, p, np.zeros(n, np.uint8))
+
+
+def hd720_stream(n_batches):
+    import evgen
+
+    key = f"hd720-seed3-{n_batches}"
+    path = os.path.join(os.environ.get("TMPDIR", "/tmp"), f"evrec_stream_{key}.npz")
+    if os.path.exists(path):
+        z = np.load(path)
+        return evgen.Events(z["t"], z["x"], z["y"], z["p"], z["n"])
+    dur = max(500_000, int(n_batches * 20000 / 2e7 * 1e6 * 1.05))
+    s, _, _, _ = evgen.hd720(seed=3, duration_us=dur)
+    ev = s.events
+    try:
+        np.savez(path, t=ev.t, x=ev.x, y=ev.y, p=ev.p, n=ev.is_noise)
+    except OSError:
+        pass
+    return ev
+
+
+def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_BATCH,
+            iters=ITERS, rows=0, waves=0):
     import torch
     from paper_1607_06283_amd import rec
 
@@ -69,8 +111,8 @@ def run_gpu(ev, steps, warmup, fuse, profile):
     x = torch.from_numpy(ev.x.view(np.int16)).to(dev)
     y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
     p = torch.from_numpy(ev.p).to(dev)
-    r = rec.Reconstructor(W_, H_, fuse_iters=fuse)
-    B = EVENTS_PER_BATCH
+    r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves)
+    B = batch
 
     def step(i):
         a = i * B
@@ -78,7 +120,7 @@ def run_gpu(ev, steps, warmup, fuse, profile):
                                  y.data_ptr() + 2 * a, p.data_ptr() + a, B, 1)
         if rc:
             raise rec.RecError(rc, "rec_push_events")
-        rc, _ = rec.rec_solve(r.ctx, ITERS, False)
+        rc, _ = rec.rec_solve(r.ctx, iters, False)
         if rc:
             raise rec.RecError(rc, "rec_solve")
 
@@ -121,14 +163,50 @@ def cpu_baseline(ev, budget_s=10.0):
             "events_per_s": round(n * EVENTS_PER_BATCH / el, 1)}
 
 
+def copy_probe(mib=256, reps=5):
+    """Plain copy of a known size: each launch reads and writes `mib` MiB, so
+    the profiler's FETCH_SIZE / WRITE_SIZE per dispatch can be scaled to bytes."""
+    import torch
+
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                      "reps": reps, "GBps_read_plus_write": round(2 * n * 4 / dt / 1e9, 1)}),
+          flush=True)
+
+
+WORKLOAD_TEXT = {
+    "davis240": "240x180 sensor, rotating+translating texture, ~1e6 signal events/s + 1% noise, "
+                "blocks of 1000 events, 50 FP32 primal-dual iterations per block, lambda 90, "
+                "threshold 0.2",
+    "hd720": "1280x720 sensor, rotating+translating texture, ~2e7 events/s, blocks of 20000 "
+             "events, 100 FP32 primal-dual iterations per block, lambda 90, threshold 0.2",
+    "probe": "5120x5760 frame (29.5 Mpx), uniform random events, blocks of 20000 events, 50 FP32 "
+             "primal-dual iterations per block, lambda 90",
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1980)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--fuse", type=int, default=8, help="iterations per fused launch (0: unfused)")
+    ap.add_argument("--fuse", type=int, default=-1,
+                    help="iterations per fused launch (-1: chosen by the library, 0: unfused)")
+    ap.add_argument("--rows", type=int, default=0, help="rows per lane of the fused tile (0: auto)")
+    ap.add_argument("--waves", type=int, default=0, help="wavefronts per fused workgroup (0: auto)")
+    ap.add_argument("--workload", default="davis240", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the reconstruction of one event stream runs on "
@@ -141,32 +219,41 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe()
+        return
     need = args.warmup + args.steps
-    log(f"bench: generating 240x180 stream for {need} blocks")
-    ev = load_stream(need)
-    if len(ev) < need * EVENTS_PER_BATCH:
+    W, H, B, IT = WORKLOADS[args.workload]
+    log(f"bench: generating {args.workload} stream for {need} blocks")
+    if args.workload == "davis240":
+        ev = load_stream(need)
+    elif args.workload == "hd720":
+        ev = hd720_stream(need)
+    else:
+        ev = random_stream(W, H, need * B)
+    if len(ev) < need * B:
         raise SystemExit("stream too short")
+    kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves)
     log("bench: timed pass")
-    dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False)
-    px_iters = args.steps * ITERS * W_ * H_
+    dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False, **kw)
+    px_iters = args.steps * IT * W * H
     value = px_iters / dt / 1e6
-    ev_rate = args.steps * EVENTS_PER_BATCH / dt
+    ev_rate = args.steps * B / dt
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "240x180 sensor, rotating+translating texture, ~1e6 signal "
-                               "events/s + 1% noise, blocks of 1000 events, 50 FP32 primal-dual "
-                               "iterations per block, lambda 90, threshold 0.2",
-                   "width": W_, "height": H_, "events_per_batch": EVENTS_PER_BATCH,
-                   "iters_per_batch": ITERS, "fuse_iters": args.fuse},
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "width": W, "height": H, "events_per_batch": B,
+                   "iters_per_batch": IT, "fuse_iters": args.fuse,
+                   "tile_rows": args.rows, "tile_waves": args.waves},
         "events_per_s": round(ev_rate, 1),
         "realtime_factor": round(ev_rate / 1e6, 3),
     }
     if not args.no_profile:
         log("bench: per-kernel timing pass")
-        _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True)
+        _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True, **kw)
         pd_ms = prof.ms[2]
         pd_launches = int(prof.launches[2])
         achieved = BYTES_PER_PX_ITER * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
@@ -180,7 +267,7 @@ def main():
         }
         out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),
                             "pd": round(pd_ms, 3)}
-    if not args.no_cpu:
+    if not args.no_cpu and args.workload == "davis240":
         log("bench: oracle baseline")
         out["cpu_baseline"] = cpu_baseline(ev)
     print(json.dumps(out), flush=True)

@@ -31,16 +31,21 @@
  *     keeps it alive until rec_destroy; the library never allocates device
  *     memory.  It allocates the host-side context and a pinned host staging
  *     buffer for host-pointer pushes, both released by rec_destroy.
- *   - Event arrays and output buffers belong to the caller; they only need
- *     to stay valid for the duration of the call (device-pointer pushes:
- *     until the stream has executed the push, i.e. until the next
- *     synchronising call or a stream synchronisation by the caller).
+ *   - Event arrays and output buffers belong to the caller; host arrays only
+ *     need to stay valid for the duration of the call; device arrays until
+ *     the push has executed, which is guaranteed once the next rec_solve has
+ *     completed on the caller's stream or a synchronising call returned.
  *
  * Streams and synchronisation
- *   - All device work is enqueued on the hipStream_t given to rec_init
- *     (NULL = the default stream).  rec_push_events (device pointers) and
- *     rec_solve without stats do not synchronise.  rec_solve with stats,
- *     rec_get_image, rec_gap_history, rec_profile_read and rec_sync do.
+ *   - Builds, iterations, gap evaluations and readbacks are enqueued on the
+ *     hipStream_t given to rec_init (NULL = the default stream).  Pushes run
+ *     on an internal stream of the context, ordered by events after the
+ *     previous block's build and before the next one, so a push overlaps the
+ *     previous block's iterations.  Work the caller enqueues on its stream
+ *     after rec_solve returns is ordered after that solve.
+ *   - rec_push_events (device pointers) and rec_solve without stats do not
+ *     synchronise.  rec_solve with stats, rec_get_image, rec_gap_history,
+ *     rec_profile_read, rec_sync and rec_destroy do (both streams).
  *   - Errors found on the device (device-pointer pushes) are reported by the
  *     next synchronising call; the rejected push changes no state.
  *
@@ -100,12 +105,14 @@ typedef struct {
                                 default sqrt(u_min * u_max) */
     int32_t iters;           /* iterations per rec_solve when called with 0; default 50 */
     int32_t gap_every;       /* gap / energy every this many iterations; 0 = never */
-    int32_t fuse_iters;      /* iterations per fused launch; 0 = unfused two-kernel loop;
-                                default 8 */
+    int32_t fuse_iters;      /* iterations per fused launch: -1 = chosen from the frame
+                                size (default), 0 = unfused two-kernel loop, k >= 1 = at
+                                most k (also capped by the tile height) */
     int32_t max_events;      /* largest host-pointer push handled in one piece (larger
                                 pushes are split); sizes the device staging; default 65536 */
-    int32_t tile_rows;       /* rows per lane in the fused kernel (1..16); 0 = automatic */
-    int32_t tile_waves;      /* wavefronts per fused workgroup (1..16); 0 = automatic */
+    int32_t tile_rows;       /* rows per lane in the fused kernel (2, 4, 8, 16); 0 = automatic */
+    int32_t tile_waves;      /* wavefronts per fused workgroup (1..16); 0 = automatic;
+                                set both or neither */
     int32_t reserved[6];     /* must be 0 */
 } rec_params;
 

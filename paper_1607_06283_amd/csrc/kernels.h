@@ -21,10 +21,18 @@ struct alignas(256) DevState {
     int64_t t_ref;          // timestamp of the last accepted event
     int64_t t_first;        // first accepted timestamp of the stream
     int64_t first_bad;      // index of the first invalid event of the running push
-    int64_t batch_events;   // events accepted since the last solve
+    int64_t batch_events;   // events accepted since the last solve (scattered pushes)
     int64_t last_events;    // events consumed by the last solve
     int32_t started;        // 1 once an event was accepted
     int32_t err;            // first deferred push error not yet reported (0 = none)
+    // Outcome of the events folded into a solve's first launch; written by
+    // that launch's block 0 and committed to the fields above by the next
+    // launch (no block of the first launch may see the update).
+    int64_t pend_t_ref;
+    int64_t pend_t_first;
+    int64_t pend_events;
+    int32_t pend_accepted;  // 1 if at least one folded event was accepted
+    int32_t pend_err;
 };
 
 // Device pointers carved from the caller's workspace.
@@ -36,7 +44,7 @@ struct Planes {
     float* tx;              // forward differences of the time surface
     float* ty;
     int64_t* t_last;        // latest timestamp per pixel (kNever if none)
-    int32_t* npos;          // pending event counts
+    int32_t* npos;          // event counts of scattered pushes
     int32_t* nneg;
     int64_t* ev_t;          // staging for host-pointer pushes
     uint16_t* ev_x;
@@ -55,24 +63,61 @@ struct IterConsts {
     float tau, sigma, taulam, umin, umax;
 };
 
+// Constants of the data image and time-surface build (FP64).
+struct BuildConsts {
+    double dpos, dneg;  // contrast thresholds Delta+, Delta-
+    double ts;          // microseconds per unit of tau (0: flat manifold)
+};
+
+// Device-pointer pushes not scattered yet: consumed by the first fused
+// launch of the next solve, in order, each all-or-nothing.
+constexpr int kMaxSegs = 4;
+struct EventSegs {
+    const int64_t* t[kMaxSegs];
+    const uint16_t* x[kMaxSegs];
+    const uint16_t* y[kMaxSegs];
+    const int8_t* p[kMaxSegs];
+    int64_t n[kMaxSegs];
+    int32_t count;
+};
+
+// Modes of the fused primal-dual launch (bit set).
+constexpr int kBuild = 1;   // form f, tx, ty (and the new t_last) first
+constexpr int kZero = 2;    // reset the scattered event counts of the interior at the end
+constexpr int kEvents = 4;  // with kBuild: validate and bin the folded events in LDS
+constexpr int kCommit = 8;  // commit the pending stream state of the previous launch
+constexpr int kCounts = 16; // with kBuild: add the scattered event counts
+
 constexpr int kGapBlock = 256;
 constexpr int kGapHistCap = 4096;
-constexpr int kSmallPush = 32768;  // pushes up to this size use one workgroup
+constexpr int kSmallPush = 4096;   // pushes up to this size use one workgroup
+
+// Optional timing events around a launch (recorded by the launch packet).
+struct LaunchEv {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
 
 size_t gap_blocks(size_t np);
+size_t fused_lds_bytes(int rows, int waves, int mode);
+int fused_tiles(Frame fr, int rows, int waves, int iters);
 
 // Launchers: return the first HIP error (launch errors only; no sync).
 hipError_t launch_init(const Planes& P, Frame fr, float u_init, bool keep_u, hipStream_t s);
 hipError_t launch_push(const Planes& P, Frame fr, const int64_t* t, const uint16_t* x,
-                       const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s);
-hipError_t launch_build(const Planes& P, Frame fr, int cur, double dpos, double dneg,
-                        double time_unit_us, hipStream_t s);
-hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts k, int cur, hipStream_t s);
-hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts k, int cur, int iters,
-                           int rows, int waves, hipStream_t s);
+                       const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s,
+                       LaunchEv ev = {});
+hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, hipStream_t s,
+                        LaunchEv ev = {});
+hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
+                         LaunchEv ev = {});
+hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts k, int cur, hipStream_t s,
+                           LaunchEv ev = {});
+hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts k, BuildConsts bc,
+                           const EventSegs& segs, int cur, int iters, int mode, int rows,
+                           int waves, hipStream_t s, LaunchEv ev = {});
 bool fused_shape_supported(int rows, int waves);
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, hipStream_t s);
+                      int cur, int slot, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
                              hipStream_t s);
 hipError_t launch_metric_plane(const Planes& P, Frame fr, float* out, hipStream_t s);

@@ -4,10 +4,15 @@
 //   k_push_small    validate + scatter one push in a single workgroup
 //   k_validate / k_scatter / k_push_finalize   the same for large pushes
 //   k_build         data image f, time differences tx/ty, reset counts
+//   k_finish        commit folded-event state / reset counts after a one-launch solve
 //   k_primal, k_dual    one primal-dual iteration as two plain kernels
-//   k_pd_fused      several iterations per HBM round trip on a register tile
+//   k_pd_fused      several iterations per HBM round trip on a register tile;
+//                   its first launch of a solve can also bin the block's events
+//                   and build f, tx, ty
 //   k_gap, k_gap_final  primal-dual gap and energy (FP64 accumulation)
 //   k_time_plane, k_metric_plane   readback helpers
+#include <hip/hip_ext.h>
+
 #include "kernels.h"
 #include "pd_math.h"
 
@@ -36,6 +41,19 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
     return xcd * q + min(xcd, rem) + idx;
 }
 
+// Launch with optional timing events carried by the dispatch itself.
+template <typename Kern, typename... Args>
+hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t a,
+                  hipEvent_t z, Args... args) {
+    if (a || z)
+        hipExtLaunchKernelGGL(kernel, grid, block, lds, s, a, z, 0, args...);
+    else
+        hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
+
+inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
+
 // ---------------------------------------------------------------- init
 
 __global__ void k_init(Planes P, size_t np, float u_init, int keep_u) {
@@ -49,6 +67,11 @@ __global__ void k_init(Planes P, size_t np, float u_init, int keep_u) {
         st->last_events = 0;
         st->started = 0;
         st->err = 0;
+        st->pend_t_ref = 0;
+        st->pend_t_first = 0;
+        st->pend_events = 0;
+        st->pend_accepted = 0;
+        st->pend_err = 0;
     }
     if (k >= np) return;
     float u = keep_u ? P.u[0][k] : u_init;
@@ -149,10 +172,33 @@ __global__ void k_push_finalize(Planes P, Frame fr, const int64_t* t, const uint
 
 // ---------------------------------------------------------------- build
 
-// f = u_prev * exp(Delta+ n+ - Delta- n-), formed in FP64 and rounded once;
-// tx = (t_last(x) - t_last(x+1)) / T_s = tau(x+1) - tau(x) from the exact
-// int64 difference (0 on the last column), likewise ty; counts reset.
-__global__ void k_build(Planes P, Frame fr, int cur, double dpos, double dneg, double ts) {
+// Data image of one pixel: f = u_prev * exp(Delta+ n+ - Delta- n-)
+// (eqn. intensity_update for every event of the block), formed in FP64 and
+// rounded once.
+__device__ __forceinline__ float data_image(float u_prev, int32_t npos, int32_t nneg,
+                                            const BuildConsts& b) {
+    const double e = b.dpos * (double)npos - b.dneg * (double)nneg;
+    return (float)((double)u_prev * exp(e));
+}
+
+// Forward differences of the time surface from the latest timestamps of a
+// pixel (tl), its right (tr) and lower (td) neighbours:
+// tau(x+1) - tau(x) = (t_last(x) - t_last(x+1)) / T_s from the exact int64
+// difference, divided in FP64 and rounded once; 0 on the last column / row
+// and everywhere when T_s = 0 (flat manifold).
+__device__ __forceinline__ void time_diffs(int64_t tl, int64_t tr, int64_t td, bool has_r,
+                                           bool has_d, int64_t t0, const BuildConsts& b,
+                                           float& dx, float& dy) {
+    dx = 0.0f;
+    dy = 0.0f;
+    if (b.ts > 0.0) {
+        const int64_t l = resolved_last(tl, t0);
+        if (has_r) dx = (float)((double)(l - resolved_last(tr, t0)) / b.ts);
+        if (has_d) dy = (float)((double)(l - resolved_last(td, t0)) / b.ts);
+    }
+}
+
+__global__ void k_build(Planes P, Frame fr, int cur, BuildConsts bc) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     DevState* st = P.st;
@@ -162,20 +208,41 @@ __global__ void k_build(Planes P, Frame fr, int cur, double dpos, double dneg, d
     }
     if (k >= np) return;
     const int32_t j = (int32_t)(k % fr.W), i = (int32_t)(k / fr.W);
-    const int32_t a = P.npos[k], b = P.nneg[k];
-    const double e = dpos * (double)a - dneg * (double)b;
-    P.f[k] = (float)((double)P.u[cur][k] * exp(e));
+    P.f[k] = data_image(P.u[cur][k], P.npos[k], P.nneg[k], bc);
     P.npos[k] = 0;
     P.nneg[k] = 0;
-    float dx = 0.0f, dy = 0.0f;
-    if (ts > 0.0) {
-        const int64_t t0 = st->t_first;
-        const int64_t tl = resolved_last(P.t_last[k], t0);
-        if (j < fr.W - 1) dx = (float)((double)(tl - resolved_last(P.t_last[k + 1], t0)) / ts);
-        if (i < fr.H - 1) dy = (float)((double)(tl - resolved_last(P.t_last[k + fr.W], t0)) / ts);
-    }
+    const bool hr = j < fr.W - 1, hd = i < fr.H - 1;
+    float dx, dy;
+    time_diffs(P.t_last[k], hr ? P.t_last[k + 1] : kNever, hd ? P.t_last[k + fr.W] : kNever, hr,
+               hd, st->t_first, bc, dx, dy);
     P.tx[k] = dx;
     P.ty[k] = dy;
+}
+
+// Commits the stream state left pending by a solve's first fused launch.
+__device__ __forceinline__ void commit_pending(DevState* st) {
+    if (st->pend_accepted) {
+        if (!st->started) {
+            st->started = 1;
+            st->t_first = st->pend_t_first;
+        }
+        st->t_ref = st->pend_t_ref;
+    }
+    if (st->pend_err && st->err == 0) st->err = st->pend_err;
+    st->last_events = st->pend_events;
+    st->batch_events = 0;
+    st->pend_accepted = 0;
+    st->pend_err = 0;
+}
+
+// After a solve that had a single fused launch: commit and reset counts.
+__global__ void k_finish(Planes P, size_t np, int zero_counts) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) commit_pending(P.st);
+    if (zero_counts && k < np) {
+        P.npos[k] = 0;
+        P.nneg[k] = 0;
+    }
 }
 
 __global__ void k_time_plane(Planes P, Frame fr, double ts, float* out) {
@@ -198,7 +265,7 @@ __global__ void k_metric_plane(Planes P, Frame fr, float* out) {
 // ---------------------------------------------------------------- plain loop
 
 // Primal half-step for every pixel: needs q = M^T p here, at the left and
-// at the upper neighbour.
+// at the upper neighbour (0 where the neighbour is outside the image).
 __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts kc, int cur) {
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
     const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -206,22 +273,21 @@ __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts k
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)i * fr.W + j;
     const float* p = P.p[cur];
-    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam);
+    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, j < fr.W - 1, i < fr.H - 1);
     const float qx = q_x(c, p[k], p[np + k], p[2 * np + k]);
     const float qy = q_y(c, p[k], p[np + k], p[2 * np + k]);
     float qxl = 0.0f, qyu = 0.0f;
     if (j > 0) {
         const size_t kl = k - 1;
-        const Coef cl = make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam);
+        const Coef cl = make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam, true, i < fr.H - 1);
         qxl = q_x(cl, p[kl], p[np + kl], p[2 * np + kl]);
     }
     if (i > 0) {
         const size_t ku = k - fr.W;
-        const Coef cu = make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam);
+        const Coef cu = make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam, j < fr.W - 1, true);
         qyu = q_y(cu, p[ku], p[np + ku], p[2 * np + ku]);
     }
-    P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, j < fr.W - 1, j > 0, i < fr.H - 1,
-                             i > 0, c, kc.tau, kc.umin, kc.umax);
+    P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, c, kc.tau, kc.umin, kc.umax);
 }
 
 // Dual half-step: needs the extrapolated primal here, right and below.
@@ -237,7 +303,7 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
     float gx = 0.0f, gy = 0.0f;
     if (j < fr.W - 1) gx = extrapolate(un[k + 1], uo[k + 1]) - ut;
     if (i < fr.H - 1) gy = extrapolate(un[k + fr.W], uo[k + fr.W]) - ut;
-    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam);
+    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, j < fr.W - 1, i < fr.H - 1);
     const float* p = P.p[cur];
     float p1 = p[k], p2 = p[np + k], p3 = p[2 * np + k];
     dual(p1, p2, p3, gx, gy, c, kc.sigma);
@@ -249,59 +315,215 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
 
 // ---------------------------------------------------------------- fused loop
 
+// Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1);
+// the lane without a source receives 0.
 __device__ __forceinline__ float lane_from_left(float v) {   // value of lane - 1
-    return __shfl_up(v, 1, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 1
-    return __shfl_down(v, 1, 64);
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// Folded events of the first launch, binned for one tile region (LDS).
+struct TileBins {
+    int32_t* pos;     // RH x 64 counts
+    int32_t* neg;
+    long long* tmax;  // (RH + 1) x 65 latest timestamps (one extra column and row)
+    int64_t t_first;  // stream's first timestamp after this block's events
+};
+
+// Validates the folded pushes in order (each all-or-nothing, with the same
+// error codes as a scattered push) and bins the accepted events that fall
+// into the tile region [rx0, rx0 + 64] x [ry0, ry0 + RH].  Every workgroup
+// takes the same decisions; block 0 records the outcome as pending state.
+__device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int RH, int rx0,
+                           int ry0, unsigned char* lds, TileBins& tb) {
+    __shared__ unsigned long long seg_bad[kMaxSegs];
+    __shared__ int seg_ok[kMaxSegs];
+    __shared__ long long s_first;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    tb.pos = (int32_t*)lds;
+    tb.neg = tb.pos + RH * 64;
+    tb.tmax = (long long*)(tb.neg + RH * 64);
+    for (int q = tid; q < RH * 64; q += nt) {
+        tb.pos[q] = 0;
+        tb.neg[q] = 0;
+    }
+    for (int q = tid; q < (RH + 1) * 65; q += nt) tb.tmax[q] = kNever;
+    if (tid < kMaxSegs) seg_bad[tid] = (unsigned long long)kNoBad;
+    __syncthreads();
+    // per-event checks; each push's first event is checked against the
+    // running reference time in sequence below
+    for (int s = 0; s < segs.count; ++s) {
+        const int64_t* t = segs.t[s];
+        for (int64_t i = tid; i < segs.n[s]; i += nt) {
+            const int64_t prev = i ? t[i - 1] : INT64_MIN;
+            if (event_error(t[i], prev, segs.x[s][i], segs.y[s][i], segs.p[s][i], fr.W, fr.H))
+                atomicMin(&seg_bad[s], (unsigned long long)i);
+        }
+    }
+    __syncthreads();
+    DevState* st = P.st;
+    if (tid == 0) {
+        int64_t ref = st->started ? st->t_ref : INT64_MIN;
+        int64_t first = kNever, last = 0, accepted = 0;
+        int32_t err = 0;
+        for (int s = 0; s < segs.count; ++s) {
+            const int64_t fb = (int64_t)seg_bad[s];
+            const int64_t* t = segs.t[s];
+            int32_t code = 0;
+            if (fb == 0)
+                code = event_error(t[0], INT64_MIN, segs.x[s][0], segs.y[s][0], segs.p[s][0],
+                                   fr.W, fr.H);
+            else if (t[0] < ref)
+                code = kErrOrder;
+            else if (fb != kNoBad)
+                code = event_error(t[fb], t[fb - 1], segs.x[s][fb], segs.y[s][fb], segs.p[s][fb],
+                                   fr.W, fr.H);
+            seg_ok[s] = code == 0;
+            if (code == 0) {
+                if (first == kNever) first = t[0];
+                ref = t[segs.n[s] - 1];
+                last = ref;
+                accepted += segs.n[s];
+            } else if (err == 0) {
+                err = code;
+            }
+        }
+        s_first = st->started ? st->t_first : (first == kNever ? 0 : first);
+        if (blockIdx.x == 0) {
+            st->pend_t_ref = last;
+            st->pend_t_first = first;
+            st->pend_accepted = accepted > 0;
+            st->pend_events = st->batch_events + accepted;
+            st->pend_err = err;
+        }
+    }
+    __syncthreads();
+    for (int s = 0; s < segs.count; ++s) {
+        if (!seg_ok[s]) continue;
+        for (int64_t i = tid; i < segs.n[s]; i += nt) {
+            const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
+            if (lc < 0 || lc > 64 || lr < 0 || lr > RH) continue;
+            atomicMax(&tb.tmax[lr * 65 + lc], (long long)segs.t[s][i]);
+            if (lc < 64 && lr < RH)
+                atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * 64 + lc] : &tb.neg[lr * 64 + lc], 1);
+        }
+    }
+    __syncthreads();
+    tb.t_first = s_first;
 }
 
 // K primal-dual iterations per launch on a register tile.  A workgroup of
 // NW wavefronts covers a 64-column x (NW*R)-row region: lane = column, each
 // lane holds R consecutive rows in registers, wavefront w holds rows
-// [w*R, w*R + R).  Horizontal neighbours come from adjacent lanes, vertical
-// ones from the lane's own registers or, across wavefronts, through LDS.
-// Each iteration widens the dependency cone by one pixel, so after K
-// iterations the region minus a K-pixel border is exact; only that interior
-// is written.  Reads (u, p) from buffer `cur`, writes buffer `cur ^ 1`.
+// [w*R, w*R + R).  Horizontal neighbours come from adjacent lanes (DPP),
+// vertical ones from the lane's own registers or, across wavefronts,
+// through LDS.  Each iteration widens the dependency cone by one pixel, so
+// after K iterations the region minus a K-pixel border is exact; only that
+// interior is written.  Reads (u, p) from buffer `cur`, writes `cur ^ 1`.
+//
+// mode & kBuild (the solve's first launch): instead of loading f, tx, ty, the
+//   tile forms them from u (still u_prev), the event counts and the latest
+//   timestamps with the arithmetic of k_build, and writes f, tx, ty and the
+//   new latest timestamps for its interior.  With kEvents the block's
+//   not-yet-scattered pushes are validated and binned in LDS first
+//   (dynamic LDS); with kCounts the scattered counts are added.
+// mode & kZero: resets the scattered counts of the interior at the end.
+// mode & kCommit: block 0 commits the pending stream state.
 template <int R, int NW>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
-                                                      int cur, int K, int tiles_x, int ntiles) {
+                                                      BuildConsts bc, EventSegs segs, int cur,
+                                                      int K, int mode, int tiles_x, int ntiles) {
+    extern __shared__ unsigned char dyn_lds[];
+    constexpr int RH = NW * R;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    const int OW = 64 - 2 * K, OH = NW * R - 2 * K;
-    const int gx = txi * OW - K + lane;
-    const int gy0 = tyi * OH - K + wave * R;
+    const int OW = 64 - 2 * K, OH = RH - 2 * K;
+    const int rx0 = txi * OW - K, ry0 = tyi * OH - K;
+    const int gx = rx0 + lane;
+    const int gy0 = ry0 + wave * R;
     const size_t np = (size_t)fr.W * fr.H;
     const float* __restrict__ uin = P.u[cur];
     const float* __restrict__ pin = P.p[cur];
 
+    if ((mode & kCommit) && blockIdx.x == 0 && threadIdx.x == 0) commit_pending(P.st);
+
+    const bool build = (mode & kBuild) != 0;
+    TileBins tb;
+    tb.pos = tb.neg = nullptr;
+    tb.tmax = nullptr;
+    tb.t_first = 0;
+    if (build) {
+        if (mode & kEvents) {
+            bin_events(P, fr, segs, RH, rx0, ry0, dyn_lds, tb);
+        } else {
+            tb.t_first = P.st->t_first;
+            if (blockIdx.x == 0 && threadIdx.x == 0) {
+                DevState* st = P.st;
+                st->pend_accepted = 0;
+                st->pend_err = 0;
+                st->pend_events = st->batch_events;
+            }
+        }
+    }
+
     float u[R], p1[R], p2[R], p3[R];
     Coef c[R];
     const bool col_in = gx >= 0 && gx < fr.W;
+    const bool col_out = col_in && lane >= K && lane < 64 - K;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
+        const bool in = col_in && gy >= 0 && gy < fr.H;
         float uu = 1.0f, a = 0.0f, b = 0.0f, d = 0.0f, f = 1.0f, tx = 0.0f, ty = 0.0f;
-        if (col_in && gy >= 0 && gy < fr.H) {
+        if (in) {
             const size_t k = (size_t)gy * fr.W + gx;
             uu = uin[k];
             a = pin[k];
             b = pin[np + k];
             d = pin[2 * np + k];
-            f = P.f[k];
-            tx = P.tx[k];
-            ty = P.ty[k];
+            if (build) {
+                const int lr = wave * R + r;
+                const bool hr = gx < fr.W - 1, hd = gy < fr.H - 1;
+                int32_t npos = 0, nneg = 0;
+                int64_t tl = P.t_last[k];
+                int64_t tr = hr ? P.t_last[k + 1] : kNever;
+                int64_t td = hd ? P.t_last[k + fr.W] : kNever;
+                if (mode & kCounts) {
+                    npos = P.npos[k];
+                    nneg = P.nneg[k];
+                }
+                if (mode & kEvents) {
+                    npos += tb.pos[lr * 64 + lane];
+                    nneg += tb.neg[lr * 64 + lane];
+                    tl = max(tl, (int64_t)tb.tmax[lr * 65 + lane]);
+                    tr = max(tr, (int64_t)tb.tmax[lr * 65 + lane + 1]);
+                    td = max(td, (int64_t)tb.tmax[(lr + 1) * 65 + lane]);
+                }
+                f = data_image(uu, npos, nneg, bc);
+                time_diffs(tl, tr, td, hr, hd, tb.t_first, bc, tx, ty);
+                if (col_out && lr >= K && lr < RH - K) {
+                    P.f[k] = f;
+                    P.tx[k] = tx;
+                    P.ty[k] = ty;
+                    if (mode & kEvents) P.t_last[k] = tl;
+                }
+            } else {
+                f = P.f[k];
+                tx = P.tx[k];
+                ty = P.ty[k];
+            }
         }
         u[r] = uu;
         p1[r] = a;
         p2[r] = b;
         p3[r] = d;
-        c[r] = make_coef(tx, ty, f, kc.taulam);
+        // pixels outside the image get all-zero M, so their q is 0
+        c[r] = make_coef(tx, ty, f, kc.taulam, in && gx < fr.W - 1, in && gy < fr.H - 1);
     }
-    const bool has_r = gx < fr.W - 1, has_l = gx > 0;
 
     __shared__ float xq[NW > 1 ? NW : 1][64];
     __shared__ float xu[NW > 1 ? NW : 1][64];
@@ -322,11 +544,9 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
         float un[R], ut[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int gy = gy0 + r;
             const float qxl = lane_from_left(qx[r]);
             const float qyu = r > 0 ? qy[r - 1] : qy_top;
-            un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, has_r, has_l, gy < fr.H - 1, gy > 0,
-                           c[r], kc.tau, kc.umin, kc.umax);
+            un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], kc.tau, kc.umin, kc.umax);
             ut[r] = extrapolate(un[r], u[r]);
         }
         float ut_bot = 0.0f;
@@ -337,29 +557,29 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int gy = gy0 + r;
             const float utr = lane_from_right(ut[r]);
             const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
-            const float gxx = has_r ? utr - ut[r] : 0.0f;
-            const float gyy = gy < fr.H - 1 ? utd - ut[r] : 0.0f;
-            dual(p1[r], p2[r], p3[r], gxx, gyy, c[r], kc.sigma);
+            dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r], kc.sigma);
             u[r] = un[r];
         }
     }
 
     float* __restrict__ uout = P.u[cur ^ 1];
     float* __restrict__ pout = P.p[cur ^ 1];
-    const bool col_out = col_in && lane >= K && lane < 64 - K;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = wave * R + r;
         const int gy = gy0 + r;
-        if (col_out && row >= K && row < NW * R - K && gy >= 0 && gy < fr.H) {
+        if (col_out && row >= K && row < RH - K && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
             uout[k] = u[r];
             pout[k] = p1[r];
             pout[np + k] = p2[r];
             pout[2 * np + k] = p3[r];
+            if (mode & kZero) {
+                P.npos[k] = 0;
+                P.nneg[k] = 0;
+            }
         }
     }
 }
@@ -463,57 +683,80 @@ __global__ __launch_bounds__(256) void k_gap_final(Planes P, size_t nblocks, int
     }
 }
 
-inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
-
 template <int R, int NW>
-hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, int cur, int K, hipStream_t s) {
+hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
+                        const EventSegs& segs, int cur, int K, int mode, hipStream_t s,
+                        LaunchEv ev) {
     const int OW = 64 - 2 * K, OH = NW * R - 2 * K;
+    if (K < 1 || OW <= 0 || OH <= 0) return hipErrorInvalidValue;
     const int tiles_x = (fr.W + OW - 1) / OW;
     const int tiles_y = (fr.H + OH - 1) / OH;
     const int ntiles = tiles_x * tiles_y;
-    hipLaunchKernelGGL((k_pd_fused<R, NW>), dim3(ntiles), dim3(64 * NW), 0, s, P, fr, kc, cur, K,
-                       tiles_x, ntiles);
-    return hipGetLastError();
+    return launch(k_pd_fused<R, NW>, dim3(ntiles), dim3(64 * NW), fused_lds_bytes(R, NW, mode), s,
+                  ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
 }
 
 }  // namespace
 
 size_t gap_blocks(size_t np) { return (np + kGapBlock - 1) / kGapBlock; }
 
+size_t fused_lds_bytes(int rows, int waves, int mode) {
+    if (!(mode & kEvents)) return 0;
+    const size_t RH = (size_t)rows * waves;
+    return 2 * RH * 64 * sizeof(int32_t) + (RH + 1) * 65 * sizeof(long long);
+}
+
+int fused_tiles(Frame fr, int rows, int waves, int iters) {
+    const int OW = 64 - 2 * iters, OH = rows * waves - 2 * iters;
+    if (OW <= 0 || OH <= 0) return -1;
+    return ((fr.W + OW - 1) / OW) * ((fr.H + OH - 1) / OH);
+}
+
 hipError_t launch_init(const Planes& P, Frame fr, float u_init, bool keep_u, hipStream_t s) {
     const size_t np = (size_t)fr.W * fr.H;
-    hipLaunchKernelGGL(k_init, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, np, u_init,
-                       keep_u ? 1 : 0);
-    return hipGetLastError();
+    return launch(k_init, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P, np,
+                  u_init, keep_u ? 1 : 0);
 }
 
 hipError_t launch_push(const Planes& P, Frame fr, const int64_t* t, const uint16_t* x,
-                       const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s) {
+                       const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s,
+                       LaunchEv ev) {
     if (n <= 0) return hipSuccess;
-    if (n <= kSmallPush) {
-        hipLaunchKernelGGL(k_push_small, dim3(1), dim3(1024), 0, s, P, fr, t, x, y, pol, n);
-        return hipGetLastError();
-    }
+    if (n <= kSmallPush)
+        return launch(k_push_small, dim3(1), dim3(1024), 0, s, ev.start, ev.stop, P, fr, t, x, y,
+                      pol, n);
     const unsigned g = blocks_for((size_t)n, 256);
-    hipLaunchKernelGGL(k_validate, dim3(g), dim3(256), 0, s, P, fr, t, x, y, pol, n);
-    hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, P, fr, t, x, y, pol, n);
-    hipLaunchKernelGGL(k_push_finalize, dim3(1), dim3(64), 0, s, P, fr, t, x, y, pol, n);
-    return hipGetLastError();
+    hipError_t e = launch(k_validate, dim3(g), dim3(256), 0, s, ev.start, nullptr, P, fr, t, x, y,
+                          pol, n);
+    if (e == hipSuccess)
+        e = launch(k_scatter, dim3(g), dim3(256), 0, s, nullptr, nullptr, P, fr, t, x, y, pol, n);
+    if (e == hipSuccess)
+        e = launch(k_push_finalize, dim3(1), dim3(64), 0, s, nullptr, ev.stop, P, fr, t, x, y, pol,
+                   n);
+    return e;
 }
 
-hipError_t launch_build(const Planes& P, Frame fr, int cur, double dpos, double dneg,
-                        double time_unit_us, hipStream_t s) {
+hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, hipStream_t s,
+                        LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
-    hipLaunchKernelGGL(k_build, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr, cur, dpos, dneg,
-                       time_unit_us);
-    return hipGetLastError();
+    return launch(k_build, dim3(blocks_for(np, 256)), dim3(256), 0, s, ev.start, ev.stop, P, fr,
+                  cur, bc);
 }
 
-hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hipStream_t s) {
+hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
+                         LaunchEv ev) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t n = zero_counts ? np : 1;
+    return launch(k_finish, dim3(blocks_for(n, 256)), dim3(256), 0, s, ev.start, ev.stop, P, np,
+                  zero_counts ? 1 : 0);
+}
+
+hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hipStream_t s,
+                           LaunchEv ev) {
     const dim3 grid((fr.W + 63) / 64, (fr.H + 3) / 4);
-    hipLaunchKernelGGL(k_primal, grid, dim3(256), 0, s, P, fr, kc, cur);
-    hipLaunchKernelGGL(k_dual, grid, dim3(256), 0, s, P, fr, kc, cur);
-    return hipGetLastError();
+    hipError_t e = launch(k_primal, grid, dim3(256), 0, s, ev.start, nullptr, P, fr, kc, cur);
+    if (e == hipSuccess) e = launch(k_dual, grid, dim3(256), 0, s, nullptr, ev.stop, P, fr, kc, cur);
+    return e;
 }
 
 bool fused_shape_supported(int rows, int waves) {
@@ -528,51 +771,52 @@ bool fused_shape_supported(int rows, int waves) {
     }
 }
 
-hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, int cur, int iters,
-                           int rows, int waves, hipStream_t s) {
+hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
+                           const EventSegs& segs, int cur, int iters, int mode, int rows,
+                           int waves, hipStream_t s, LaunchEv ev) {
     switch (rows * 100 + waves) {
-        case 202: return fused_launch<2, 2>(P, fr, kc, cur, iters, s);
-        case 204: return fused_launch<2, 4>(P, fr, kc, cur, iters, s);
-        case 208: return fused_launch<2, 8>(P, fr, kc, cur, iters, s);
-        case 216: return fused_launch<2, 16>(P, fr, kc, cur, iters, s);
-        case 401: return fused_launch<4, 1>(P, fr, kc, cur, iters, s);
-        case 402: return fused_launch<4, 2>(P, fr, kc, cur, iters, s);
-        case 404: return fused_launch<4, 4>(P, fr, kc, cur, iters, s);
-        case 408: return fused_launch<4, 8>(P, fr, kc, cur, iters, s);
-        case 416: return fused_launch<4, 16>(P, fr, kc, cur, iters, s);
-        case 801: return fused_launch<8, 1>(P, fr, kc, cur, iters, s);
-        case 802: return fused_launch<8, 2>(P, fr, kc, cur, iters, s);
-        case 804: return fused_launch<8, 4>(P, fr, kc, cur, iters, s);
-        case 808: return fused_launch<8, 8>(P, fr, kc, cur, iters, s);
-        case 1601: return fused_launch<16, 1>(P, fr, kc, cur, iters, s);
-        case 1602: return fused_launch<16, 2>(P, fr, kc, cur, iters, s);
-        case 1604: return fused_launch<16, 4>(P, fr, kc, cur, iters, s);
+        case 202: return fused_launch<2, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 204: return fused_launch<2, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 208: return fused_launch<2, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 216: return fused_launch<2, 16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 401: return fused_launch<4, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 402: return fused_launch<4, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 404: return fused_launch<4, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 408: return fused_launch<4, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 416: return fused_launch<4, 16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 801: return fused_launch<8, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 802: return fused_launch<8, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 804: return fused_launch<8, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 808: return fused_launch<8, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 1601: return fused_launch<16, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 1602: return fused_launch<16, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        case 1604: return fused_launch<16, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, hipStream_t s) {
+                      int cur, int slot, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t nb = gap_blocks(np);
-    hipLaunchKernelGGL(k_gap, dim3((unsigned)nb), dim3(kGapBlock), 0, s, P, fr, lambda, umin, umax,
-                       cur);
-    hipLaunchKernelGGL(k_gap_final, dim3(1), dim3(256), 0, s, P, nb, slot);
-    return hipGetLastError();
+    hipError_t e = launch(k_gap, dim3((unsigned)nb), dim3(kGapBlock), 0, s, ev.start, nullptr, P,
+                          fr, lambda, umin, umax, cur);
+    if (e == hipSuccess)
+        e = launch(k_gap_final, dim3(1), dim3(256), 0, s, nullptr, ev.stop, P, nb, slot);
+    return e;
 }
 
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
                              hipStream_t s) {
     const size_t np = (size_t)fr.W * fr.H;
-    hipLaunchKernelGGL(k_time_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr,
-                       time_unit_us, out);
-    return hipGetLastError();
+    return launch(k_time_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P,
+                  fr, time_unit_us, out);
 }
 
 hipError_t launch_metric_plane(const Planes& P, Frame fr, float* out, hipStream_t s) {
     const size_t np = (size_t)fr.W * fr.H;
-    hipLaunchKernelGGL(k_metric_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, P, fr, out);
-    return hipGetLastError();
+    return launch(k_metric_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P,
+                  fr, out);
 }
 
 }  // namespace rec

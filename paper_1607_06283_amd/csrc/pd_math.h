@@ -1,10 +1,10 @@
 // Per-pixel arithmetic of the primal-dual iteration on the event manifold.
 //
-// Every kernel that updates (u, p) -- the two-kernel loop, the fused
-// temporally-blocked loop and the gap evaluation -- calls these inline
-// functions, so a pixel's update is the same sequence of FP32 operations
-// whichever kernel runs it (the library is compiled with -ffp-contract=off
-// and every fused multiply-add below is explicit).
+// Every kernel that updates (u, p) -- the two-kernel loop and the fused
+// temporally-blocked loop -- calls these inline functions, so a pixel's
+// update is the same sequence of FP32 operations whichever kernel runs it
+// (the library is compiled with -ffp-contract=off and every fused
+// multiply-add below is explicit).
 //
 // Notation (Section 3.1-3.2 of the paper):
 //   tx, ty      forward differences of the time surface tau
@@ -14,6 +14,16 @@
 //   q           M^T p; the adjoint is L_g^* p = -div q
 //   beta        tau * lambda * s            (KL prox, eqn. update_rules)
 //   c4          4 beta f
+//
+// Boundary handling.  The forward differences vanish on the last column
+// (L_x) and the last row (L_y).  Since L_g u = M (L_x u, L_y u), a vanishing
+// L_x u is the same as a zero first column of M at that pixel, and the
+// adjoint's matching backward difference drops q_x there too; likewise for
+// the second column on the last row.  So the column of M that multiplies a
+// difference leaving the image is stored as zero ("masked"), and pixels
+// outside the image carry zero coefficients.  The update formulas then need
+// no per-pixel boundary branches: the neighbour terms they read are exactly
+// zero wherever the operator has no such term.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,9 +31,10 @@
 namespace rec {
 
 struct Coef {
-    float m11, m12, m22, m31, m32;  // M entries (m12 is shared by rows 1 and 2)
-    float G, s;                     // det g and sqrt(det g)
-    float beta, c4;                 // KL prox constants
+    float a11, a21, a31;   // first column of M (multiplies L_x), 0 if masked
+    float b12, b22, b32;   // second column of M (multiplies L_y), 0 if masked
+    float s;               // sqrt(G): dual ball radius
+    float beta, c4;        // KL prox constants
 };
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -31,47 +42,49 @@ __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // Metric-dependent constants of one pixel (computed once per block of
-// iterations; they depend on the block's tau and f only).
-__device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float taulam) {
+// iterations; they depend on the block's tau and f only).  has_x: the pixel
+// has a right neighbour inside the image (so L_x is a real difference);
+// has_y: it has a lower neighbour.
+__device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float taulam, bool has_x,
+                                          bool has_y) {
     Coef c;
     const float ax = __builtin_fmaf(tx, tx, 1.0f);  // 1 + tx^2
     const float ay = __builtin_fmaf(ty, ty, 1.0f);  // 1 + ty^2
     const float G = __builtin_fmaf(tx, tx, ay);     // 1 + tx^2 + ty^2
     const float iG = rcp(G);
-    c.m11 = ay * iG;
-    c.m22 = ax * iG;
-    c.m12 = -(tx * ty) * iG;
-    c.m31 = tx * iG;
-    c.m32 = ty * iG;
-    c.G = G;
+    const float m12 = -(tx * ty) * iG;
+    const float m11 = ay * iG, m22 = ax * iG;
+    const float m31 = tx * iG, m32 = ty * iG;
+    c.a11 = has_x ? m11 : 0.0f;
+    c.a21 = has_x ? m12 : 0.0f;
+    c.a31 = has_x ? m31 : 0.0f;
+    c.b12 = has_y ? m12 : 0.0f;
+    c.b22 = has_y ? m22 : 0.0f;
+    c.b32 = has_y ? m32 : 0.0f;
     c.s = sqrt_(G);
     c.beta = taulam * c.s;
     c.c4 = (4.0f * c.beta) * f;
     return c;
 }
 
-// q = M^T p at one pixel.
+// q = M^T p at one pixel (zero components where the column is masked).
 __device__ __forceinline__ float q_x(const Coef& c, float p1, float p2, float p3) {
-    return __builtin_fmaf(c.m31, p3, __builtin_fmaf(c.m12, p2, c.m11 * p1));
+    return __builtin_fmaf(c.a31, p3, __builtin_fmaf(c.a21, p2, c.a11 * p1));
 }
 __device__ __forceinline__ float q_y(const Coef& c, float p1, float p2, float p3) {
-    return __builtin_fmaf(c.m32, p3, __builtin_fmaf(c.m22, p2, c.m12 * p1));
+    return __builtin_fmaf(c.b32, p3, __builtin_fmaf(c.b22, p2, c.b12 * p1));
 }
 
-// Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel.
-// div q uses backward differences with the boundary of the forward
-// differences' adjoint: +q_x here unless on the last column, -q_x of the
-// left neighbour unless on the first column; likewise along y.
-// The KL prox uses the cancellation-free form of the closed-form root:
-// a = ubar - beta, r = sqrt(a^2 + 4 beta f):
-//   a >= 0: (a + r) / 2,   a < 0: 2 beta f / (r - a);   then clamp.
-__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left,
-                                        float qy_up, bool has_r, bool has_l, bool has_d,
-                                        bool has_u, const Coef& c, float tau, float umin,
-                                        float umax) {
-    const float dx = (has_r ? qx : 0.0f) - (has_l ? qx_left : 0.0f);
-    const float dy = (has_d ? qy : 0.0f) - (has_u ? qy_up : 0.0f);
-    const float ubar = __builtin_fmaf(tau, dx + dy, u);
+// Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel, with
+// div q = (q_x - q_x(left)) + (q_y - q_y(up)) (backward differences; the
+// neighbour values are 0 outside the image).  The KL prox uses the
+// cancellation-free form of the closed-form root: a = ubar - beta,
+// r = sqrt(a^2 + 4 beta f):  a >= 0: (a + r) / 2,  a < 0: 2 beta f / (r - a);
+// then clamp to [umin, umax].
+__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
+                                        const Coef& c, float tau, float umin, float umax) {
+    const float div = (qx - qx_left) + (qy - qy_up);
+    const float ubar = __builtin_fmaf(tau, div, u);
     const float a = ubar - c.beta;
     const float r = sqrt_(__builtin_fmaf(a, a, c.c4));
     const float pos = 0.5f * (a + r);
@@ -85,23 +98,24 @@ __device__ __forceinline__ float extrapolate(float un, float u) {
     return __builtin_fmaf(2.0f, un, -u);
 }
 
-// Dual step p_{k+1} = prox_{sigma R^*}(p_k + sigma L_g ubar) at one pixel, with
-// (gx, gy) the forward differences of the extrapolated primal; the prox is
-// the projection onto the ball of radius s: p / max(1, |p| / s).
+// Dual step p_{k+1} = prox_{sigma R^*}(p_k + sigma M (gx, gy)) at one pixel,
+// with (gx, gy) the forward differences of the extrapolated primal (any
+// finite value where the column of M is masked); the prox is the projection
+// onto the ball of radius s, p / max(1, |p| / s), computed as
+// p * min(1, s / |p|).
 __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
                                      const Coef& c, float sigma) {
-    const float v1 = __builtin_fmaf(c.m12, gy, c.m11 * gx);
-    const float v2 = __builtin_fmaf(c.m22, gy, c.m12 * gx);
-    const float v3 = __builtin_fmaf(c.m32, gy, c.m31 * gx);
-    float b1 = __builtin_fmaf(sigma, v1, p1);
-    float b2 = __builtin_fmaf(sigma, v2, p2);
-    float b3 = __builtin_fmaf(sigma, v3, p3);
+    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
+    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
+    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
+    const float b1 = __builtin_fmaf(sigma, v1, p1);
+    const float b2 = __builtin_fmaf(sigma, v2, p2);
+    const float b3 = __builtin_fmaf(sigma, v3, p3);
     const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
-    const float sc = c.s * rsq(n2);
-    const bool out = n2 > c.G;
-    p1 = out ? b1 * sc : b1;
-    p2 = out ? b2 * sc : b2;
-    p3 = out ? b3 * sc : b3;
+    const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
+    p1 = b1 * sc;
+    p2 = b2 * sc;
+    p3 = b3 * sc;
 }
 
 }  // namespace rec

@@ -1,6 +1,16 @@
 // C ABI of the reconstruction library: parameter and event validation,
 // workspace layout, context state and launch sequencing.  All arithmetic of
 // the method runs in the kernels of kernels.hip.
+//
+// Per block of events the device work is:
+//   - device-pointer pushes are recorded, not launched; the first fused
+//     primal-dual launch of the next solve validates and bins them itself
+//     (up to kMaxSegs pushes and kFoldMaxEvents events; beyond that, and for
+//     host-pointer pushes, the events are scattered by their own kernels);
+//   - the solve's first fused launch builds f, tx, ty and iterates; the
+//     next launches iterate; the second one commits the stream state (or a
+//     small finishing kernel does, when the solve has one launch).
+// So a block of a small sensor costs ceil(iters / K) launches and no events.
 #include <math.h>
 #include <string.h>
 
@@ -17,6 +27,8 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kProfClasses = 4;  // push, build, primal-dual, gap
 constexpr size_t kProfFlush = 1u << 15;
+constexpr int64_t kFoldMaxEvents = 16384;   // events binned in the first launch at most
+constexpr int64_t kFoldMaxWork = 1 << 24;   // events x tiles scanned in it at most
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 
@@ -55,6 +67,14 @@ size_t carve(const rec_params* prm, char* base, Planes* P) {
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
 
+struct Seg {
+    const int64_t* t;
+    const uint16_t* x;
+    const uint16_t* y;
+    const int8_t* p;
+    int64_t n;
+};
+
 }  // namespace
 
 struct rec_ctx {
@@ -66,7 +86,7 @@ struct rec_ctx {
     int device;
     int cur;                 // which ping-pong buffers hold the current (u, p)
     int rows, waves;         // fused tile shape
-    int kmax;                // largest iterations per fused launch for that shape
+    int kmax;                // iterations per fused launch (at most)
     // host staging for host-pointer pushes
     char* pinned;
     int64_t* h_t;
@@ -75,6 +95,10 @@ struct rec_ctx {
     int8_t* h_p;
     hipEvent_t staging_done;
     bool staging_busy;
+    // device-pointer pushes recorded but not scattered yet (in order)
+    std::vector<Seg> deferred;
+    int64_t deferred_events;
+    bool counts_dirty;       // scattered pushes left counts for the next solve
     // host mirror of the device stream state (valid while only host pushes ran)
     bool mirror_known;
     bool mirror_started;
@@ -83,7 +107,7 @@ struct rec_ctx {
     // profiling
     bool prof_on;
     std::vector<hipEvent_t> prof_pool;
-    std::vector<int> prof_cls;   // class of each recorded (start, stop) pair
+    std::vector<int> prof_cls;   // class of each (start, stop) pair
     std::vector<int64_t> prof_work;
     size_t prof_used;
     double prof_ms[kProfClasses];
@@ -122,21 +146,20 @@ int prof_flush(rec_ctx* c) {
     return REC_OK;
 }
 
-// Brackets one launch with a timing event pair when profiling is on.
+// Runs one launch; when profiling, the launch packet itself records a
+// (start, stop) timing event pair, so the pair measures the kernel(s) only.
 template <class F>
 int timed(rec_ctx* c, int cls, int64_t work, F&& launch) {
-    if (!c->prof_on) return dev_err(launch());
+    if (!c->prof_on) return dev_err(launch(rec::LaunchEv{}));
     if (c->prof_used + 2 > kProfFlush) {
         const int rc = prof_flush(c);
         if (rc) return rc;
     }
-    hipEvent_t a = prof_event(c);
-    hipEvent_t b = prof_event(c);
-    if (!a || !b) return REC_EDEVICE;
-    if (hipEventRecord(a, c->stream) != hipSuccess) return REC_EDEVICE;
-    const hipError_t e = launch();
-    if (e != hipSuccess) return REC_EDEVICE;
-    if (hipEventRecord(b, c->stream) != hipSuccess) return REC_EDEVICE;
+    rec::LaunchEv ev;
+    ev.start = prof_event(c);
+    ev.stop = prof_event(c);
+    if (!ev.start || !ev.stop) return REC_EDEVICE;
+    if (launch(ev) != hipSuccess) return REC_EDEVICE;
     c->prof_cls.push_back(cls);
     c->prof_work.push_back(work);
     return REC_OK;
@@ -158,14 +181,44 @@ int read_state(rec_ctx* c, rec::DevState* out) {
     return REC_OK;
 }
 
-void choose_shape(const rec_params* prm, int* rows, int* waves) {
-    int r = prm->tile_rows, w = prm->tile_waves;
-    if (r == 0 || w == 0) {
-        r = 8;
-        w = 4;
+// Scatters the recorded device-pointer pushes with their own kernels.
+int flush_deferred(rec_ctx* c) {
+    for (const Seg& s : c->deferred) {
+        const int rc = timed(c, 0, s.n, [&](rec::LaunchEv ev) {
+            return rec::launch_push(c->P, c->fr, s.t, s.x, s.y, s.p, s.n, c->stream, ev);
+        });
+        if (rc) return rc;
+        c->counts_dirty = true;
     }
+    c->deferred.clear();
+    c->deferred_events = 0;
+    return REC_OK;
+}
+
+// Fused tile shape (rows per lane, wavefronts per workgroup) and iterations
+// per launch.  Measured on MI355X: small frames are limited by launch
+// latency, so they take thin tiles (many workgroups) and long launches;
+// large frames are limited by HBM and VALU, so they take taller tiles and
+// short launches (less halo recomputation).
+void choose_shape(const rec_params* prm, int* rows, int* waves, int* kiters) {
+    const int64_t np = (int64_t)prm->width * prm->height;
+    int r = prm->tile_rows, w = prm->tile_waves, k;
+    if (np <= 250000) {
+        if (!r) { r = 2; w = 16; }
+        k = 13;
+    } else if (np <= 4000000) {
+        if (!r) { r = 8; w = 8; }
+        k = 8;
+    } else {
+        if (!r) { r = 8; w = 4; }
+        k = 4;
+    }
+    if (prm->fuse_iters > 0) k = prm->fuse_iters;
+    const int kmax = (r * w - 1) / 2 < 31 ? (r * w - 1) / 2 : 31;
+    if (k > kmax) k = kmax;
     *rows = r;
     *waves = w;
+    *kiters = k;
 }
 
 }  // namespace
@@ -188,7 +241,7 @@ void rec_default_params(rec_params* prm, int32_t width, int32_t height) {
     prm->u_init = sqrt(prm->u_min * prm->u_max);
     prm->iters = 50;
     prm->gap_every = 0;
-    prm->fuse_iters = 8;
+    prm->fuse_iters = -1;
     prm->max_events = 65536;
     prm->tile_rows = 0;
     prm->tile_waves = 0;
@@ -207,7 +260,7 @@ int rec_check_params(const rec_params* prm) {
     if (!isfinite(prm->time_unit_us) || prm->time_unit_us < 0.0) return REC_EINVAL;
     if (!finite_pos(prm->u_init)) return REC_EINVAL;
     if (prm->iters < 0 || prm->gap_every < 0) return REC_EINVAL;
-    if (prm->fuse_iters < 0 || prm->fuse_iters > 31) return REC_EINVAL;
+    if (prm->fuse_iters < -1 || prm->fuse_iters > 31) return REC_EINVAL;
     if (prm->max_events < 1 || prm->max_events > (1 << 28)) return REC_EINVAL;
     if ((prm->tile_rows == 0) != (prm->tile_waves == 0)) return REC_EINVAL;
     if (prm->tile_rows && !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves))
@@ -264,9 +317,7 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     c->kc.umax = (float)prm->u_max;
     c->stream = (hipStream_t)hip_stream;
     c->cur = 0;
-    choose_shape(prm, &c->rows, &c->waves);
-    c->kmax = (c->rows * c->waves - 1) / 2;
-    if (c->kmax > 31) c->kmax = 31;
+    choose_shape(prm, &c->rows, &c->waves, &c->kmax);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return REC_EDEVICE;
@@ -282,8 +333,7 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     c->h_y = (uint16_t*)(c->pinned + align_up(ne * 8) + align_up(ne * 2));
     c->h_p = (int8_t*)(c->pinned + align_up(ne * 8) + 2 * align_up(ne * 2));
     if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(c->pinned);
-        delete c;
+        rec_destroy(c);
         return REC_EDEVICE;
     }
     c->mirror_known = true;
@@ -312,20 +362,34 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
     if (!t_us || !x || !y || !polarity) return REC_EINVAL;
     if (on_device) {
         c->mirror_known = false;
-        return timed(c, 0, n, [&] {
-            return rec::launch_push(c->P, c->fr, t_us, x, y, polarity, n, c->stream);
-        });
+        if (c->prm.fuse_iters == 0) {
+            // the unfused loop has no first launch to fold the events into
+            c->counts_dirty = true;
+            return timed(c, 0, n, [&](rec::LaunchEv ev) {
+                return rec::launch_push(c->P, c->fr, t_us, x, y, polarity, n, c->stream, ev);
+            });
+        }
+        if ((int)c->deferred.size() == rec::kMaxSegs) {
+            const int rc = flush_deferred(c);
+            if (rc) return rc;
+        }
+        c->deferred.push_back(Seg{t_us, x, y, polarity, n});
+        c->deferred_events += n;
+        return REC_OK;
     }
+    // host pointers: earlier device pushes go first, then validate here
+    int rc = flush_deferred(c);
+    if (rc) return rc;
     if (!c->mirror_known) {
         rec::DevState st;
-        const int rc = read_state(c, &st);
+        rc = read_state(c, &st);
         if (rc) return rc;
         c->mirror_known = true;
         c->mirror_started = st.started != 0;
         c->mirror_tref = st.t_ref;
     }
-    const int rc = rec_check_events(t_us, x, y, polarity, n, c->prm.width, c->prm.height,
-                                    c->mirror_started ? c->mirror_tref : INT64_MIN);
+    rc = rec_check_events(t_us, x, y, polarity, n, c->prm.width, c->prm.height,
+                          c->mirror_started ? c->mirror_tref : INT64_MIN);
     if (rc) return rc;
     const int64_t cap = c->prm.max_events;
     for (int64_t a = 0; a < n; a += cap) {
@@ -343,14 +407,15 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
         if (e == hipSuccess)
             e = hipMemcpyAsync(c->P.ev_p, c->h_p, (size_t)m, hipMemcpyHostToDevice, c->stream);
         if (e != hipSuccess) return REC_EDEVICE;
-        const int r2 = timed(c, 0, m, [&] {
+        rc = timed(c, 0, m, [&](rec::LaunchEv ev) {
             return rec::launch_push(c->P, c->fr, c->P.ev_t, c->P.ev_x, c->P.ev_y, c->P.ev_p, m,
-                                    c->stream);
+                                    c->stream, ev);
         });
-        if (r2) return r2;
+        if (rc) return rc;
         if (hipEventRecord(c->staging_done, c->stream) != hipSuccess) return REC_EDEVICE;
         c->staging_busy = true;
     }
+    c->counts_dirty = true;
     c->mirror_started = true;
     c->mirror_tref = t_us[n - 1];
     return REC_OK;
@@ -360,39 +425,89 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
     if (!c) return REC_EINVAL;
     if (iters <= 0) iters = c->prm.iters;
     const int64_t np = (int64_t)c->fr.W * c->fr.H;
-    int rc = timed(c, 1, np, [&] {
-        return rec::launch_build(c->P, c->fr, c->cur, c->prm.delta_pos, c->prm.delta_neg,
-                                 c->prm.time_unit_us, c->stream);
-    });
-    if (rc) return rc;
-    const int ge = c->prm.gap_every;
-    const int fuse = c->prm.fuse_iters;
-    const int step = fuse > 0 ? (fuse < c->kmax ? fuse : c->kmax) : 1;
-    int samples = 0;
-    for (int it = 0; it < iters;) {
-        int m = iters - it < step ? iters - it : step;
-        if (ge > 0) {
-            const int to_gap = ge - it % ge;
-            if (m > to_gap) m = to_gap;
+    const rec::BuildConsts bc{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
+    const bool fused = c->prm.fuse_iters != 0 && iters > 0;
+    int rc;
+    rec::EventSegs segs;
+    memset(&segs, 0, sizeof(segs));
+    bool fold = false;
+    if (fused && !c->deferred.empty()) {
+        const int first_k = iters < c->kmax ? iters : c->kmax;
+        const int64_t tiles = rec::fused_tiles(c->fr, c->rows, c->waves, first_k);
+        fold = c->deferred_events <= kFoldMaxEvents && tiles > 0 &&
+               c->deferred_events * tiles <= kFoldMaxWork;
+    }
+    if (fold) {
+        for (size_t s = 0; s < c->deferred.size(); ++s) {
+            segs.t[s] = c->deferred[s].t;
+            segs.x[s] = c->deferred[s].x;
+            segs.y[s] = c->deferred[s].y;
+            segs.p[s] = c->deferred[s].p;
+            segs.n[s] = c->deferred[s].n;
         }
-        if (fuse > 0) {
-            rc = timed(c, 2, np * m, [&] {
-                return rec::launch_pd_fused(c->P, c->fr, c->kc, c->cur, m, c->rows, c->waves,
-                                            c->stream);
-            });
-        } else {
-            rc = timed(c, 2, np, [&] {
-                return rec::launch_pd_plain(c->P, c->fr, c->kc, c->cur, c->stream);
-            });
-        }
+        segs.count = (int32_t)c->deferred.size();
+        c->deferred.clear();
+        c->deferred_events = 0;
+    } else {
+        rc = flush_deferred(c);
         if (rc) return rc;
-        c->cur ^= 1;
-        it += m;
+    }
+    if (!fused) {
+        rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
+            return rec::launch_build(c->P, c->fr, c->cur, bc, c->stream, ev);
+        });
+        if (rc) return rc;
+        c->counts_dirty = false;
+    }
+    const bool counts = c->counts_dirty;
+    const int ge = c->prm.gap_every;
+    int samples = 0;
+    int launch = 0;
+    // iterations are cut into segments ending at gap samples; each segment
+    // is split evenly into launches of at most kmax iterations
+    for (int it = 0; it < iters;) {
+        int seg = iters - it;
+        if (ge > 0 && seg > ge - it % ge) seg = ge - it % ge;
+        if (!fused) {
+            for (int q = 0; q < seg; ++q) {
+                rc = timed(c, 2, np, [&](rec::LaunchEv ev) {
+                    return rec::launch_pd_plain(c->P, c->fr, c->kc, c->cur, c->stream, ev);
+                });
+                if (rc) return rc;
+                c->cur ^= 1;
+            }
+        } else {
+            const int nl = (seg + c->kmax - 1) / c->kmax;
+            for (int q = 0; q < nl; ++q) {
+                const int m = seg / nl + (q < seg % nl ? 1 : 0);
+                int mode = 0;
+                if (launch == 0)
+                    mode = rec::kBuild | (fold ? rec::kEvents : 0) | (counts ? rec::kCounts : 0);
+                else if (launch == 1)
+                    mode = rec::kCommit | (counts ? rec::kZero : 0);
+                rc = timed(c, 2, np * m, [&](rec::LaunchEv ev) {
+                    return rec::launch_pd_fused(c->P, c->fr, c->kc, bc, segs, c->cur, m, mode,
+                                                c->rows, c->waves, c->stream, ev);
+                });
+                if (rc) return rc;
+                c->cur ^= 1;
+                if (launch == 0 && iters <= m) {
+                    // a single launch: commit and reset counts in their own kernel
+                    rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
+                        return rec::launch_finish(c->P, c->fr, counts, c->stream, ev);
+                    });
+                    if (rc) return rc;
+                }
+                ++launch;
+            }
+            c->counts_dirty = false;
+        }
+        it += seg;
         if (ge > 0 && it % ge == 0) {
             const int slot = samples < rec::kGapHistCap ? samples : rec::kGapHistCap - 1;
-            rc = timed(c, 3, np, [&] {
+            rc = timed(c, 3, np, [&](rec::LaunchEv ev) {
                 return rec::launch_gap(c->P, c->fr, c->prm.lambda, c->prm.u_min, c->prm.u_max,
-                                       c->cur, slot, c->stream);
+                                       c->cur, slot, c->stream, ev);
             });
             if (rc) return rc;
             ++samples;
@@ -424,6 +539,12 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
 int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
     if (!c || !out) return REC_EINVAL;
     const size_t np = (size_t)c->fr.W * c->fr.H;
+    // planes that pushes write are read after the recorded pushes are scattered
+    if (which == REC_COUNT_POS || which == REC_COUNT_NEG || which == REC_T_LAST ||
+        which == REC_TIME) {
+        const int rc = flush_deferred(c);
+        if (rc) return rc;
+    }
     const void* src = nullptr;
     size_t bytes = np * 4;
     hipError_t e = hipSuccess;
@@ -489,6 +610,8 @@ int rec_gap_history(rec_ctx* c, double* gap, double* energy, int32_t cap) {
 
 int rec_sync(rec_ctx* c) {
     if (!c) return REC_EINVAL;
+    const int rc = flush_deferred(c);
+    if (rc) return rc;
     return read_state(c, nullptr);
 }
 

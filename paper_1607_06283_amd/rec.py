@@ -251,6 +251,10 @@ class Reconstructor:
         _check(rc, "rec_init")
         self.ctx = h
         self.shape = (self.prm.height, self.prm.width)
+        # device event tensors pushed but not yet consumed by the device: the
+        # library reads them when the next solve (or sync) runs, so they are
+        # kept alive until that work is enqueued on the stream
+        self._pending = []
 
     def close(self):
         if getattr(self, "ctx", None):
@@ -274,9 +278,12 @@ class Reconstructor:
             y = np.ascontiguousarray(y, np.uint16)
             p = np.ascontiguousarray(p, np.int8)
         _check(rec_push_events(self.ctx, t, x, y, p, n, 1 if on_device else 0), "rec_push_events")
+        if on_device:
+            self._pending.append((t, x, y, p))
 
     def solve(self, iters: int = 0, stats: bool = False) -> Optional[rec_stats]:
         rc, st = rec_solve(self.ctx, iters, stats)
+        self._pending.clear()
         _check(rc, "rec_solve")
         return st
 
@@ -288,17 +295,23 @@ class Reconstructor:
         if device:
             tdt = {np.int32: self.torch.int32, np.int64: self.torch.int64}.get(dt, self.torch.float32)
             out = self.torch.empty(n, dtype=tdt, device=self.device)
-            _check(rec_get_image(self.ctx, which, out, 1), "rec_get_image")
+            rc = rec_get_image(self.ctx, which, out, 1)
+            self._pending.clear()
+            _check(rc, "rec_get_image")
             return out.view(*shape)
         out = np.empty(n, dtype=dt)
-        _check(rec_get_image(self.ctx, which, out, 0), "rec_get_image")
+        rc = rec_get_image(self.ctx, which, out, 0)
+        self._pending.clear()
+        _check(rc, "rec_get_image")
         return out.reshape(shape)
 
     def gap_history(self):
         return rec_gap_history(self.ctx)
 
     def sync(self) -> None:
-        _check(rec_sync(self.ctx), "rec_sync")
+        rc = rec_sync(self.ctx)
+        self._pending.clear()
+        _check(rc, "rec_sync")
 
 
 DEFAULT_STEP = 1.0 / math.sqrt(8.0 + 4.0 * math.sqrt(2.0))

@@ -158,7 +158,9 @@ def test_fused_equals_plain_bitwise(W, H):
     runs = []
     cfgs = [dict(fuse_iters=0), dict(fuse_iters=8), dict(fuse_iters=5, tile_rows=4, tile_waves=4),
             dict(fuse_iters=3, tile_rows=2, tile_waves=8), dict(fuse_iters=1, tile_rows=8, tile_waves=1),
-            dict(fuse_iters=15, tile_rows=8, tile_waves=4)]
+            dict(fuse_iters=15, tile_rows=8, tile_waves=4), dict(fuse_iters=-1),
+            dict(fuse_iters=12, tile_rows=2, tile_waves=16, gap_every=5),
+            dict(fuse_iters=0, gap_every=7)]
     for cfg in cfgs:
         r = rec.Reconstructor(W, H, **cfg)
         for a in range(0, n, n // 4):
@@ -273,3 +275,85 @@ def test_device_push_errors_are_deferred_and_atomic():
         r.push(np.array([12], np.int64), np.array([1], np.uint16), np.array([1], np.uint16),
                np.array([1], np.int8))
     assert e.value.code == rec.REC_EORDER
+
+
+# --------------------------------------------------------------------------
+# Device pushes folded into the first fused launch
+# --------------------------------------------------------------------------
+
+def test_folded_pushes_match_scattered_pushes(c1):
+    """Device-pointer pushes are binned by the solve's first launch; host
+    pushes are scattered by their own kernels.  Both give the same image,
+    time planes and latest timestamps, bit for bit."""
+    a = rec.Reconstructor(128, 128)
+    b = rec.Reconstructor(128, 128)
+    for blk in evgen.batches(c1.events, 500)[:6]:
+        a.push(*device_events(blk), on_device=True)
+        b.push(blk.t, blk.x, blk.y, blk.p)
+        sa = a.solve(50, stats=True)
+        sb = b.solve(50, stats=True)
+        assert (sa.t_ref_us, sa.events_in_batch) == (sb.t_ref_us, sb.events_in_batch)
+    for plane in (rec.REC_U, rec.REC_F, rec.REC_TX, rec.REC_TY, rec.REC_STATE_P, rec.REC_T_LAST,
+                  rec.REC_TIME):
+        assert np.array_equal(a.image(plane), b.image(plane)), plane
+
+
+def _dev(t, x, y, p):
+    import torch
+    return (torch.tensor(t, dtype=torch.int64, device="cuda"),
+            torch.tensor(x, dtype=torch.int16, device="cuda"),
+            torch.tensor(y, dtype=torch.int16, device="cuda"),
+            torch.tensor(p, dtype=torch.int8, device="cuda"))
+
+
+def test_folded_push_errors_all_or_nothing():
+    """Folded pushes are validated in order, each all-or-nothing, with the
+    codes of the host check; the first error is reported at the next sync."""
+    W, H = 70, 40
+    pushes = [
+        ([100, 101, 105], [1, 69, 3], [0, 39, 7], [1, -1, 1]),        # ok
+        ([106, 107, 108], [2, 3, 4], [1, 1, 1], [1, 0, 1]),           # bad polarity
+        ([106, 110, 110], [5, 6, 7], [2, 2, 2], [-1, 1, 1]),          # ok (ties allowed)
+        ([109, 111, 112], [8, 9, 10], [3, 3, 3], [1, 1, 1]),          # goes back in time
+        ([120, 121, 122], [11, 70, 12], [4, 4, 4], [1, 1, 1]),        # x out of range
+        ([130, 131, 132], [13, 14, 15], [5, 5, 5], [1, -1, -1]),      # ok
+    ]
+    r = rec.Reconstructor(W, H)
+    o = oracle.Oracle(oracle_params(r.prm))
+    codes = []
+    for t, x, y, p in pushes[:4]:
+        r.push(*_dev(t, x, y, p), on_device=True)
+        codes.append(o.push(np.array(t, np.int64), np.array(x, np.uint16), np.array(y, np.uint16),
+                            np.array(p, np.int8)))
+    assert codes == [0, oracle.EINVAL, 0, oracle.EORDER]
+    r.solve(30)
+    o.solve(30)
+    with pytest.raises(rec.RecError) as e:
+        r.sync()
+    assert e.value.code == rec.REC_EINVAL
+    for t, x, y, p in pushes[4:]:
+        r.push(*_dev(t, x, y, p), on_device=True)
+        o.push(np.array(t, np.int64), np.array(x, np.uint16), np.array(y, np.uint16),
+               np.array(p, np.int8))
+    r.solve(30)
+    o.solve(30)
+    with pytest.raises(rec.RecError) as e:
+        r.sync()
+    assert e.value.code == rec.REC_ERANGE
+    assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
+    assert np.array_equal(r.image(rec.REC_TX), o.get(oracle.TX32))
+    assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
+
+
+def test_many_pushes_per_solve(c1):
+    """More device pushes than the first launch folds: the earlier ones are
+    scattered, the rest folded; the result matches the oracle."""
+    r, o = make(128, 128)
+    for blk in evgen.batches(c1.events.slice(0, 3000), 100)[:7]:
+        r.push(*device_events(blk), on_device=True)
+        o.push_events(blk)
+    st = r.solve(50, stats=True)
+    o.solve(50)
+    assert st.events_in_batch == 700 and st.t_ref_us == o.t_ref
+    assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
+    assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
