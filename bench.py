@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 METRIC = "PD iter*Mpix/s and events/s at 50 it/batch; fwd+bwd vs plain; %HBM BW"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX_ITER = 44  # u 4 + p 12 + f 4 + tx/ty 8 read, u 4 + p 12 written
+BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 W_, H_ = 240, 180
 EVENTS_PER_BATCH = 1000
 ITERS = 50
@@ -102,7 +103,7 @@ def hd720_stream(n_batches):
 
 
 def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_BATCH,
-            iters=ITERS, rows=0, waves=0):
+            iters=ITERS, rows=0, waves=0, storage=0):
     import torch
     from paper_1607_06283_amd import rec
 
@@ -111,7 +112,8 @@ def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_B
     x = torch.from_numpy(ev.x.view(np.int16)).to(dev)
     y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
     p = torch.from_numpy(ev.p).to(dev)
-    r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves)
+    r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves,
+                          storage=storage)
     B = batch
 
     def step(i):
@@ -203,6 +205,8 @@ def main():
     ap.add_argument("--rows", type=int, default=0, help="rows per lane of the fused tile (0: auto)")
     ap.add_argument("--waves", type=int, default=0, help="wavefronts per fused workgroup (0: auto)")
     ap.add_argument("--workload", default="davis240", choices=sorted(WORKLOADS))
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
+                    help="storage of the dual field and time differences (arithmetic is FP32)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--copy-probe", action="store_true",
@@ -233,7 +237,8 @@ def main():
         ev = random_stream(W, H, need * B)
     if len(ev) < need * B:
         raise SystemExit("stream too short")
-    kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves)
+    storage = {"f32": 0, "bf16": 1, "f16": 2}[args.storage]
+    kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves, storage=storage)
     log("bench: timed pass")
     dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False, **kw)
     px_iters = args.steps * IT * W * H
@@ -243,6 +248,7 @@ def main():
         "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "storage": args.storage,
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "width": W, "height": H, "events_per_batch": B,
@@ -256,14 +262,15 @@ def main():
         _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True, **kw)
         pd_ms = prof.ms[2]
         pd_launches = int(prof.launches[2])
-        achieved = BYTES_PER_PX_ITER * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
+        bpi = BYTES_PER_PX_ITER if storage == 0 else BYTES_PER_PX_ITER_16
+        achieved = bpi * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "kernel": "k_pd_fused" if args.fuse else "k_primal+k_dual",
             "avg_launch_us": round(pd_ms / pd_launches * 1e3, 3),
             "launches": pd_launches,
-            "bytes_per_px_iter": BYTES_PER_PX_ITER,
+            "bytes_per_px_iter": bpi,
         }
         out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),
                             "pd": round(pd_ms, 3)}

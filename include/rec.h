@@ -88,6 +88,9 @@ enum {
     REC_T_LAST = 9     /* int64[H*W]  latest timestamp (first stream timestamp if none) */
 };
 
+/* Storage of the dual field and the time differences (rec_params.storage). */
+enum { REC_STORE_F32 = 0, REC_STORE_BF16 = 1, REC_STORE_F16 = 2 };
+
 typedef struct rec_ctx rec_ctx;
 
 /* Method and launch parameters.  rec_default_params fills every field. */
@@ -113,7 +116,15 @@ typedef struct {
     int32_t tile_rows;       /* rows per lane in the fused kernel (2, 4, 8, 16); 0 = automatic */
     int32_t tile_waves;      /* wavefronts per fused workgroup (1..16); 0 = automatic;
                                 set both or neither */
-    int32_t reserved[6];     /* must be 0 */
+    int32_t storage;         /* storage of the dual field p and of tx, ty: REC_STORE_F32
+                                (default), REC_STORE_BF16 or REC_STORE_F16; the arithmetic
+                                is FP32 in every case (16-bit forms need the fused loop) */
+    int32_t tvl1_iters;      /* timestamp denoising before the metric is built (Section 4:
+                                "a few iterations of a TV-L1 denoising method"): FP64
+                                Chambolle-Pock iterations for min TV(v) + tvl1_lambda |v - tau|_1;
+                                0 = off (default) */
+    double tvl1_lambda;      /* L1 weight of the denoising, > 0; default 1 */
+    int32_t reserved[4];     /* must be 0 */
 } rec_params;
 
 /* Statistics of one rec_solve (filled when stats are requested). */

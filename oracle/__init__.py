@@ -38,6 +38,8 @@ class _P(ctypes.Structure):
         ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
         ("time_unit_us", ctypes.c_double),
         ("u_init", ctypes.c_double),
+        ("tvl1_iters", ctypes.c_int32),
+        ("tvl1_lambda", ctypes.c_double),
     ]
 
 
@@ -54,10 +56,13 @@ class Params:
     sigma: float = STEP
     time_unit_us: float = 1000.0
     u_init: float = math.exp(0.5)
+    tvl1_iters: int = 0
+    tvl1_lambda: float = 1.0
 
     def _c(self) -> _P:
         return _P(self.width, self.height, self.lam, self.delta_pos, self.delta_neg,
-                  self.u_min, self.u_max, self.tau, self.sigma, self.time_unit_us, self.u_init)
+                  self.u_min, self.u_max, self.tau, self.sigma, self.time_unit_us, self.u_init,
+                  self.tvl1_iters, self.tvl1_lambda)
 
 
 def build(force: bool = True) -> str:
@@ -117,6 +122,8 @@ def _load():
         lib.orc_prox_kl.argtypes = [ctypes.c_double] * 5
         lib.orc_project.restype = None
         lib.orc_project.argtypes = [_vp, _vp, _vp, ctypes.c_double]
+        lib.orc_tvl1.restype = None
+        lib.orc_tvl1.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, _vp]
         _lib = lib
     return _lib
 
@@ -175,6 +182,15 @@ def project(q, s):
     a = [ctypes.c_double(float(v)) for v in q]
     _load().orc_project(ctypes.byref(a[0]), ctypes.byref(a[1]), ctypes.byref(a[2]), float(s))
     return np.array([a[0].value, a[1].value, a[2].value])
+
+
+def tvl1(f, iters: int, lam: float):
+    """TV-L1 denoising of an image by Chambolle-Pock (the timestamp step of Section 4)."""
+    f = _f64(f)
+    H, W = f.shape
+    out = np.empty_like(f)
+    _load().orc_tvl1(W, H, _ptr(f), int(iters), float(lam), _ptr(out))
+    return out
 
 
 def check_params(p: Params) -> int:

@@ -37,6 +37,12 @@
  *     with a = ubar - beta, d = sqrt(a^2 + 4 beta f):
  *     a >= 0: (a + d) / 2;  a < 0: 2 beta f / (d - a).  Then clamp.
  *   - Warm start: u and p carry over between blocks; p starts at 0.
+ *   - Timestamp denoising (Section 4: "a few iterations of a TV-L1
+ *     denoising method", neither the weight nor the count given): optional,
+ *     off by default.  When on, tau is replaced by the result of n
+ *     Chambolle-Pock iterations for  min_v TV(v) + lambda_t |v - tau|_1
+ *     started at v = tau, dual 0, steps 1/sqrt(8), before the differences
+ *     are taken.
  *
  * Primal-dual gap (not in the paper; standard Fenchel duality for eqn. (5)),
  * per pixel, with A = L_g u, d = (L_g^* p), s = sqrt(G), b = lambda s:
@@ -65,6 +71,8 @@ typedef struct {
     double tau, sigma;
     double time_unit_us;   /* T_s; 0 = flat manifold */
     double u_init;
+    int32_t tvl1_iters;    /* timestamp denoising iterations; 0 = off */
+    double tvl1_lambda;    /* its L1 data weight */
 } orc_params;
 
 typedef struct {
@@ -166,6 +174,43 @@ void orc_project(double* q1, double* q2, double* q3, double s) {
     *q3 /= m;
 }
 
+/* TV-L1 denoising of an image f by Chambolle-Pock (2011):
+ *   v_{k+1} = prox(v_k + s div q_k),  prox(w) = f + shrink(w - f, s lambda)
+ *   q_{k+1} = q / max(1, |q|) with q = q_k + s grad(2 v_{k+1} - v_k)
+ * with s = 1/sqrt(8) (||grad||^2 <= 8), v_0 = f, q_0 = 0. */
+void orc_tvl1(int W, int H, const double* f, int iters, double lambda, double* v) {
+    const size_t n = (size_t)W * H;
+    const double s = 1.0 / sqrt(8.0);
+    double* qx = (double*)calloc(n, sizeof(double));
+    double* qy = (double*)calloc(n, sizeof(double));
+    double* d = (double*)malloc(sizeof(double) * n);
+    double* vn = (double*)malloc(sizeof(double) * n);
+    double* vb = (double*)malloc(sizeof(double) * n);
+    double* gx = (double*)malloc(sizeof(double) * n);
+    double* gy = (double*)malloc(sizeof(double) * n);
+    for (size_t k = 0; k < n; ++k) v[k] = f[k];
+    for (int it = 0; it < iters; ++it) {
+        orc_div(W, H, qx, qy, d);
+        for (size_t k = 0; k < n; ++k) {
+            double w = v[k] + s * d[k] - f[k];
+            double t = s * lambda;
+            double r = w > t ? w - t : (w < -t ? w + t : 0.0);
+            vn[k] = f[k] + r;
+            vb[k] = 2.0 * vn[k] - v[k];
+        }
+        orc_grad(W, H, vb, gx, gy);
+        for (size_t k = 0; k < n; ++k) {
+            double a = qx[k] + s * gx[k], b = qy[k] + s * gy[k];
+            double m = sqrt(a * a + b * b);
+            if (m < 1.0) m = 1.0;
+            qx[k] = a / m;
+            qy[k] = b / m;
+            v[k] = vn[k];
+        }
+    }
+    free(qx); free(qy); free(d); free(vn); free(vb); free(gx); free(gy);
+}
+
 /* ------------------------------------------------------------------ */
 /* State                                                               */
 /* ------------------------------------------------------------------ */
@@ -179,6 +224,8 @@ int orc_check_params(const orc_params* P) {
     if (!(P->tau > 0.0) || !(P->sigma > 0.0)) return ORC_EINVAL;
     if (!(P->time_unit_us >= 0.0) || !isfinite(P->time_unit_us)) return ORC_EINVAL;
     if (!(P->u_init > 0.0) || !isfinite(P->u_init)) return ORC_EINVAL;
+    if (P->tvl1_iters < 0) return ORC_EINVAL;
+    if (P->tvl1_iters > 0 && !(P->tvl1_lambda > 0.0)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -273,7 +320,28 @@ void orc_build(orc_state* S) {
         for (int j = 0; j < W; ++j) {
             size_t k = (size_t)i * W + j;
             int64_t tl = S->t_last[k] == ORC_NEVER ? S->t_first : S->t_last[k];
-            double tau = (Ts > 0.0) ? (double)(S->t_ref - tl) / Ts : 0.0;
+            S->tau_s[k] = (Ts > 0.0) ? (double)(S->t_ref - tl) / Ts : 0.0;
+            S->tau32[k] = (float)S->tau_s[k];
+        }
+    if (Ts > 0.0 && S->P.tvl1_iters > 0) {
+        /* denoised surface (Section 4), then plain differences of it */
+        double* v = (double*)malloc(sizeof(double) * S->np);
+        orc_tvl1(W, H, S->tau_s, S->P.tvl1_iters, S->P.tvl1_lambda, v);
+        for (int i = 0; i < H; ++i)
+            for (int j = 0; j < W; ++j) {
+                size_t k = (size_t)i * W + j;
+                S->tx[k] = (j < W - 1) ? v[k + 1] - v[k] : 0.0;
+                S->ty[k] = (i < H - 1) ? v[k + W] - v[k] : 0.0;
+                S->tx32[k] = (float)S->tx[k];
+                S->ty32[k] = (float)S->ty[k];
+            }
+        free(v);
+        return;
+    }
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            size_t k = (size_t)i * W + j;
+            int64_t tl = S->t_last[k] == ORC_NEVER ? S->t_first : S->t_last[k];
             double dx = 0.0, dy = 0.0;
             if (Ts > 0.0 && j < W - 1) {
                 int64_t tr = S->t_last[k + 1] == ORC_NEVER ? S->t_first : S->t_last[k + 1];
@@ -283,10 +351,8 @@ void orc_build(orc_state* S) {
                 int64_t td = S->t_last[k + W] == ORC_NEVER ? S->t_first : S->t_last[k + W];
                 dy = (double)(tl - td) / Ts;   /* tau(i+1) - tau(i) */
             }
-            S->tau_s[k] = tau;
             S->tx[k] = dx;
             S->ty[k] = dy;
-            S->tau32[k] = (float)tau;
             S->tx32[k] = (float)dx;
             S->ty32[k] = (float)dy;
         }

@@ -52,6 +52,9 @@ struct Planes {
     int8_t* ev_p;
     double* gap_part;       // per-block (gap, energy) partial sums
     double* gap_hist;       // (gap, energy) per sample of the running solve
+    double* tv0;            // timestamp denoising (when enabled): raw surface,
+    double* tv[2];          //   iterate (ping-pong),
+    double* tq;             //   dual field (2 planes)
 };
 
 struct Frame {
@@ -87,10 +90,16 @@ constexpr int kZero = 2;    // reset the scattered event counts of the interior 
 constexpr int kEvents = 4;  // with kBuild: validate and bin the folded events in LDS
 constexpr int kCommit = 8;  // commit the pending stream state of the previous launch
 constexpr int kCounts = 16; // with kBuild: add the scattered event counts
+constexpr int kTimeMem = 32; // with kBuild: tx, ty were written by the timestamp denoising
 
 constexpr int kGapBlock = 256;
 constexpr int kGapHistCap = 4096;
 constexpr int kSmallPush = 4096;   // pushes up to this size use one workgroup
+
+// Storage of p and tx, ty (arithmetic is FP32 in every case).
+constexpr int kStoreF32 = 0;
+constexpr int kStoreBF16 = 1;
+constexpr int kStoreF16 = 2;
 
 // Optional timing events around a launch (recorded by the launch packet).
 struct LaunchEv {
@@ -106,20 +115,25 @@ hipError_t launch_init(const Planes& P, Frame fr, float u_init, bool keep_u, hip
 hipError_t launch_push(const Planes& P, Frame fr, const int64_t* t, const uint16_t* x,
                        const uint16_t* y, const int8_t* pol, int64_t n, hipStream_t s,
                        LaunchEv ev = {});
-hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, hipStream_t s,
-                        LaunchEv ev = {});
+hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool time_mem,
+                        hipStream_t s, LaunchEv ev = {});
+// Timestamp denoising: `iters` TV-L1 iterations on the surface, then tx, ty
+// (in the given storage) from the denoised surface.
+hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
+                       int storage, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
                          LaunchEv ev = {});
 hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts k, int cur, hipStream_t s,
                            LaunchEv ev = {});
 hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts k, BuildConsts bc,
                            const EventSegs& segs, int cur, int iters, int mode, int rows,
-                           int waves, hipStream_t s, LaunchEv ev = {});
-bool fused_shape_supported(int rows, int waves);
+                           int waves, int storage, hipStream_t s, LaunchEv ev = {});
+bool fused_shape_supported(int rows, int waves, int storage);
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, hipStream_t s, LaunchEv ev = {});
+                      int cur, int slot, int storage, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
                              hipStream_t s);
-hipError_t launch_metric_plane(const Planes& P, Frame fr, float* out, hipStream_t s);
+hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s);
+hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s);
 
 }  // namespace rec

@@ -54,6 +54,35 @@ hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Storage of the dual field p and of the time differences tx, ty.  The
+// arithmetic is FP32 in every case; 16-bit forms round on store (RNE) and
+// widen exactly on load.  tx, ty are rounded before use, so every launch
+// of a solve sees the same metric.
+struct StoreF32 {
+    using T = float;
+    static __device__ __forceinline__ float ld(const T* a, size_t k) { return a[k]; }
+    static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = v; }
+    static __device__ __forceinline__ float round(float v) { return v; }
+};
+struct StoreF16 {
+    using T = _Float16;
+    static __device__ __forceinline__ float ld(const T* a, size_t k) { return (float)a[k]; }
+    static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = (_Float16)v; }
+    static __device__ __forceinline__ float round(float v) { return (float)(_Float16)v; }
+};
+struct StoreBF16 {
+    using T = uint16_t;
+    static __device__ __forceinline__ uint16_t enc(float v) {  // round to nearest even
+        uint32_t u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+    static __device__ __forceinline__ float dec(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+    static __device__ __forceinline__ float ld(const T* a, size_t k) { return dec(a[k]); }
+    static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = enc(v); }
+    static __device__ __forceinline__ float round(float v) { return dec(enc(v)); }
+};
+
 // ---------------------------------------------------------------- init
 
 __global__ void k_init(Planes P, size_t np, float u_init, int keep_u) {
@@ -198,7 +227,7 @@ __device__ __forceinline__ void time_diffs(int64_t tl, int64_t tr, int64_t td, b
     }
 }
 
-__global__ void k_build(Planes P, Frame fr, int cur, BuildConsts bc) {
+__global__ void k_build(Planes P, Frame fr, int cur, BuildConsts bc, int time_mem) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     DevState* st = P.st;
@@ -211,6 +240,7 @@ __global__ void k_build(Planes P, Frame fr, int cur, BuildConsts bc) {
     P.f[k] = data_image(P.u[cur][k], P.npos[k], P.nneg[k], bc);
     P.npos[k] = 0;
     P.nneg[k] = 0;
+    if (time_mem) return;  // tx, ty come from the timestamp denoising
     const bool hr = j < fr.W - 1, hd = i < fr.H - 1;
     float dx, dy;
     time_diffs(P.t_last[k], hr ? P.t_last[k + 1] : kNever, hd ? P.t_last[k + fr.W] : kNever, hr,
@@ -254,12 +284,91 @@ __global__ void k_time_plane(Planes P, Frame fr, double ts, float* out) {
     out[k] = ts > 0.0 ? (float)((double)(st->t_ref - tl) / ts) : 0.0f;
 }
 
+template <class S>
 __global__ void k_metric_plane(Planes P, Frame fr, float* out) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
-    const float tx = P.tx[k], ty = P.ty[k];
+    const float tx = S::ld((const typename S::T*)P.tx, k), ty = S::ld((const typename S::T*)P.ty, k);
     out[k] = __builtin_fmaf(tx, tx, __builtin_fmaf(ty, ty, 1.0f));
+}
+
+// Widens n stored values to FP32 (readback of 16-bit planes).
+template <class S>
+__global__ void k_widen(const void* src, float* out, size_t n) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) out[k] = S::ld((const typename S::T*)src, k);
+}
+
+// ---------------------------------------------------------------- timestamp denoising
+
+// Section 4 denoises the timestamps with a few TV-L1 iterations before the
+// manifold is built: Chambolle-Pock for  min_v TV(v) + lambda |v - tau|_1
+// (isotropic forward-difference TV, steps 1/sqrt(8), v_0 = tau, dual 0),
+// in FP64.  tau = (t_ref - t_last) / T_s.
+__global__ void k_tvl1_init(Planes P, Frame fr, double ts) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const DevState* st = P.st;
+    const double t0 = (double)(st->t_ref - resolved_last(P.t_last[k], st->t_first)) / ts;
+    P.tv0[k] = t0;
+    P.tv[0][k] = t0;
+    P.tq[k] = 0.0;
+    P.tq[np + k] = 0.0;
+}
+
+// v+ = tau + shrink(v + s div q - tau, s lambda) into tv[cur ^ 1].
+__global__ void k_tvl1_primal(Planes P, Frame fr, int cur, double lambda) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int j = (int)(k % fr.W), i = (int)(k / fr.W);
+    const double s = 0.35355339059327373;  // 1 / sqrt(8)
+    const double* qx = P.tq;
+    const double* qy = P.tq + np;
+    double d = 0.0;
+    if (j < fr.W - 1) d += qx[k];
+    if (j > 0) d -= qx[k - 1];
+    if (i < fr.H - 1) d += qy[k];
+    if (i > 0) d -= qy[k - fr.W];
+    const double w = P.tv[cur][k] + s * d - P.tv0[k];
+    const double t = s * lambda;
+    const double r = w > t ? w - t : (w < -t ? w + t : 0.0);
+    P.tv[cur ^ 1][k] = P.tv0[k] + r;
+}
+
+// q+ = q / max(1, |q|) with q = q + s grad(2 v+ - v).
+__global__ void k_tvl1_dual(Planes P, Frame fr, int cur) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int j = (int)(k % fr.W), i = (int)(k / fr.W);
+    const double s = 0.35355339059327373;
+    const double* vo = P.tv[cur];
+    const double* vn = P.tv[cur ^ 1];
+    const double b = 2.0 * vn[k] - vo[k];
+    const double gx = j < fr.W - 1 ? (2.0 * vn[k + 1] - vo[k + 1]) - b : 0.0;
+    const double gy = i < fr.H - 1 ? (2.0 * vn[k + fr.W] - vo[k + fr.W]) - b : 0.0;
+    const double a = P.tq[k] + s * gx, c = P.tq[np + k] + s * gy;
+    double m = sqrt(a * a + c * c);
+    if (m < 1.0) m = 1.0;
+    P.tq[k] = a / m;
+    P.tq[np + k] = c / m;
+}
+
+// tx, ty = forward differences of the denoised surface, rounded once.
+template <class S>
+__global__ void k_tvl1_finish(Planes P, Frame fr, int cur) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    const int j = (int)(k % fr.W), i = (int)(k / fr.W);
+    const double* v = P.tv[cur];
+    const float dx = j < fr.W - 1 ? (float)(v[k + 1] - v[k]) : 0.0f;
+    const float dy = i < fr.H - 1 ? (float)(v[k + fr.W] - v[k]) : 0.0f;
+    S::st((typename S::T*)P.tx, k, dx);
+    S::st((typename S::T*)P.ty, k, dy);
 }
 
 // ---------------------------------------------------------------- plain loop
@@ -431,7 +540,7 @@ __device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int
 //   (dynamic LDS); with kCounts the scattered counts are added.
 // mode & kZero: resets the scattered counts of the interior at the end.
 // mode & kCommit: block 0 commits the pending stream state.
-template <int R, int NW>
+template <int R, int NW, class S>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
                                                       BuildConsts bc, EventSegs segs, int cur,
                                                       int K, int mode, int tiles_x, int ntiles) {
@@ -447,7 +556,9 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     const int gy0 = ry0 + wave * R;
     const size_t np = (size_t)fr.W * fr.H;
     const float* __restrict__ uin = P.u[cur];
-    const float* __restrict__ pin = P.p[cur];
+    const typename S::T* __restrict__ pin = (const typename S::T*)P.p[cur];
+    typename S::T* __restrict__ txs = (typename S::T*)P.tx;
+    typename S::T* __restrict__ tys = (typename S::T*)P.ty;
 
     if ((mode & kCommit) && blockIdx.x == 0 && threadIdx.x == 0) commit_pending(P.st);
 
@@ -482,9 +593,9 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
         if (in) {
             const size_t k = (size_t)gy * fr.W + gx;
             uu = uin[k];
-            a = pin[k];
-            b = pin[np + k];
-            d = pin[2 * np + k];
+            a = S::ld(pin, k);
+            b = S::ld(pin, np + k);
+            d = S::ld(pin, 2 * np + k);
             if (build) {
                 const int lr = wave * R + r;
                 const bool hr = gx < fr.W - 1, hd = gy < fr.H - 1;
@@ -504,17 +615,26 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
                     td = max(td, (int64_t)tb.tmax[(lr + 1) * 65 + lane]);
                 }
                 f = data_image(uu, npos, nneg, bc);
-                time_diffs(tl, tr, td, hr, hd, tb.t_first, bc, tx, ty);
+                if (mode & kTimeMem) {
+                    tx = S::ld(txs, k);
+                    ty = S::ld(tys, k);
+                } else {
+                    time_diffs(tl, tr, td, hr, hd, tb.t_first, bc, tx, ty);
+                    tx = S::round(tx);
+                    ty = S::round(ty);
+                }
                 if (col_out && lr >= K && lr < RH - K) {
                     P.f[k] = f;
-                    P.tx[k] = tx;
-                    P.ty[k] = ty;
+                    if (!(mode & kTimeMem)) {
+                        S::st(txs, k, tx);
+                        S::st(tys, k, ty);
+                    }
                     if (mode & kEvents) P.t_last[k] = tl;
                 }
             } else {
                 f = P.f[k];
-                tx = P.tx[k];
-                ty = P.ty[k];
+                tx = S::ld(txs, k);
+                ty = S::ld(tys, k);
             }
         }
         u[r] = uu;
@@ -565,7 +685,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     }
 
     float* __restrict__ uout = P.u[cur ^ 1];
-    float* __restrict__ pout = P.p[cur ^ 1];
+    typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = wave * R + r;
@@ -573,9 +693,9 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
         if (col_out && row >= K && row < RH - K && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
             uout[k] = u[r];
-            pout[k] = p1[r];
-            pout[np + k] = p2[r];
-            pout[2 * np + k] = p3[r];
+            S::st(pout, k, p1[r]);
+            S::st(pout, np + k, p2[r]);
+            S::st(pout, 2 * np + k, p3[r]);
             if (mode & kZero) {
                 P.npos[k] = 0;
                 P.nneg[k] = 0;
@@ -597,6 +717,7 @@ __device__ __forceinline__ double warp_sum(double v) {
 //   term2 = (u - v)(b + d) - b f log(u / v),  d = L_g^* p, b = lambda s,
 //           v = clamp(b f / (b + d)) if b + d > 0 else u_max
 //   energy = s |A| + b (u - f log u)
+template <class S>
 __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double lambda,
                                                    double umin, double umax, int cur) {
     const size_t np = (size_t)fr.W * fr.H;
@@ -605,15 +726,17 @@ __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double la
     if (k < np) {
         const int j = (int)(k % fr.W), i = (int)(k / fr.W);
         const float* u = P.u[cur];
-        const float* p = P.p[cur];
+        const typename S::T* p = (const typename S::T*)P.p[cur];
+        const typename S::T* txs = (const typename S::T*)P.tx;
+        const typename S::T* tys = (const typename S::T*)P.ty;
         auto qxy = [&](size_t kk, double& qx, double& qy) {
-            const double tx = P.tx[kk], ty = P.ty[kk];
+            const double tx = S::ld(txs, kk), ty = S::ld(tys, kk);
             const double G = 1.0 + tx * tx + ty * ty;
-            const double a = p[kk], b = p[np + kk], d = p[2 * np + kk];
+            const double a = S::ld(p, kk), b = S::ld(p, np + kk), d = S::ld(p, 2 * np + kk);
             qx = ((1.0 + ty * ty) * a - tx * ty * b + tx * d) / G;
             qy = (-tx * ty * a + (1.0 + tx * tx) * b + ty * d) / G;
         };
-        const double tx = P.tx[k], ty = P.ty[k];
+        const double tx = S::ld(txs, k), ty = S::ld(tys, k);
         const double G = 1.0 + tx * tx + ty * ty;
         const double s = sqrt(G);
         const double uk = u[k];
@@ -623,7 +746,8 @@ __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double la
         const double A2 = ((1.0 + tx * tx) * uy - tx * ty * ux) / G;
         const double A3 = (tx * ux + ty * uy) / G;
         const double nA = sqrt(A1 * A1 + A2 * A2 + A3 * A3);
-        const double t1 = s * nA - (A1 * p[k] + A2 * p[np + k] + A3 * p[2 * np + k]);
+        const double t1 =
+            s * nA - (A1 * S::ld(p, k) + A2 * S::ld(p, np + k) + A3 * S::ld(p, 2 * np + k));
         double qx, qy, qxl = 0.0, qyu = 0.0, dummy;
         qxy(k, qx, qy);
         if (j > 0) qxy(k - 1, qxl, dummy);
@@ -683,7 +807,7 @@ __global__ __launch_bounds__(256) void k_gap_final(Planes P, size_t nblocks, int
     }
 }
 
-template <int R, int NW>
+template <int R, int NW, class S>
 hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
                         const EventSegs& segs, int cur, int K, int mode, hipStream_t s,
                         LaunchEv ev) {
@@ -692,7 +816,7 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
     const int tiles_x = (fr.W + OW - 1) / OW;
     const int tiles_y = (fr.H + OH - 1) / OH;
     const int ntiles = tiles_x * tiles_y;
-    return launch(k_pd_fused<R, NW>, dim3(ntiles), dim3(64 * NW), fused_lds_bytes(R, NW, mode), s,
+    return launch(k_pd_fused<R, NW, S>, dim3(ntiles), dim3(64 * NW), fused_lds_bytes(R, NW, mode), s,
                   ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
 }
 
@@ -736,11 +860,30 @@ hipError_t launch_push(const Planes& P, Frame fr, const int64_t* t, const uint16
     return e;
 }
 
-hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, hipStream_t s,
-                        LaunchEv ev) {
+hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool time_mem,
+                        hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     return launch(k_build, dim3(blocks_for(np, 256)), dim3(256), 0, s, ev.start, ev.stop, P, fr,
-                  cur, bc);
+                  cur, bc, time_mem ? 1 : 0);
+}
+
+hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
+                       int storage, hipStream_t s, LaunchEv ev) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const dim3 g(blocks_for(np, 256)), b(256);
+    hipError_t e = launch(k_tvl1_init, g, b, 0, s, ev.start, nullptr, P, fr, ts);
+    int cur = 0;
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        e = launch(k_tvl1_primal, g, b, 0, s, nullptr, nullptr, P, fr, cur, lambda);
+        if (e == hipSuccess) e = launch(k_tvl1_dual, g, b, 0, s, nullptr, nullptr, P, fr, cur);
+        cur ^= 1;
+    }
+    if (e != hipSuccess) return e;
+    if (storage == kStoreF16)
+        return launch(k_tvl1_finish<StoreF16>, g, b, 0, s, nullptr, ev.stop, P, fr, cur);
+    if (storage == kStoreBF16)
+        return launch(k_tvl1_finish<StoreBF16>, g, b, 0, s, nullptr, ev.stop, P, fr, cur);
+    return launch(k_tvl1_finish<StoreF32>, g, b, 0, s, nullptr, ev.stop, P, fr, cur);
 }
 
 hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
@@ -759,8 +902,11 @@ hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hi
     return e;
 }
 
-bool fused_shape_supported(int rows, int waves) {
-    switch (rows * 100 + waves) {
+bool fused_shape_supported(int rows, int waves, int storage) {
+    const int key = rows * 100 + waves;
+    if (storage != kStoreF32)
+        return key == 216 || key == 416 || key == 804 || key == 808 || key == 408;
+    switch (key) {
         case 202: case 204: case 208: case 216:
         case 401: case 402: case 404: case 408: case 416:
         case 801: case 802: case 804: case 808:
@@ -771,36 +917,62 @@ bool fused_shape_supported(int rows, int waves) {
     }
 }
 
+#define REC_FUSED_CASE(R, NW) \
+    case R * 100 + NW: return fused_launch<R, NW, StoreF32>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+#define REC_FUSED_CASE16(R, NW)                                                                   \
+    case R * 100 + NW:                                                                           \
+        return storage == kStoreF16                                                              \
+                   ? fused_launch<R, NW, StoreF16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev)  \
+                   : fused_launch<R, NW, StoreBF16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+
 hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
                            const EventSegs& segs, int cur, int iters, int mode, int rows,
-                           int waves, hipStream_t s, LaunchEv ev) {
+                           int waves, int storage, hipStream_t s, LaunchEv ev) {
+    if (!fused_shape_supported(rows, waves, storage)) return hipErrorInvalidValue;
+    if (storage != kStoreF32) {
+        switch (rows * 100 + waves) {
+            REC_FUSED_CASE16(2, 16)
+            REC_FUSED_CASE16(4, 16)
+            REC_FUSED_CASE16(4, 8)
+            REC_FUSED_CASE16(8, 4)
+            REC_FUSED_CASE16(8, 8)
+            default: return hipErrorInvalidValue;
+        }
+    }
     switch (rows * 100 + waves) {
-        case 202: return fused_launch<2, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 204: return fused_launch<2, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 208: return fused_launch<2, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 216: return fused_launch<2, 16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 401: return fused_launch<4, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 402: return fused_launch<4, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 404: return fused_launch<4, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 408: return fused_launch<4, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 416: return fused_launch<4, 16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 801: return fused_launch<8, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 802: return fused_launch<8, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 804: return fused_launch<8, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 808: return fused_launch<8, 8>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 1601: return fused_launch<16, 1>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 1602: return fused_launch<16, 2>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-        case 1604: return fused_launch<16, 4>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+        REC_FUSED_CASE(2, 2)
+        REC_FUSED_CASE(2, 4)
+        REC_FUSED_CASE(2, 8)
+        REC_FUSED_CASE(2, 16)
+        REC_FUSED_CASE(4, 1)
+        REC_FUSED_CASE(4, 2)
+        REC_FUSED_CASE(4, 4)
+        REC_FUSED_CASE(4, 8)
+        REC_FUSED_CASE(4, 16)
+        REC_FUSED_CASE(8, 1)
+        REC_FUSED_CASE(8, 2)
+        REC_FUSED_CASE(8, 4)
+        REC_FUSED_CASE(8, 8)
+        REC_FUSED_CASE(16, 1)
+        REC_FUSED_CASE(16, 2)
+        REC_FUSED_CASE(16, 4)
         default: return hipErrorInvalidValue;
     }
 }
+#undef REC_FUSED_CASE
+#undef REC_FUSED_CASE16
 
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, hipStream_t s, LaunchEv ev) {
+                      int cur, int slot, int storage, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t nb = gap_blocks(np);
-    hipError_t e = launch(k_gap, dim3((unsigned)nb), dim3(kGapBlock), 0, s, ev.start, nullptr, P,
-                          fr, lambda, umin, umax, cur);
+    const dim3 g((unsigned)nb), b(kGapBlock);
+    hipError_t e =
+        storage == kStoreF16
+            ? launch(k_gap<StoreF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur)
+        : storage == kStoreBF16
+            ? launch(k_gap<StoreBF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur)
+            : launch(k_gap<StoreF32>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur);
     if (e == hipSuccess)
         e = launch(k_gap_final, dim3(1), dim3(256), 0, s, nullptr, ev.stop, P, nb, slot);
     return e;
@@ -813,10 +985,23 @@ hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, flo
                   fr, time_unit_us, out);
 }
 
-hipError_t launch_metric_plane(const Planes& P, Frame fr, float* out, hipStream_t s) {
+hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s) {
     const size_t np = (size_t)fr.W * fr.H;
-    return launch(k_metric_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P,
-                  fr, out);
+    const dim3 g(blocks_for(np, 256)), b(256);
+    if (storage == kStoreF16)
+        return launch(k_metric_plane<StoreF16>, g, b, 0, s, nullptr, nullptr, P, fr, out);
+    if (storage == kStoreBF16)
+        return launch(k_metric_plane<StoreBF16>, g, b, 0, s, nullptr, nullptr, P, fr, out);
+    return launch(k_metric_plane<StoreF32>, g, b, 0, s, nullptr, nullptr, P, fr, out);
+}
+
+hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s) {
+    const dim3 g(blocks_for(n, 256)), b(256);
+    if (storage == kStoreF16)
+        return launch(k_widen<StoreF16>, g, b, 0, s, nullptr, nullptr, src, out, n);
+    if (storage == kStoreBF16)
+        return launch(k_widen<StoreBF16>, g, b, 0, s, nullptr, nullptr, src, out, n);
+    return launch(k_widen<StoreF32>, g, b, 0, s, nullptr, nullptr, src, out, n);
 }
 
 }  // namespace rec

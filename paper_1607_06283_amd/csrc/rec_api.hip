@@ -61,6 +61,11 @@ size_t carve(const rec_params* prm, char* base, Planes* P) {
     q.ev_p = (int8_t*)take(ne);
     q.gap_part = (double*)take(rec::gap_blocks(np) * 2 * sizeof(double));
     q.gap_hist = (double*)take((size_t)rec::kGapHistCap * 2 * sizeof(double));
+    const size_t nt = prm->tvl1_iters > 0 ? np : 0;  // denoising planes only when enabled
+    q.tv0 = (double*)take(nt * 8);
+    q.tv[0] = (double*)take(nt * 8);
+    q.tv[1] = (double*)take(nt * 8);
+    q.tq = (double*)take(2 * nt * 8);
     if (P) *P = q;
     return align_up(off);
 }
@@ -245,6 +250,9 @@ void rec_default_params(rec_params* prm, int32_t width, int32_t height) {
     prm->max_events = 65536;
     prm->tile_rows = 0;
     prm->tile_waves = 0;
+    prm->storage = REC_STORE_F32;
+    prm->tvl1_iters = 0;
+    prm->tvl1_lambda = 1.0;
 }
 
 int rec_check_params(const rec_params* prm) {
@@ -262,10 +270,17 @@ int rec_check_params(const rec_params* prm) {
     if (prm->iters < 0 || prm->gap_every < 0) return REC_EINVAL;
     if (prm->fuse_iters < -1 || prm->fuse_iters > 31) return REC_EINVAL;
     if (prm->max_events < 1 || prm->max_events > (1 << 28)) return REC_EINVAL;
-    if ((prm->tile_rows == 0) != (prm->tile_waves == 0)) return REC_EINVAL;
-    if (prm->tile_rows && !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves))
+    if (prm->storage != REC_STORE_F32 && prm->storage != REC_STORE_BF16 &&
+        prm->storage != REC_STORE_F16)
         return REC_EINVAL;
-    for (int i = 0; i < 6; ++i)
+    if (prm->storage != REC_STORE_F32 && prm->fuse_iters == 0) return REC_EINVAL;
+    if (prm->tvl1_iters < 0 || prm->tvl1_iters > 10000) return REC_EINVAL;
+    if (prm->tvl1_iters > 0 && !finite_pos(prm->tvl1_lambda)) return REC_EINVAL;
+    if ((prm->tile_rows == 0) != (prm->tile_waves == 0)) return REC_EINVAL;
+    if (prm->tile_rows &&
+        !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves, prm->storage))
+        return REC_EINVAL;
+    for (int i = 0; i < 4; ++i)
         if (prm->reserved[i] != 0) return REC_EINVAL;
     return REC_OK;
 }
@@ -427,11 +442,12 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
     const int64_t np = (int64_t)c->fr.W * c->fr.H;
     const rec::BuildConsts bc{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
     const bool fused = c->prm.fuse_iters != 0 && iters > 0;
+    const bool denoise = c->prm.tvl1_iters > 0 && c->prm.time_unit_us > 0.0;
     int rc;
     rec::EventSegs segs;
     memset(&segs, 0, sizeof(segs));
     bool fold = false;
-    if (fused && !c->deferred.empty()) {
+    if (fused && !denoise && !c->deferred.empty()) {
         const int first_k = iters < c->kmax ? iters : c->kmax;
         const int64_t tiles = rec::fused_tiles(c->fr, c->rows, c->waves, first_k);
         fold = c->deferred_events <= kFoldMaxEvents && tiles > 0 &&
@@ -452,9 +468,17 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
         rc = flush_deferred(c);
         if (rc) return rc;
     }
+    if (denoise) {
+        // the denoised surface needs every timestamp of the block first
+        rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
+            return rec::launch_tvl1(c->P, c->fr, c->prm.time_unit_us, c->prm.tvl1_iters,
+                                    c->prm.tvl1_lambda, c->prm.storage, c->stream, ev);
+        });
+        if (rc) return rc;
+    }
     if (!fused) {
         rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
-            return rec::launch_build(c->P, c->fr, c->cur, bc, c->stream, ev);
+            return rec::launch_build(c->P, c->fr, c->cur, bc, denoise, c->stream, ev);
         });
         if (rc) return rc;
         c->counts_dirty = false;
@@ -482,12 +506,13 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
                 const int m = seg / nl + (q < seg % nl ? 1 : 0);
                 int mode = 0;
                 if (launch == 0)
-                    mode = rec::kBuild | (fold ? rec::kEvents : 0) | (counts ? rec::kCounts : 0);
+                    mode = rec::kBuild | (fold ? rec::kEvents : 0) | (counts ? rec::kCounts : 0) |
+                           (denoise ? rec::kTimeMem : 0);
                 else if (launch == 1)
                     mode = rec::kCommit | (counts ? rec::kZero : 0);
                 rc = timed(c, 2, np * m, [&](rec::LaunchEv ev) {
                     return rec::launch_pd_fused(c->P, c->fr, c->kc, bc, segs, c->cur, m, mode,
-                                                c->rows, c->waves, c->stream, ev);
+                                                c->rows, c->waves, c->prm.storage, c->stream, ev);
                 });
                 if (rc) return rc;
                 c->cur ^= 1;
@@ -507,7 +532,7 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
             const int slot = samples < rec::kGapHistCap ? samples : rec::kGapHistCap - 1;
             rc = timed(c, 3, np, [&](rec::LaunchEv ev) {
                 return rec::launch_gap(c->P, c->fr, c->prm.lambda, c->prm.u_min, c->prm.u_max,
-                                       c->cur, slot, c->stream, ev);
+                                       c->cur, slot, c->prm.storage, c->stream, ev);
             });
             if (rc) return rc;
             ++samples;
@@ -550,12 +575,27 @@ int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
     hipError_t e = hipSuccess;
     // derived planes go through a spare ping-pong buffer unless written in place
     float* spare = c->P.u[c->cur ^ 1];
+    float* spare3 = c->P.p[c->cur ^ 1];  // 3 planes, FP32-sized whatever the storage
+    const bool narrow = c->prm.storage != REC_STORE_F32;
     switch (which) {
         case REC_U: src = c->P.u[c->cur]; break;
         case REC_F: src = c->P.f; break;
-        case REC_TX: src = c->P.tx; break;
-        case REC_TY: src = c->P.ty; break;
-        case REC_STATE_P: src = c->P.p[c->cur]; bytes = 3 * np * 4; break;
+        case REC_TX:
+        case REC_TY:
+        case REC_STATE_P: {
+            const void* raw = which == REC_TX ? (const void*)c->P.tx
+                            : which == REC_TY ? (const void*)c->P.ty : (const void*)c->P.p[c->cur];
+            const size_t n = which == REC_STATE_P ? 3 * np : np;
+            bytes = n * 4;
+            if (!narrow) {
+                src = raw;
+                break;
+            }
+            float* dst = on_device ? (float*)out : (which == REC_STATE_P ? spare3 : spare);
+            e = rec::launch_widen(raw, c->prm.storage, dst, n, c->stream);
+            src = on_device ? nullptr : dst;
+            break;
+        }
         case REC_COUNT_POS: src = c->P.npos; break;
         case REC_COUNT_NEG: src = c->P.nneg; break;
         case REC_T_LAST: src = c->P.t_last; bytes = np * 8; break;
@@ -567,7 +607,7 @@ int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
         }
         case REC_METRIC_G: {
             float* dst = on_device ? (float*)out : spare;
-            e = rec::launch_metric_plane(c->P, c->fr, dst, c->stream);
+            e = rec::launch_metric_plane(c->P, c->fr, c->prm.storage, dst, c->stream);
             src = on_device ? nullptr : spare;
             break;
         }

@@ -25,6 +25,8 @@ REC_OK, REC_EINVAL, REC_ERANGE, REC_EORDER, REC_EDEVICE, REC_ENUMERIC, REC_ESTAT
 (REC_U, REC_F, REC_TIME, REC_METRIC_G, REC_STATE_P, REC_TX, REC_TY, REC_COUNT_POS,
  REC_COUNT_NEG, REC_T_LAST) = range(10)
 
+REC_STORE_F32, REC_STORE_BF16, REC_STORE_F16 = 0, 1, 2
+
 _PLANE_DTYPE = {REC_COUNT_POS: np.int32, REC_COUNT_NEG: np.int32, REC_T_LAST: np.int64}
 
 
@@ -43,7 +45,10 @@ class rec_params(ctypes.Structure):
         ("max_events", ctypes.c_int32),
         ("tile_rows", ctypes.c_int32),
         ("tile_waves", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 6),
+        ("storage", ctypes.c_int32),
+        ("tvl1_iters", ctypes.c_int32),
+        ("tvl1_lambda", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 

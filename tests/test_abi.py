@@ -28,9 +28,10 @@ def test_exports_match_header():
 
 
 def test_struct_sizes_match_header_layout():
-    # rec_params: 2 int32, 9 double, 6 int32, 6 int32 reserved = 8 + 72 + 24 + 24
+    # rec_params: 2 int32, 9 double, 8 int32, 1 double, 4 int32 reserved
     import ctypes
-    assert ctypes.sizeof(rec.rec_params) == 128
+    assert ctypes.sizeof(rec.rec_params) == 136
+    assert rec.rec_params.tvl1_lambda.offset == 112
     assert ctypes.sizeof(rec.rec_stats) == 40
     assert ctypes.sizeof(rec.rec_profile_t) == 72
 
@@ -51,6 +52,7 @@ def test_default_params():
     ("delta_pos", -0.1), ("u_min", 0.0), ("u_max", 0.5), ("tau", 0.6), ("sigma", 0.0),
     ("time_unit_us", -1.0), ("time_unit_us", float("inf")), ("u_init", 0.0), ("iters", -1),
     ("gap_every", -2), ("fuse_iters", 40), ("max_events", 0), ("tile_rows", 3),
+    ("storage", 3), ("storage", -1), ("tvl1_iters", -1), ("tvl1_iters", 20000),
 ])
 def test_bad_params_rejected(field, value):
     p = rec.rec_default_params(64, 48)
@@ -59,6 +61,33 @@ def test_bad_params_rejected(field, value):
         p.tile_waves = 4
     assert rec.rec_check_params(p) == rec.REC_EINVAL
     assert rec.rec_workspace_bytes(p) == 0
+
+
+def test_reduced_storage_needs_fused_loop():
+    p = rec.rec_default_params(64, 48)
+    for st in (rec.REC_STORE_BF16, rec.REC_STORE_F16):
+        p.storage = st
+        p.fuse_iters = -1
+        assert rec.rec_check_params(p) == rec.REC_OK
+        p.fuse_iters = 0
+        assert rec.rec_check_params(p) == rec.REC_EINVAL
+        p.fuse_iters = -1
+        p.tile_rows, p.tile_waves = 16, 4   # no 16-bit variant of this tile
+        assert rec.rec_check_params(p) == rec.REC_EINVAL
+        p.tile_rows, p.tile_waves = 4, 16
+        assert rec.rec_check_params(p) == rec.REC_OK
+        p.tile_rows, p.tile_waves = 0, 0
+
+
+def test_denoising_params():
+    p = rec.rec_default_params(32, 32)
+    assert p.tvl1_iters == 0 and p.tvl1_lambda == 1.0
+    p.tvl1_iters = 5
+    assert rec.rec_check_params(p) == rec.REC_OK
+    base = rec.rec_workspace_bytes(rec.rec_default_params(32, 32))
+    assert rec.rec_workspace_bytes(p) >= base + 5 * 8 * 32 * 32  # FP64 planes only when on
+    p.tvl1_lambda = 0.0
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
 
 
 def test_step_size_bound():

@@ -357,3 +357,86 @@ def test_many_pushes_per_solve(c1):
     assert st.events_in_batch == 700 and st.t_ref_us == o.t_ref
     assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
     assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
+
+
+# --------------------------------------------------------------------------
+# Reduced-precision storage of p and (tx, ty), FP32 arithmetic
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage,bound", [(rec.REC_STORE_F16, 2e-3), (rec.REC_STORE_BF16, 2e-2)])
+def test_reduced_storage_error_vs_oracle(c1, storage, bound):
+    """16-bit storage of the dual field and the time differences: the error
+    against the FP64 oracle after every block of the 128x128 stream stays
+    below the stated bound (FP16 2e-3, BF16 2e-2 max-abs on u in [1, e])."""
+    r, o = make(128, 128, storage=storage)
+    worst = 0.0
+    for b in evgen.batches(c1.events, 500)[:20]:
+        r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(50)
+        o.solve(50)
+        worst = max(worst, float(np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max()))
+    print(f"storage={storage} max-abs error vs FP64 oracle over 20 blocks: {worst:.3e}")
+    assert worst <= bound
+
+
+@pytest.mark.parametrize("storage", [rec.REC_STORE_F16, rec.REC_STORE_BF16])
+def test_reduced_storage_tile_independent(storage):
+    """With the same iterations per launch, the 16-bit form gives the same
+    bits whatever the tile shape (rounding happens only at launch ends)."""
+    W, H = 150, 97
+    t, x, y, p = _random_stream(W, H, 4000, seed=77)
+    outs = []
+    for rows, waves in [(2, 16), (4, 16), (4, 8), (8, 4), (8, 8)]:
+        r = rec.Reconstructor(W, H, storage=storage, fuse_iters=6, tile_rows=rows, tile_waves=waves)
+        for a in range(0, 4000, 1000):
+            r.push(*device_events(evgen.Events(t[a:a + 1000], x[a:a + 1000], y[a:a + 1000],
+                                               p[a:a + 1000], np.zeros(1000, np.uint8))),
+                   on_device=True)
+            r.solve(31)
+        outs.append((r.image(rec.REC_U), r.image(rec.REC_STATE_P), r.image(rec.REC_TX)))
+        r.close()
+    for u, pp, tx in outs[1:]:
+        assert np.array_equal(u, outs[0][0])
+        assert np.array_equal(pp, outs[0][1])
+        assert np.array_equal(tx, outs[0][2])
+
+
+# --------------------------------------------------------------------------
+# Timestamp denoising (TV-L1 before the metric, Section 4)
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def noisy():
+    spec = evgen.StreamSpec(96, 72, 21, duration_us=60_000, speed_px_s=400.0, omega_rad_s=3.0,
+                            noise_frac=0.05)
+    return evgen.generate(spec).events
+
+
+@pytest.mark.parametrize("fuse", [-1, 0])
+def test_denoised_time_differences_and_image(noisy, fuse):
+    r, o = make(96, 72, tvl1_iters=5, tvl1_lambda=1.0, fuse_iters=fuse)
+    n = len(noisy)
+    for a in range(0, n - n % 4, n // 4):
+        b = noisy.slice(a, a + n // 4)
+        r.push(*device_events(b), on_device=True)
+        o.push_events(b)
+        r.solve(50)
+        o.solve(50)
+        tx, ty = r.image(rec.REC_TX), r.image(rec.REC_TY)
+        assert np.allclose(tx, o.get(oracle.TX32), rtol=1e-6, atol=1e-9)
+        assert np.allclose(ty, o.get(oracle.TY32), rtol=1e-6, atol=1e-9)
+        assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
+
+
+def test_denoising_flattens_noise_spikes(noisy):
+    """Uniform noise events put isolated, out-of-sequence timestamps into the
+    surface; the denoised surface has far fewer large time differences."""
+    raw = rec.Reconstructor(96, 72)
+    den = rec.Reconstructor(96, 72, tvl1_iters=50, tvl1_lambda=1.0)
+    for r in (raw, den):
+        r.push(noisy.t, noisy.x, noisy.y, noisy.p)
+        r.solve(1)
+    big_raw = (np.abs(raw.image(rec.REC_TX)) > 5.0).sum()
+    big_den = (np.abs(den.image(rec.REC_TX)) > 5.0).sum()
+    assert big_den < 0.5 * big_raw
