@@ -266,3 +266,31 @@ def hd720(seed: int = 3, duration_us: int = 500_000, rate: float = 2e7):
     spec = calibrate(base, rate, pilot_us=20_000)
     s = generate(dataclasses.replace(spec, duration_us=duration_us))
     return s, 20000, (len(s.events) + 19999) // 20000, 100
+
+
+def diff_inputs(seed: int, batch: int, height: int, width: int, iters_hint: int = 0) -> dict:
+    """Random inputs of the differentiable unrolled solve (no method
+    arithmetic here): a smooth initial image u0 inside (1, e), small signed
+    event counts, a smooth time-surface slope field (tx, ty) with a little
+    noise, and data weights w around 1.  Float planes are float32 so the GPU
+    and the FP64 references see identical values.  Shapes [batch, H, W]."""
+    rng = np.random.default_rng(seed)
+    yy, xx = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
+    def smooth(lo, hi, waves=3):
+        acc = np.zeros((batch, height, width))
+        for b in range(batch):
+            for _ in range(waves):
+                kx, ky = rng.uniform(-0.35, 0.35, 2)
+                ph = rng.uniform(0, 2 * np.pi)
+                acc[b] += np.sin(kx * xx + ky * yy + ph)
+        acc = (acc - acc.min()) / max(acc.max() - acc.min(), 1e-12)
+        return lo + (hi - lo) * acc
+    u0 = np.exp(smooth(0.25, 0.75)).astype(np.float32)
+    fired = rng.random((batch, height, width)) < 0.3
+    npos = np.where(fired & (rng.random(fired.shape) < 0.5), rng.integers(1, 4, fired.shape), 0)
+    nneg = np.where(fired & (npos == 0), rng.integers(1, 4, fired.shape), 0)
+    tx = (smooth(-1.5, 1.5) + 0.05 * rng.standard_normal(fired.shape)).astype(np.float32)
+    ty = (smooth(-1.5, 1.5) + 0.05 * rng.standard_normal(fired.shape)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, fired.shape).astype(np.float32)
+    return {"u0": u0, "npos": npos.astype(np.int32), "nneg": nneg.astype(np.int32),
+            "tx": tx, "ty": ty, "w": w}

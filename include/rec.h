@@ -208,6 +208,126 @@ int rec_destroy(rec_ctx* c);
 /* Static description of a status code. */
 const char* rec_strerror(int code);
 
+/* ---------------------------------------------------------------------
+ * Batched solves.  Many independent streams (cameras of different sizes
+ * and event rates) are solved together: every launch of a batched solve
+ * covers the tiles of all streams, so a solve costs ceil(iters / K)
+ * launches for the whole batch instead of per stream.  Results are the
+ * same bits as solving each stream alone with the same iterations per
+ * launch.  (Not in the paper, which reconstructs one camera.)
+ * ------------------------------------------------------------------- */
+typedef struct rec_batch rec_batch;
+
+/* Device workspace bytes for a batch of these contexts (0 if invalid). */
+size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n);
+
+/* Group n contexts.  They must share device, stream and storage, use the
+ * fused loop, and have no timestamp denoising and no gap sampling.  The
+ * contexts stay owned by the caller and must outlive the batch.  With
+ * tune_iters > 0 an autotuner times every candidate tile geometry (rows
+ * per lane, wavefronts, iterations per launch) on the streams' current
+ * state without changing it, and keeps the one that runs tune_iters
+ * iterations fastest (synchronises); with 0 the automatic geometry of the
+ * largest stream is used. */
+int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t ws_bytes,
+                   int32_t tune_iters, rec_batch** out);
+
+/* Solve the pending block of every stream of the batch with `iters`
+ * iterations (each stream's pushes since its last solve; a stream without
+ * new events smooths its previous image).  Does not synchronise. */
+int rec_batch_solve(rec_batch* b, int32_t iters);
+
+/* The geometry in use and the autotuner's measured time per launch (us,
+ * 0 when not tuned).  Any output may be NULL. */
+int rec_batch_config(const rec_batch* b, int32_t* rows, int32_t* waves, int32_t* kiters,
+                     double* launch_us);
+
+/* Release the batch (after synchronising its stream).  NULL is a no-op. */
+int rec_batch_destroy(rec_batch* b);
+
+/* -------------------------------------------------------------------
+ * Differentiable unrolled solve (training through the reconstruction).
+ *
+ * Not in the paper: the K primal-dual iterations of Section 3.2 on one
+ * block of data, unrolled as a function of its inputs, with a hand-written
+ * reverse sweep.  For a batch of B images of W x H:
+ *
+ *   f     = u0 * exp(dpos n+ - dneg n-)            (eqn. intensity_update)
+ *   ubar  = u_k - tau L_g^* p_k
+ *   u_k+1 = clamp(prox_{tau D}(ubar), u_min, u_max)  with the data term
+ *           lambda * w * (u - f log u) * sqrt(G) per pixel
+ *   p_k+1 = proj_{|.| <= sqrt(G)}(p_k + sigma L_g (2 u_k+1 - u_k))
+ *
+ * from (u0, p0), with L_g, G from the time differences (tx, ty) (eqn. 3).
+ * w = 1 is the paper's model.  rec_diff_forward returns (u_K, p_K) and keeps
+ * checkpoints of (u, p) every ckpt_every iterations in the workspace;
+ * rec_diff_backward, given dJ/du_K (and optionally dJ/dp_K), recomputes each
+ * segment from its checkpoint and runs the adjoint iterations backwards,
+ * returning dJ/du0 (through u0 and through f), dJ/dp0, dJ/dw and
+ * dJ/d(lambda, dpos, dneg).  The derivative of the clamped prox is zero on
+ * clamped pixels; the projection contributes (s/|q|)(I - q q^T/|q|^2)
+ * where it is active (q the point projected).  Arithmetic is FP32 as in the
+ * forward solve; the scalar gradients are reduced in FP64.
+ *
+ * Layouts (device memory, row-major, x fastest):
+ *   image planes  float / int32 [B][H][W]
+ *   dual fields   float [B][3][H][W]   (the 3 components of p per image)
+ *   theta         double [3] = (lambda, delta_pos, delta_neg), device memory
+ *                 so that it can itself be a trained parameter; lambda > 0
+ *                 and finite deltas are the caller's to ensure.
+ * ------------------------------------------------------------------- */
+typedef struct rec_diff_desc {
+    int32_t width, height;  /* 1..65535 */
+    int32_t batch;          /* images, 1..65535 */
+    int32_t iters;          /* unrolled iterations K >= 0 */
+    int32_t ckpt_every;     /* checkpoint interval, 1..max(K, 1) */
+    int32_t reserved;       /* must be 0 */
+    double tau, sigma;      /* steps: tau sigma (8 + 4 sqrt 2) <= 1 */
+    double u_min, u_max;    /* 0 < u_min < u_max */
+} rec_diff_desc;
+
+typedef struct rec_diff_inputs {
+    const float* u0;        /* initial image and u_prev of f; > 0; required */
+    const float* p0;        /* initial dual field, or NULL for zero */
+    const int32_t* npos;    /* event counts of the block; required */
+    const int32_t* nneg;
+    const float* tx;        /* forward differences of the time surface; required */
+    const float* ty;
+    const float* w;         /* data weights, or NULL for all 1 */
+    const double* theta;    /* (lambda, delta_pos, delta_neg); required */
+} rec_diff_inputs;
+
+typedef struct rec_diff_grads {
+    float* u0;              /* dJ/du0 [B][H][W], or NULL */
+    float* p0;              /* dJ/dp0 [B][3][H][W], or NULL */
+    float* w;               /* dJ/dw [B][H][W], or NULL */
+    double* theta;          /* dJ/d(lambda, delta_pos, delta_neg) [3], or NULL */
+} rec_diff_grads;
+
+/* Device workspace bytes (0 if the descriptor is invalid): the data image,
+ * ceil(K / ckpt_every) + 1 checkpoints and ckpt_every - 1 recomputed states
+ * of 16 bytes per pixel each, and the adjoint planes. */
+size_t rec_diff_workspace_bytes(const rec_diff_desc* d);
+
+/* Forward: (u_K, p_K) into u_out [B][H][W] (required) and p_out
+ * [B][3][H][W] (or NULL), and checkpoints into the workspace (256-byte
+ * aligned, rec_diff_workspace_bytes long, owned by the caller).  Enqueued on
+ * `stream` (a hipStream_t, NULL = default); no synchronisation, no
+ * allocation.  REC_EINVAL for a bad descriptor or a missing required
+ * pointer, REC_ENOMEM for a short workspace, REC_EDEVICE if a launch fails.
+ * The outputs must not alias the inputs or the workspace. */
+int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
+                     float* p_out, void* dev_workspace, size_t ws_bytes, void* stream);
+
+/* Backward: g_u = dJ/du_K [B][H][W] and g_p = dJ/dp_K [B][3][H][W] (either
+ * may be NULL for zero); the gradients requested in `out` are overwritten.
+ * Must follow rec_diff_forward with the same descriptor, the same inputs
+ * (unchanged in between) and the same workspace, on the same stream or
+ * ordered after it.  Same errors as rec_diff_forward. */
+int rec_diff_backward(const rec_diff_desc* d, const rec_diff_inputs* in, const float* g_u,
+                      const float* g_p, const rec_diff_grads* out, void* dev_workspace,
+                      size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -122,6 +122,8 @@ def _load():
         lib.orc_prox_kl.argtypes = [ctypes.c_double] * 5
         lib.orc_project.restype = None
         lib.orc_project.argtypes = [_vp, _vp, _vp, ctypes.c_double]
+        lib.orc_set_weights.restype = ctypes.c_int
+        lib.orc_set_weights.argtypes = [_vp, _vp]
         lib.orc_tvl1.restype = None
         lib.orc_tvl1.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, _vp]
         _lib = lib
@@ -282,6 +284,10 @@ class Oracle:
         u = None if u is None else _f64(u)
         ps = [None, None, None] if p is None else [_f64(p[i]) for i in range(3)]
         self._lib.orc_set_state(self._h, _ptr(u), *[_ptr(a) for a in ps])
+
+    def set_weights(self, w=None):
+        w = None if w is None else _f64(w)
+        self._lib.orc_set_weights(self._h, _ptr(w))
 
     def set_data(self, f=None, tx=None, ty=None):
         f = None if f is None else _f64(f)

@@ -44,6 +44,10 @@
  *     started at v = tau, dual 0, steps 1/sqrt(8), before the differences
  *     are taken.
  *
+ * Optional per-pixel data weights w (not in the paper; they make the data
+ * term lambda sum w (u - f log u) sqrt(G) and are the weights a learned
+ * reconstruction would differentiate; w = 1 is the paper's model).
+ *
  * Primal-dual gap (not in the paper; standard Fenchel duality for eqn. (5)),
  * per pixel, with A = L_g u, d = (L_g^* p), s = sqrt(G), b = lambda s:
  *   term1 = s |A| - <A, p>                                  (>= 0 if |p| <= s)
@@ -80,6 +84,7 @@ typedef struct {
     size_t np;
     double *u, *p1, *p2, *p3;        /* primal image, dual field (3 planes) */
     double *f;                       /* data image of the current block */
+    double *w;                       /* per-pixel data weights (NULL: all 1) */
     double *tau_s, *tx, *ty;         /* time surface and its forward differences */
     float *tau32, *tx32, *ty32;      /* the same, rounded once to FP32 */
     int32_t *npos, *nneg;            /* events of the pending block */
@@ -234,7 +239,7 @@ void orc_free(orc_state* S) {
     free(S->u); free(S->p1); free(S->p2); free(S->p3); free(S->f);
     free(S->tau_s); free(S->tx); free(S->ty);
     free(S->tau32); free(S->tx32); free(S->ty32);
-    free(S->npos); free(S->nneg); free(S->t_last);
+    free(S->npos); free(S->nneg); free(S->t_last); free(S->w);
     free(S);
 }
 
@@ -373,7 +378,7 @@ void orc_gap_energy(const orc_state* S, double* gap, double* energy) {
         double s = sqrt(1.0 + S->tx[k] * S->tx[k] + S->ty[k] * S->ty[k]);
         double na = sqrt(a1[k] * a1[k] + a2[k] * a2[k] + a3[k] * a3[k]);
         double t1 = s * na - (a1[k] * S->p1[k] + a2[k] * S->p2[k] + a3[k] * S->p3[k]);
-        double b = S->P.lambda * s;
+        double b = S->P.lambda * (S->w ? S->w[k] : 1.0) * s;
         double d = ls[k];
         double u = S->u[k], f = S->f[k];
         double v;
@@ -414,7 +419,7 @@ void orc_iterate(orc_state* S, int iters, int gap_every, double* gaps, double* e
         orc_apply_LgT(W, H, S->tx, S->ty, S->p1, S->p2, S->p3, ls);
         for (size_t k = 0; k < n; ++k) {
             double s = sqrt(1.0 + S->tx[k] * S->tx[k] + S->ty[k] * S->ty[k]);
-            double beta = tau * lam * s;
+            double beta = tau * lam * (S->w ? S->w[k] : 1.0) * s;
             double ubar = S->u[k] - tau * ls[k];
             unew[k] = orc_prox_kl(ubar, beta, S->f[k], S->P.u_min, S->P.u_max);
             ut[k] = 2.0 * unew[k] - S->u[k];
@@ -495,6 +500,20 @@ int orc_set_state(orc_state* S, const double* u, const double* p1, const double*
     if (p1) memcpy(S->p1, p1, n * sizeof(double));
     if (p2) memcpy(S->p2, p2, n * sizeof(double));
     if (p3) memcpy(S->p3, p3, n * sizeof(double));
+    return ORC_OK;
+}
+
+/* Per-pixel data weights (NULL restores w = 1). */
+int orc_set_weights(orc_state* S, const double* w) {
+    if (!S) return ORC_EINVAL;
+    if (!w) {
+        free(S->w);
+        S->w = NULL;
+        return ORC_OK;
+    }
+    if (!S->w) S->w = (double*)malloc(sizeof(double) * S->np);
+    if (!S->w) return ORC_EINVAL;
+    memcpy(S->w, w, S->np * sizeof(double));
     return ORC_OK;
 }
 

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librec.so")
-SOURCES = ["kernels.hip", "rec_api.hip"]
+SOURCES = ["kernels.hip", "rec_api.hip", "adjoint.hip"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: every fused multiply-add in the per-pixel arithmetic is

@@ -1,0 +1,550 @@
+// Differentiable unrolled primal-dual loop: forward with checkpoints and the
+// hand-written reverse sweep (C ABI rec_diff_*).
+//
+// Forward (per iteration, Section 3.2, eqn. cont_iterates, with per-pixel
+// data weights w):
+//   ubar = u - tau L_g^* p,   u+ = clamp(prox(ubar; beta, f)),  beta = tau lambda w s
+//   p+   = proj_s(pbar),      pbar = p + sigma L_g (2 u+ - u)
+// Reverse (adjoints written with a hat; h_u, h_p those of (u+, p+)):
+//   q      = J_proj(pbar)^T h_p          J = I inside the ball,
+//                                        (s/|pbar|)(I - n n^T) outside
+//   ut_hat = sigma L_g^* q
+//   H      = h_u + 2 ut_hat              adjoint of u+ including the extrapolation
+//   ub_hat = (u+/r) H,  beta_hat = ((f - u+)/r) H,  f_hat = (beta/r) H
+//                                        (derivatives of the root u+ of
+//                                        u^2 - a u - beta f = 0, a = ubar - beta,
+//                                        r = sqrt(a^2 + 4 beta f); all 0 where
+//                                        the clamp is active)
+//   hat u  = ub_hat - ut_hat,   hat p = q - tau L_g ub_hat
+// and after the last reverse step
+//   dJ/du0 = hat u_0 + f_hat_sum * exp(dpos n+ - dneg n-)   (f = u0 exp(...))
+//   dJ/dw  = tau lambda s beta_hat_sum,  dJ/dlambda = sum tau w s beta_hat_sum
+//   dJ/ddpos = sum f_hat_sum f n+,  dJ/ddneg = -sum f_hat_sum f n-.
+// The reverse step needs (u_k, p_k, u_k+1): every ckpt_every-th state is a
+// checkpoint of the forward; the states between two checkpoints are
+// recomputed, bit for bit, by the same forward kernels before the segment's
+// reverse steps run.
+//
+// Kernels are one thread per pixel, 64 x 4 pixels per workgroup (a
+// wavefront covers 64 consecutive pixels of a row), blockIdx.z = image.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include "pd_math.h"
+#include "rec.h"
+
+namespace rec {
+namespace {
+
+constexpr int kTileX = 64, kTileY = 4, kThreads = kTileX * kTileY;
+
+struct Dims {
+    int32_t W, H;
+    size_t np;  // W * H
+};
+
+// One (u, p) state of the whole batch: u [B][np], p [B][3][np].
+struct State {
+    float* u;
+    float* p;
+};
+
+struct Steps {
+    double tau_d;          // tau in FP64 (for tau * lambda, as the forward solve forms it)
+    float tau, sigma, umin, umax;
+};
+
+__device__ __forceinline__ bool pixel(const Dims& d, int& i, int& j, size_t& o, size_t& b) {
+    j = blockIdx.x * kTileX + (threadIdx.x & (kTileX - 1));
+    i = blockIdx.y * kTileY + (threadIdx.x >> 6);
+    b = blockIdx.z;
+    o = b * d.np + (size_t)i * d.W + j;
+    return j < d.W && i < d.H;
+}
+
+// tau * lambda * w of one pixel (FP32, the product the forward solve uses
+// when w = 1).
+__device__ __forceinline__ float taulam_w(const double* theta, double tau, const float* w,
+                                          size_t o) {
+    const float tl = (float)(tau * theta[0]);
+    return w ? tl * w[o] : tl;
+}
+
+// q_x of the left neighbour / q_y of the upper neighbour of field v
+// (3 planes of stride np starting at v), 0 outside the image.
+__device__ __forceinline__ float qx_left(const Dims& d, int i, int j, size_t o, const float* tx,
+                                         const float* ty, const float* v1, size_t np) {
+    if (j == 0) return 0.0f;
+    const size_t l = o - 1;
+    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, true, i < d.H - 1);
+    return q_x(c, v1[l], v1[np + l], v1[2 * np + l]);
+}
+__device__ __forceinline__ float qy_up(const Dims& d, int i, int j, size_t o, const float* tx,
+                                       const float* ty, const float* v1, size_t np) {
+    if (i == 0) return 0.0f;
+    const size_t l = o - d.W;
+    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, j < d.W - 1, true);
+    return q_y(c, v1[l], v1[np + l], v1[2 * np + l]);
+}
+
+// Offset of pixel o of image b in a 3-plane field [B][3][np]: component m
+// is at base + m * np.
+__device__ __forceinline__ size_t field(const Dims& d, size_t b, size_t o) {
+    return o + 2 * b * d.np;  // b * 3 np + (o - b np)
+}
+
+// ------------------------------------------------------------------ forward
+
+// f = u0 exp(dpos n+ - dneg n-); state 0 = (u0, p0 or 0).
+__global__ __launch_bounds__(kThreads) void k_diff_init(Dims d, const float* __restrict__ u0,
+                                                        const float* __restrict__ p0,
+                                                        const int32_t* __restrict__ npos,
+                                                        const int32_t* __restrict__ nneg,
+                                                        const double* __restrict__ theta,
+                                                        float* __restrict__ f, State s0) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    const float u = u0[o];
+    f[o] = data_image(u, npos[o], nneg[o], theta[1], theta[2]);
+    s0.u[o] = u;
+    const size_t q = field(d, b, o);
+    for (int m = 0; m < 3; ++m) s0.p[q + m * d.np] = p0 ? p0[q + m * d.np] : 0.0f;
+}
+
+// Primal half-step from state a into b.u.
+__global__ __launch_bounds__(kThreads) void k_diff_primal(Dims d, State a, State b_,
+                                                          const float* __restrict__ f,
+                                                          const float* __restrict__ tx,
+                                                          const float* __restrict__ ty,
+                                                          const float* __restrict__ w,
+                                                          const double* __restrict__ theta,
+                                                          Steps st) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    const size_t q = field(d, b, o);
+    const float* p = a.p + (q - o);  // image b's field, indexed by o
+    const Coef c = make_coef(tx[o], ty[o], f[o], taulam_w(theta, st.tau_d, w, o), j < d.W - 1,
+                             i < d.H - 1);
+    const float qx = q_x(c, p[o], p[d.np + o], p[2 * d.np + o]);
+    const float qy = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
+    const float qxl = qx_left(d, i, j, o, tx, ty, p, d.np);
+    const float qyu = qy_up(d, i, j, o, tx, ty, p, d.np);
+    b_.u[o] = primal(a.u[o], qx, qy, qxl, qyu, c, st.tau, st.umin, st.umax);
+}
+
+// Dual half-step: p of state a, primal a.u -> b.u, into b.p.
+__global__ __launch_bounds__(kThreads) void k_diff_dual(Dims d, State a, State b_,
+                                                        const float* __restrict__ tx,
+                                                        const float* __restrict__ ty, Steps st) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    const float ut = extrapolate(b_.u[o], a.u[o]);
+    float gx = 0.0f, gy = 0.0f;
+    if (j < d.W - 1) gx = extrapolate(b_.u[o + 1], a.u[o + 1]) - ut;
+    if (i < d.H - 1) gy = extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut;
+    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+    const size_t q = field(d, b, o);
+    float p1 = a.p[q], p2 = a.p[q + d.np], p3 = a.p[q + 2 * d.np];
+    dual(p1, p2, p3, gx, gy, c, st.sigma);
+    b_.p[q] = p1;
+    b_.p[q + d.np] = p2;
+    b_.p[q + 2 * d.np] = p3;
+}
+
+__global__ __launch_bounds__(kThreads) void k_diff_out(Dims d, State s, float* __restrict__ u,
+                                                       float* __restrict__ p) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    u[o] = s.u[o];
+    if (p) {
+        const size_t q = field(d, b, o);
+        for (int m = 0; m < 3; ++m) p[q + m * d.np] = s.p[q + m * d.np];
+    }
+}
+
+// ------------------------------------------------------------------ reverse
+
+// Adjoint planes of the reverse sweep.
+struct Adj {
+    float* q;      // [B][3][np] J_proj^T h_p of the latest reverse step
+    float* ub;     // [B][np] ub_hat of the latest reverse step
+    float* uh;     // [B][np] hat u of the latest reverse step
+    float* gbeta;  // [B][np] sum of beta_hat over the steps
+    float* gf;     // [B][np] sum of f_hat over the steps
+};
+
+// hat p of the state after the latest reverse step, at one pixel:
+// q - tau L_g ub_hat (first = no step yet: g_p, or 0).
+__device__ __forceinline__ void adj_p(const Dims& d, int i, int j, size_t o, size_t q,
+                                      const Coef& c, const Adj& A, const float* g_p, bool first,
+                                      float tau, float& h1, float& h2, float& h3) {
+    if (first) {
+        h1 = g_p ? g_p[q] : 0.0f;
+        h2 = g_p ? g_p[q + d.np] : 0.0f;
+        h3 = g_p ? g_p[q + 2 * d.np] : 0.0f;
+        return;
+    }
+    const float ubc = A.ub[o];
+    const float gx = j < d.W - 1 ? A.ub[o + 1] - ubc : 0.0f;
+    const float gy = i < d.H - 1 ? A.ub[o + d.W] - ubc : 0.0f;
+    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
+    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
+    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
+    h1 = __builtin_fmaf(-tau, v1, A.q[q]);
+    h2 = __builtin_fmaf(-tau, v2, A.q[q + d.np]);
+    h3 = __builtin_fmaf(-tau, v3, A.q[q + 2 * d.np]);
+}
+
+// Reverse of the dual half-step of the iteration a -> b: q = J_proj^T h_p.
+__global__ __launch_bounds__(kThreads) void k_adj_dual(Dims d, State a, State b_,
+                                                       const float* __restrict__ tx,
+                                                       const float* __restrict__ ty, Adj A,
+                                                       const float* __restrict__ g_p, int first,
+                                                       Steps st) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    const size_t q = field(d, b, o);
+    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+    float h1, h2, h3;
+    adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.tau, h1, h2, h3);
+    // pbar of the forward step, recomputed
+    const float ut = extrapolate(b_.u[o], a.u[o]);
+    const float gx = j < d.W - 1 ? extrapolate(b_.u[o + 1], a.u[o + 1]) - ut : 0.0f;
+    const float gy = i < d.H - 1 ? extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut : 0.0f;
+    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
+    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
+    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
+    const float b1 = __builtin_fmaf(st.sigma, v1, a.p[q]);
+    const float b2 = __builtin_fmaf(st.sigma, v2, a.p[q + d.np]);
+    const float b3 = __builtin_fmaf(st.sigma, v3, a.p[q + 2 * d.np]);
+    const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
+    const float sc = c.s * rsq(n2);
+    if (sc < 1.0f) {  // the forward projected this point (same test as its min)
+        const float t = __builtin_fmaf(b3, h3, __builtin_fmaf(b2, h2, b1 * h1)) * rcp(n2);
+        h1 = sc * __builtin_fmaf(-t, b1, h1);
+        h2 = sc * __builtin_fmaf(-t, b2, h2);
+        h3 = sc * __builtin_fmaf(-t, b3, h3);
+    }
+    A.q[q] = h1;
+    A.q[q + d.np] = h2;
+    A.q[q + 2 * d.np] = h3;
+}
+
+// Reverse of the primal half-step and the extrapolation of the iteration
+// starting at state a.
+__global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
+                                                         const float* __restrict__ f,
+                                                         const float* __restrict__ tx,
+                                                         const float* __restrict__ ty,
+                                                         const float* __restrict__ w,
+                                                         const double* __restrict__ theta, Adj A,
+                                                         const float* __restrict__ g_u,
+                                                         int first, Steps st) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    const size_t q = field(d, b, o);
+    const float* qf = A.q + (q - o);
+    const float* p = a.p + (q - o);
+    const float fo = f[o];
+    const Coef c = make_coef(tx[o], ty[o], fo, taulam_w(theta, st.tau_d, w, o), j < d.W - 1,
+                             i < d.H - 1);
+    // ut_hat = sigma L_g^* q = -sigma div(M^T q)
+    const float qx = q_x(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
+    const float qy = q_y(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
+    const float divq = (qx - qx_left(d, i, j, o, tx, ty, qf, d.np)) +
+                       (qy - qy_up(d, i, j, o, tx, ty, qf, d.np));
+    const float ut_hat = -st.sigma * divq;
+    const float hu = first ? (g_u ? g_u[o] : 0.0f) : A.uh[o];
+    const float H = __builtin_fmaf(2.0f, ut_hat, hu);
+    // the forward's root, recomputed
+    const float px = q_x(c, p[o], p[d.np + o], p[2 * d.np + o]);
+    const float py = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
+    float r;
+    const float un = prox_root(a.u[o], px, py, qx_left(d, i, j, o, tx, ty, p, d.np),
+                               qy_up(d, i, j, o, tx, ty, p, d.np), c, st.tau, r);
+    const bool active = un >= st.umin && un <= st.umax;
+    const float hr = active ? H * rcp(r) : 0.0f;
+    const float ub_hat = un * hr;
+    A.ub[o] = ub_hat;
+    A.uh[o] = ub_hat - ut_hat;
+    A.gbeta[o] += (fo - un) * hr;
+    A.gf[o] += c.beta * hr;
+}
+
+__global__ __launch_bounds__(kThreads) void k_adj_zero(Dims d, Adj A) {
+    int i, j;
+    size_t o, b;
+    if (!pixel(d, i, j, o, b)) return;
+    A.gbeta[o] = 0.0f;
+    A.gf[o] = 0.0f;
+}
+
+// Gradients of the inputs; per-workgroup FP64 partial sums of the scalar
+// gradients (lambda, dpos, dneg) into part[3 * block].
+__global__ __launch_bounds__(kThreads) void k_adj_final(
+    Dims d, const float* __restrict__ f, const float* __restrict__ tx,
+    const float* __restrict__ ty, const float* __restrict__ w, const int32_t* __restrict__ npos,
+    const int32_t* __restrict__ nneg, const double* __restrict__ theta, Adj A,
+    const float* __restrict__ g_u, const float* __restrict__ g_p, int first, Steps st,
+    float* __restrict__ gu0, float* __restrict__ gp0, float* __restrict__ gw,
+    double* __restrict__ part) {
+    __shared__ double red[3][kThreads];
+    int i, j;
+    size_t o, b;
+    double s_lam = 0.0, s_dp = 0.0, s_dn = 0.0;
+    if (pixel(d, i, j, o, b)) {
+        const size_t q = field(d, b, o);
+        const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+        if (gp0) {
+            float h1, h2, h3;
+            adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.tau, h1, h2, h3);
+            gp0[q] = h1;
+            gp0[q + d.np] = h2;
+            gp0[q + 2 * d.np] = h3;
+        }
+        const double gb = first ? 0.0 : (double)A.gbeta[o];
+        const double gfo = first ? 0.0 : (double)A.gf[o];
+        const int32_t np_ = npos[o], nn_ = nneg[o];
+        if (gu0) {
+            const double e = exp(theta[1] * (double)np_ - theta[2] * (double)nn_);
+            const double hu = first ? (g_u ? (double)g_u[o] : 0.0) : (double)A.uh[o];
+            gu0[o] = (float)(hu + gfo * e);
+        }
+        const double tws = st.tau_d * (double)c.s;  // d beta / d(lambda w)
+        const double wo = w ? (double)w[o] : 1.0;
+        if (gw) gw[o] = (float)(tws * theta[0] * gb);
+        s_lam = tws * wo * gb;
+        const double ff = gfo * (double)f[o];
+        s_dp = ff * (double)np_;
+        s_dn = -ff * (double)nn_;
+    }
+    const int t = threadIdx.x;
+    red[0][t] = s_lam;
+    red[1][t] = s_dp;
+    red[2][t] = s_dn;
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int m = 0; m < 3; ++m) red[m][t] += red[m][t + h];
+        __syncthreads();
+    }
+    if (t < 3) {
+        const size_t blk = ((size_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        part[3 * blk + t] = red[t][0];
+    }
+}
+
+// Sum of the partials in a fixed order (one workgroup).
+__global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restrict__ part,
+                                                         size_t nblk, double* __restrict__ out) {
+    __shared__ double red[3][kThreads];
+    const int t = threadIdx.x;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (size_t k = t; k < nblk; k += kThreads)
+        for (int m = 0; m < 3; ++m) s[m] += part[3 * k + m];
+    for (int m = 0; m < 3; ++m) red[m][t] = s[m];
+    __syncthreads();
+    for (int h = kThreads / 2; h > 0; h >>= 1) {
+        if (t < h)
+            for (int m = 0; m < 3; ++m) red[m][t] += red[m][t + h];
+        __syncthreads();
+    }
+    if (t < 3) out[t] = red[t][0];
+}
+
+// ------------------------------------------------------------------ host
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool desc_ok(const rec_diff_desc* d) {
+    if (!d) return false;
+    if (d->width < 1 || d->width > 65535 || d->height < 1 || d->height > 65535) return false;
+    if (d->batch < 1 || d->batch > 65535 || d->iters < 0 || d->reserved != 0) return false;
+    if (d->ckpt_every < 1 || d->ckpt_every > (d->iters > 0 ? d->iters : 1)) return false;
+    if (!(d->tau > 0.0) || !(d->sigma > 0.0) || !isfinite(d->tau) || !isfinite(d->sigma))
+        return false;
+    if (d->tau * d->sigma * (8.0 + 4.0 * sqrt(2.0)) > 1.0 + 1e-12) return false;
+    if (!(d->u_min > 0.0) || !(d->u_max > d->u_min) || !isfinite(d->u_max)) return false;
+    return true;
+}
+
+int segments(const rec_diff_desc* d) {
+    return d->iters == 0 ? 0 : (d->iters + d->ckpt_every - 1) / d->ckpt_every;
+}
+
+dim3 grid_of(const rec_diff_desc* d) {
+    return dim3((unsigned)((d->width + kTileX - 1) / kTileX),
+                (unsigned)((d->height + kTileY - 1) / kTileY), (unsigned)d->batch);
+}
+
+size_t blocks_of(const rec_diff_desc* d) {
+    const dim3 g = grid_of(d);
+    return (size_t)g.x * g.y * g.z;
+}
+
+// Workspace carve: f | checkpoints (C + 1 states) | segment (k - 1 states) |
+// adjoint planes | partial sums.
+struct Carve {
+    float* f;
+    State ck0;        // checkpoint c at ck0 + c * state_stride
+    State seg0;       // segment slot j at seg0 + j * state_stride
+    size_t state_floats;
+    Adj A;
+    double* part;
+    size_t bytes;
+};
+
+Carve carve(const rec_diff_desc* d, char* base) {
+    Carve c{};
+    const size_t n = (size_t)d->width * d->height * d->batch;
+    const size_t plane = align_up(n * sizeof(float));
+    const size_t state = 4 * plane;
+    size_t off = 0;
+    c.f = (float*)(base + off);
+    off += plane;
+    c.state_floats = state / sizeof(float);
+    c.ck0.u = (float*)(base + off);
+    c.ck0.p = (float*)(base + off + plane);
+    off += state * (size_t)(segments(d) + 1);
+    c.seg0.u = (float*)(base + off);
+    c.seg0.p = (float*)(base + off + plane);
+    off += state * (size_t)(d->ckpt_every - 1);
+    c.A.q = (float*)(base + off);
+    off += 3 * plane;
+    c.A.ub = (float*)(base + off);
+    off += plane;
+    c.A.uh = (float*)(base + off);
+    off += plane;
+    c.A.gbeta = (float*)(base + off);
+    off += plane;
+    c.A.gf = (float*)(base + off);
+    off += plane;
+    c.part = (double*)(base + off);
+    off += align_up(blocks_of(d) * 3 * sizeof(double));
+    c.bytes = off;
+    return c;
+}
+
+State at(State s0, size_t stride, int k) {
+    return State{s0.u + (size_t)k * stride, s0.p + (size_t)k * stride};
+}
+
+struct Ctx {
+    const rec_diff_desc* d;
+    const rec_diff_inputs* in;
+    Carve cv;
+    Dims dims;
+    Steps st;
+    dim3 grid;
+    hipStream_t s;
+};
+
+int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size_t bytes,
+               Ctx& x) {
+    if (!desc_ok(d) || !in || !in->u0 || !in->npos || !in->nneg || !in->tx || !in->ty ||
+        !in->theta)
+        return REC_EINVAL;
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return REC_EINVAL;
+    x.d = d;
+    x.in = in;
+    x.cv = carve(d, (char*)ws);
+    if (bytes < x.cv.bytes) return REC_ENOMEM;
+    x.dims = Dims{d->width, d->height, (size_t)d->width * d->height};
+    x.st = Steps{d->tau, (float)d->tau, (float)d->sigma, (float)d->u_min, (float)d->u_max};
+    x.grid = grid_of(d);
+    return REC_OK;
+}
+
+// One forward iteration from state a into b.
+void step(const Ctx& x, State a, State b) {
+    hipLaunchKernelGGL(k_diff_primal, x.grid, dim3(kThreads), 0, x.s, x.dims, a, b, x.cv.f,
+                       x.in->tx, x.in->ty, x.in->w, x.in->theta, x.st);
+    hipLaunchKernelGGL(k_diff_dual, x.grid, dim3(kThreads), 0, x.s, x.dims, a, b, x.in->tx,
+                       x.in->ty, x.st);
+}
+
+// State j of segment c (0 = its checkpoint, m = the next checkpoint).
+State seg_state(const Ctx& x, int c, int j, int m) {
+    if (j == 0) return at(x.cv.ck0, x.cv.state_floats, c);
+    if (j == m) return at(x.cv.ck0, x.cv.state_floats, c + 1);
+    return at(x.cv.seg0, x.cv.state_floats, j - 1);
+}
+
+}  // namespace
+}  // namespace rec
+
+using namespace rec;
+
+extern "C" {
+
+size_t rec_diff_workspace_bytes(const rec_diff_desc* d) {
+    if (!desc_ok(d)) return 0;
+    return carve(d, nullptr).bytes;
+}
+
+int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
+                     float* p_out, void* dev_workspace, size_t ws_bytes, void* stream) {
+    Ctx x;
+    int rc = check_call(d, in, dev_workspace, ws_bytes, x);
+    if (rc != REC_OK) return rc;
+    if (!u_out) return REC_EINVAL;
+    x.s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_diff_init, x.grid, dim3(kThreads), 0, x.s, x.dims, in->u0, in->p0,
+                       in->npos, in->nneg, in->theta, x.cv.f, x.cv.ck0);
+    const int C = segments(d), k = d->ckpt_every;
+    for (int c = 0; c < C; ++c) {
+        const int m = (d->iters - c * k) < k ? d->iters - c * k : k;
+        for (int j = 0; j < m; ++j) step(x, seg_state(x, c, j, m), seg_state(x, c, j + 1, m));
+    }
+    hipLaunchKernelGGL(k_diff_out, x.grid, dim3(kThreads), 0, x.s, x.dims,
+                       at(x.cv.ck0, x.cv.state_floats, C), u_out, p_out);
+    return hipGetLastError() == hipSuccess ? REC_OK : REC_EDEVICE;
+}
+
+int rec_diff_backward(const rec_diff_desc* d, const rec_diff_inputs* in, const float* g_u,
+                      const float* g_p, const rec_diff_grads* out, void* dev_workspace,
+                      size_t ws_bytes, void* stream) {
+    Ctx x;
+    int rc = check_call(d, in, dev_workspace, ws_bytes, x);
+    if (rc != REC_OK) return rc;
+    if (!out) return REC_EINVAL;
+    x.s = (hipStream_t)stream;
+    (void)hipGetLastError();
+    const dim3 blk(kThreads);
+    hipLaunchKernelGGL(k_adj_zero, x.grid, blk, 0, x.s, x.dims, x.cv.A);
+    const int C = segments(d), k = d->ckpt_every;
+    int first = 1;
+    for (int c = C - 1; c >= 0; --c) {
+        const int m = (d->iters - c * k) < k ? d->iters - c * k : k;
+        for (int j = 0; j + 1 < m; ++j)  // recompute the states inside the segment
+            step(x, seg_state(x, c, j, m), seg_state(x, c, j + 1, m));
+        for (int j = m - 1; j >= 0; --j) {
+            const State a = seg_state(x, c, j, m), b = seg_state(x, c, j + 1, m);
+            hipLaunchKernelGGL(k_adj_dual, x.grid, blk, 0, x.s, x.dims, a, b, in->tx, in->ty,
+                               x.cv.A, g_p, first, x.st);
+            hipLaunchKernelGGL(k_adj_primal, x.grid, blk, 0, x.s, x.dims, a, x.cv.f, in->tx,
+                               in->ty, in->w, in->theta, x.cv.A, g_u, first, x.st);
+            first = 0;
+        }
+    }
+    hipLaunchKernelGGL(k_adj_final, x.grid, blk, 0, x.s, x.dims, x.cv.f, in->tx, in->ty, in->w,
+                       in->npos, in->nneg, in->theta, x.cv.A, g_u, g_p, first, x.st, out->u0,
+                       out->p0, out->w, x.cv.part);
+    if (out->theta)
+        hipLaunchKernelGGL(k_adj_reduce, dim3(1), blk, 0, x.s, x.cv.part, blocks_of(d),
+                           out->theta);
+    return hipGetLastError() == hipSuccess ? REC_OK : REC_EDEVICE;
+}
+
+}  // extern "C"

@@ -101,6 +101,19 @@ constexpr int kStoreF32 = 0;
 constexpr int kStoreBF16 = 1;
 constexpr int kStoreF16 = 2;
 
+// One stream of a batched solve (device copy, written before the solve).
+struct StreamDesc {
+    Planes P;
+    Frame fr;
+    IterConsts kc;
+    BuildConsts bc;
+    EventSegs segs;
+    int32_t cur;     // ping-pong parity at the start of the solve
+    int32_t mode0;   // mode of the solve's first launch
+    int32_t mode1;   // mode of its second launch
+    int32_t tiles_x; // tiles per row for the batch's tile geometry
+};
+
 // Optional timing events around a launch (recorded by the launch packet).
 struct LaunchEv {
     hipEvent_t start = nullptr, stop = nullptr;
@@ -135,5 +148,14 @@ hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, flo
                              hipStream_t s);
 hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s);
 hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s);
+// Batched solve: one launch over the work list of (stream, tile) pairs.
+// K iterations in this launch, KG the halo of the tile geometry (K <= KG),
+// li the launch's index within the solve, bins: some stream folds events.
+hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
+                           int li, bool bins, int rows, int waves, int storage, hipStream_t s,
+                           LaunchEv ev = {});
+bool batch_shape_supported(int rows, int waves);
+hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max_np,
+                               hipStream_t s);
 
 }  // namespace rec

@@ -201,15 +201,6 @@ __global__ void k_push_finalize(Planes P, Frame fr, const int64_t* t, const uint
 
 // ---------------------------------------------------------------- build
 
-// Data image of one pixel: f = u_prev * exp(Delta+ n+ - Delta- n-)
-// (eqn. intensity_update for every event of the block), formed in FP64 and
-// rounded once.
-__device__ __forceinline__ float data_image(float u_prev, int32_t npos, int32_t nneg,
-                                            const BuildConsts& b) {
-    const double e = b.dpos * (double)npos - b.dneg * (double)nneg;
-    return (float)((double)u_prev * exp(e));
-}
-
 // Forward differences of the time surface from the latest timestamps of a
 // pixel (tl), its right (tr) and lower (td) neighbours:
 // tau(x+1) - tau(x) = (t_last(x) - t_last(x+1)) / T_s from the exact int64
@@ -237,7 +228,7 @@ __global__ void k_build(Planes P, Frame fr, int cur, BuildConsts bc, int time_me
     }
     if (k >= np) return;
     const int32_t j = (int32_t)(k % fr.W), i = (int32_t)(k / fr.W);
-    P.f[k] = data_image(P.u[cur][k], P.npos[k], P.nneg[k], bc);
+    P.f[k] = data_image(P.u[cur][k], P.npos[k], P.nneg[k], bc.dpos, bc.dneg);
     P.npos[k] = 0;
     P.nneg[k] = 0;
     if (time_mem) return;  // tx, ty come from the timestamp denoising
@@ -446,7 +437,7 @@ struct TileBins {
 // into the tile region [rx0, rx0 + 64] x [ry0, ry0 + RH].  Every workgroup
 // takes the same decisions; block 0 records the outcome as pending state.
 __device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int RH, int rx0,
-                           int ry0, unsigned char* lds, TileBins& tb) {
+                           int ry0, bool lead, unsigned char* lds, TileBins& tb) {
     __shared__ unsigned long long seg_bad[kMaxSegs];
     __shared__ int seg_ok[kMaxSegs];
     __shared__ long long s_first;
@@ -500,7 +491,7 @@ __device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int
             }
         }
         s_first = st->started ? st->t_first : (first == kNever ? 0 : first);
-        if (blockIdx.x == 0) {
+        if (lead) {
             st->pend_t_ref = last;
             st->pend_t_first = first;
             st->pend_accepted = accepted > 0;
@@ -540,18 +531,21 @@ __device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int
 //   (dynamic LDS); with kCounts the scattered counts are added.
 // mode & kZero: resets the scattered counts of the interior at the end.
 // mode & kCommit: block 0 commits the pending stream state.
+//
+// The tile geometry uses a halo of KG >= K pixels (the batched launch keeps
+// one geometry for all launches of a solve); tile (txi, tyi) covers the
+// region whose interior starts at (txi, tyi) * (64 - 2 KG, NW R - 2 KG).
+// `lead`: this tile does the per-stream duties (commit, pending state).
 template <int R, int NW, class S>
-__global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
-                                                      BuildConsts bc, EventSegs segs, int cur,
-                                                      int K, int mode, int tiles_x, int ntiles) {
-    extern __shared__ unsigned char dyn_lds[];
+__device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterConsts& kc,
+                                        const BuildConsts& bc, const EventSegs& segs, int cur,
+                                        int K, int KG, int mode, int txi, int tyi, bool lead,
+                                        unsigned char* dyn_lds) {
     constexpr int RH = NW * R;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int tile = xcd_tile(blockIdx.x, ntiles);
-    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    const int OW = 64 - 2 * K, OH = RH - 2 * K;
-    const int rx0 = txi * OW - K, ry0 = tyi * OH - K;
+    const int OW = 64 - 2 * KG, OH = RH - 2 * KG;
+    const int rx0 = txi * OW - KG, ry0 = tyi * OH - KG;
     const int gx = rx0 + lane;
     const int gy0 = ry0 + wave * R;
     const size_t np = (size_t)fr.W * fr.H;
@@ -560,7 +554,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     typename S::T* __restrict__ txs = (typename S::T*)P.tx;
     typename S::T* __restrict__ tys = (typename S::T*)P.ty;
 
-    if ((mode & kCommit) && blockIdx.x == 0 && threadIdx.x == 0) commit_pending(P.st);
+    if ((mode & kCommit) && lead && threadIdx.x == 0) commit_pending(P.st);
 
     const bool build = (mode & kBuild) != 0;
     TileBins tb;
@@ -569,10 +563,10 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     tb.t_first = 0;
     if (build) {
         if (mode & kEvents) {
-            bin_events(P, fr, segs, RH, rx0, ry0, dyn_lds, tb);
+            bin_events(P, fr, segs, RH, rx0, ry0, lead, dyn_lds, tb);
         } else {
             tb.t_first = P.st->t_first;
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
+            if (lead && threadIdx.x == 0) {
                 DevState* st = P.st;
                 st->pend_accepted = 0;
                 st->pend_err = 0;
@@ -584,7 +578,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     float u[R], p1[R], p2[R], p3[R];
     Coef c[R];
     const bool col_in = gx >= 0 && gx < fr.W;
-    const bool col_out = col_in && lane >= K && lane < 64 - K;
+    const bool col_out = col_in && lane >= KG && lane < 64 - KG;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
@@ -614,7 +608,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
                     tr = max(tr, (int64_t)tb.tmax[lr * 65 + lane + 1]);
                     td = max(td, (int64_t)tb.tmax[(lr + 1) * 65 + lane]);
                 }
-                f = data_image(uu, npos, nneg, bc);
+                f = data_image(uu, npos, nneg, bc.dpos, bc.dneg);
                 if (mode & kTimeMem) {
                     tx = S::ld(txs, k);
                     ty = S::ld(tys, k);
@@ -623,7 +617,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
                     tx = S::round(tx);
                     ty = S::round(ty);
                 }
-                if (col_out && lr >= K && lr < RH - K) {
+                if (col_out && lr >= KG && lr < RH - KG) {
                     P.f[k] = f;
                     if (!(mode & kTimeMem)) {
                         S::st(txs, k, tx);
@@ -690,7 +684,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
     for (int r = 0; r < R; ++r) {
         const int row = wave * R + r;
         const int gy = gy0 + r;
-        if (col_out && row >= K && row < RH - K && gy >= 0 && gy < fr.H) {
+        if (col_out && row >= KG && row < RH - KG && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
             uout[k] = u[r];
             S::st(pout, k, p1[r]);
@@ -701,6 +695,49 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
                 P.nneg[k] = 0;
             }
         }
+    }
+}
+
+template <int R, int NW, class S>
+__global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
+                                                      BuildConsts bc, EventSegs segs, int cur,
+                                                      int K, int mode, int tiles_x, int ntiles) {
+    extern __shared__ unsigned char dyn_lds[];
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    pd_tile<R, NW, S>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
+}
+
+// One launch over the tiles of many streams (a work list of (stream, tile)
+// pairs); every stream runs the same iterations with its own planes,
+// constants and folded events.  launch = index of this launch in the solve
+// (selects the stream's first-launch and second-launch modes and the
+// ping-pong parity).
+template <int R, int NW, class S>
+__global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __restrict__ descs,
+                                                            const int2* __restrict__ work,
+                                                            int nwork, int K, int KG,
+                                                            int launch) {
+    extern __shared__ unsigned char dyn_lds[];
+    const int2 w = work[xcd_tile(blockIdx.x, nwork)];
+    const StreamDesc& d = descs[w.x];
+    const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
+    const int mode = launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0);
+    pd_tile<R, NW, S>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode, txi, tyi,
+                      w.y == 0, dyn_lds);
+}
+
+// After a one-launch batched solve: commit and reset counts of every stream.
+__global__ void k_finish_batch(const StreamDesc* __restrict__ descs, int nstreams) {
+    const int s = blockIdx.y;
+    if (s >= nstreams) return;
+    const StreamDesc& d = descs[s];
+    const size_t np = (size_t)d.fr.W * d.fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) commit_pending(d.P.st);
+    if ((d.mode1 & kZero) && k < np) {
+        d.P.npos[k] = 0;
+        d.P.nneg[k] = 0;
     }
 }
 
@@ -818,6 +855,15 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
     const int ntiles = tiles_x * tiles_y;
     return launch(k_pd_fused<R, NW, S>, dim3(ntiles), dim3(64 * NW), fused_lds_bytes(R, NW, mode), s,
                   ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
+}
+
+template <int R, int NW, class S>
+hipError_t batch_launch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
+                        int launch_idx, bool bins, hipStream_t s, LaunchEv ev) {
+    if (K < 1 || K > KG || 64 - 2 * KG <= 0 || NW * R - 2 * KG <= 0) return hipErrorInvalidValue;
+    return launch(k_pd_fused_batch<R, NW, S>, dim3(nwork), dim3(64 * NW),
+                  fused_lds_bytes(R, NW, bins ? kEvents : 0), s, ev.start, ev.stop, descs, work,
+                  nwork, K, KG, launch_idx);
 }
 
 }  // namespace
@@ -961,6 +1007,51 @@ hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts
 }
 #undef REC_FUSED_CASE
 #undef REC_FUSED_CASE16
+
+#define REC_BATCH_CASE(R, NW) \
+    case R * 100 + NW: return batch_launch<R, NW, StoreF32>(descs, work, nwork, K, KG, li, bins, s, ev);
+#define REC_BATCH_CASE16(R, NW)                                                                  \
+    case R * 100 + NW:                                                                          \
+        return storage == kStoreF16                                                             \
+                   ? batch_launch<R, NW, StoreF16>(descs, work, nwork, K, KG, li, bins, s, ev)   \
+                   : batch_launch<R, NW, StoreBF16>(descs, work, nwork, K, KG, li, bins, s, ev);
+
+hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
+                           int li, bool bins, int rows, int waves, int storage, hipStream_t s,
+                           LaunchEv ev) {
+    if (!fused_shape_supported(rows, waves, storage) || nwork <= 0) return hipErrorInvalidValue;
+    if (storage != kStoreF32) {
+        switch (rows * 100 + waves) {
+            REC_BATCH_CASE16(2, 16)
+            REC_BATCH_CASE16(4, 16)
+            REC_BATCH_CASE16(4, 8)
+            REC_BATCH_CASE16(8, 4)
+            REC_BATCH_CASE16(8, 8)
+            default: return hipErrorInvalidValue;
+        }
+    }
+    switch (rows * 100 + waves) {
+        REC_BATCH_CASE(2, 16)
+        REC_BATCH_CASE(4, 8)
+        REC_BATCH_CASE(4, 16)
+        REC_BATCH_CASE(8, 4)
+        REC_BATCH_CASE(8, 8)
+        default: return hipErrorInvalidValue;
+    }
+}
+#undef REC_BATCH_CASE
+#undef REC_BATCH_CASE16
+
+bool batch_shape_supported(int rows, int waves) {
+    const int key = rows * 100 + waves;
+    return key == 216 || key == 408 || key == 416 || key == 804 || key == 808;
+}
+
+hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max_np,
+                               hipStream_t s) {
+    return launch(k_finish_batch, dim3(blocks_for(max_np, 256), nstreams), dim3(256), 0, s,
+                  nullptr, nullptr, descs, nstreams);
+}
 
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
                       int cur, int slot, int storage, hipStream_t s, LaunchEv ev) {

@@ -41,6 +41,15 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// Data image of one pixel: f = u_prev * exp(Delta+ n+ - Delta- n-)
+// (eqn. intensity_update for every event of the block), formed in FP64 and
+// rounded once.
+__device__ __forceinline__ float data_image(float u_prev, int npos, int nneg, double dpos,
+                                            double dneg) {
+    const double e = dpos * (double)npos - dneg * (double)nneg;
+    return (float)((double)u_prev * exp(e));
+}
+
 // Metric-dependent constants of one pixel (computed once per block of
 // iterations; they depend on the block's tau and f only).  has_x: the pixel
 // has a right neighbour inside the image (so L_x is a real difference);
@@ -81,15 +90,23 @@ __device__ __forceinline__ float q_y(const Coef& c, float p1, float p2, float p3
 // cancellation-free form of the closed-form root: a = ubar - beta,
 // r = sqrt(a^2 + 4 beta f):  a >= 0: (a + r) / 2,  a < 0: 2 beta f / (r - a);
 // then clamp to [umin, umax].
-__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
-                                        const Coef& c, float tau, float umin, float umax) {
+// prox_root returns the unclamped root and r (the reverse sweep of the
+// unrolled loop needs both); primal clamps it.
+__device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
+                                           const Coef& c, float tau, float& r) {
     const float div = (qx - qx_left) + (qy - qy_up);
     const float ubar = __builtin_fmaf(tau, div, u);
     const float a = ubar - c.beta;
-    const float r = sqrt_(__builtin_fmaf(a, a, c.c4));
+    r = sqrt_(__builtin_fmaf(a, a, c.c4));
     const float pos = 0.5f * (a + r);
     const float neg = (0.5f * c.c4) * rcp(r - a);
-    const float un = a >= 0.0f ? pos : neg;
+    return a >= 0.0f ? pos : neg;
+}
+
+__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
+                                        const Coef& c, float tau, float umin, float umax) {
+    float r;
+    const float un = prox_root(u, qx, qy, qx_left, qy_up, c, tau, r);
     return __builtin_fminf(__builtin_fmaxf(un, umin), umax);
 }
 

@@ -710,3 +710,306 @@ const char* rec_strerror(int code) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------------
+// Batched solves: many streams, one launch per block of iterations.
+// ------------------------------------------------------------------------
+
+namespace {
+
+struct Shape {
+    int rows, waves, k;
+};
+
+// Candidate tile geometries of the batched launch.
+std::vector<Shape> batch_candidates() {
+    std::vector<Shape> v;
+    const int shapes[][2] = {{2, 16}, {4, 8}, {4, 16}, {8, 4}, {8, 8}};
+    const int ks[] = {4, 6, 8, 10, 13, 15};
+    for (auto& sh : shapes)
+        for (int k : ks)
+            if (k <= (sh[0] * sh[1] - 1) / 2 && k <= 31) v.push_back(Shape{sh[0], sh[1], k});
+    return v;
+}
+
+int64_t batch_tiles(rec_ctx* const* ctxs, int n, Shape sh) {
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) t += rec::fused_tiles(ctxs[i]->fr, sh.rows, sh.waves, sh.k);
+    return t;
+}
+
+}  // namespace
+
+struct rec_batch {
+    std::vector<rec_ctx*> ctx;
+    hipStream_t stream;
+    int storage;
+    Shape shape;
+    double tuned_us;             // measured time of one launch of the chosen shape (0: not tuned)
+    // device workspace
+    rec::StreamDesc* d_desc[2];  // alternating per solve
+    int2* d_work;
+    int64_t work_cap;
+    int nwork;
+    // pinned staging of the descriptors
+    rec::StreamDesc* h_desc[2];
+    hipEvent_t copied[2];
+    bool copy_used[2];
+    int parity;
+    size_t max_np;
+};
+
+namespace {
+
+size_t batch_desc_bytes(int n) { return align_up((size_t)n * sizeof(rec::StreamDesc)); }
+
+int upload_work(rec_batch* b) {
+    std::vector<int2> w;
+    for (size_t s = 0; s < b->ctx.size(); ++s) {
+        const int t = rec::fused_tiles(b->ctx[s]->fr, b->shape.rows, b->shape.waves, b->shape.k);
+        if (t <= 0) return REC_EINVAL;
+        for (int q = 0; q < t; ++q) w.push_back(make_int2((int)s, q));
+    }
+    if ((int64_t)w.size() > b->work_cap) return REC_ENOMEM;
+    b->nwork = (int)w.size();
+    if (hipMemcpy(b->d_work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return REC_EDEVICE;
+    return REC_OK;
+}
+
+void fill_desc(rec_batch* b, rec::StreamDesc* d, bool* any_fold) {
+    for (size_t s = 0; s < b->ctx.size(); ++s) {
+        rec_ctx* c = b->ctx[s];
+        rec::StreamDesc& e = d[s];
+        memset(&e, 0, sizeof(e));
+        e.P = c->P;
+        e.fr = c->fr;
+        e.kc = c->kc;
+        e.bc = rec::BuildConsts{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
+        e.cur = c->cur;
+        const int ow = 64 - 2 * b->shape.k;
+        e.tiles_x = (c->fr.W + ow - 1) / ow;
+        const bool fold = !c->deferred.empty();
+        if (fold) {
+            for (size_t q = 0; q < c->deferred.size(); ++q) {
+                e.segs.t[q] = c->deferred[q].t;
+                e.segs.x[q] = c->deferred[q].x;
+                e.segs.y[q] = c->deferred[q].y;
+                e.segs.p[q] = c->deferred[q].p;
+                e.segs.n[q] = c->deferred[q].n;
+            }
+            e.segs.count = (int32_t)c->deferred.size();
+            *any_fold = true;
+        }
+        e.mode0 = rec::kBuild | (fold ? rec::kEvents : 0) | (c->counts_dirty ? rec::kCounts : 0);
+        e.mode1 = rec::kCommit | (c->counts_dirty ? rec::kZero : 0);
+    }
+}
+
+// Time `reps` side-effect-free launches (mode 0: read buffer cur, write the
+// other; the host keeps cur) of one geometry; returns microseconds per launch.
+int time_shape(rec_batch* b, int reps, double* us) {
+    int rc = upload_work(b);
+    if (rc) return rc;
+    rec::StreamDesc* h = b->h_desc[0];
+    bool fold = false;
+    fill_desc(b, h, &fold);
+    for (size_t s = 0; s < b->ctx.size(); ++s) h[s].mode0 = h[s].mode1 = 0;
+    if (hipMemcpy(b->d_desc[0], h, b->ctx.size() * sizeof(rec::StreamDesc), hipMemcpyHostToDevice) !=
+        hipSuccess)
+        return REC_EDEVICE;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return REC_EDEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return REC_EDEVICE;
+    }
+    hipError_t e = hipSuccess;
+    for (int q = 0; q < reps + 2 && e == hipSuccess; ++q) {
+        rec::LaunchEv ev;
+        if (q == 2) ev.start = e0;
+        if (q == reps + 1) ev.stop = e1;
+        // launch index 2: mode 0 for every stream, parity of launch 0
+        e = rec::launch_pd_batch(b->d_desc[0], b->d_work, b->nwork, b->shape.k, b->shape.k, 2, false,
+                                 b->shape.rows, b->shape.waves, b->storage, b->stream, ev);
+    }
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return REC_EDEVICE;
+    *us = (double)ms * 1e3 / reps;
+    return REC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n) {
+    if (!ctxs || n < 1) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!ctxs[i]) return 0;
+    int64_t tiles = 0;
+    for (const Shape& sh : batch_candidates()) {
+        const int64_t t = batch_tiles(ctxs, n, sh);
+        if (t > tiles) tiles = t;
+    }
+    return 2 * batch_desc_bytes(n) + align_up((size_t)tiles * sizeof(int2));
+}
+
+int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t ws_bytes,
+                   int32_t tune_iters, rec_batch** out) {
+    if (!out) return REC_EINVAL;
+    *out = nullptr;
+    if (!ctxs || n < 1 || tune_iters < 0) return REC_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        rec_ctx* c = ctxs[i];
+        if (!c || c->stream != ctxs[0]->stream || c->device != ctxs[0]->device) return REC_EINVAL;
+        if (c->prm.storage != ctxs[0]->prm.storage || c->prm.fuse_iters == 0 ||
+            c->prm.tvl1_iters > 0 || c->prm.gap_every > 0)
+            return REC_EINVAL;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return REC_EINVAL;
+    }
+    if (!dev_workspace || ((uintptr_t)dev_workspace & (kAlign - 1))) return REC_EINVAL;
+    const size_t need = rec_batch_workspace_bytes(ctxs, n);
+    if (ws_bytes < need) return REC_ENOMEM;
+    rec_batch* b = new (std::nothrow) rec_batch();
+    if (!b) return REC_ENOMEM;
+    b->ctx.assign(ctxs, ctxs + n);
+    b->stream = ctxs[0]->stream;
+    b->storage = ctxs[0]->prm.storage;
+    char* base = (char*)dev_workspace;
+    b->d_desc[0] = (rec::StreamDesc*)base;
+    b->d_desc[1] = (rec::StreamDesc*)(base + batch_desc_bytes(n));
+    b->d_work = (int2*)(base + 2 * batch_desc_bytes(n));
+    b->work_cap = (int64_t)((ws_bytes - 2 * batch_desc_bytes(n)) / sizeof(int2));
+    for (int i = 0; i < n; ++i) {
+        const size_t np = (size_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
+        if (np > b->max_np) b->max_np = np;
+    }
+    for (int q = 0; q < 2; ++q) {
+        if (hipHostMalloc((void**)&b->h_desc[q], (size_t)n * sizeof(rec::StreamDesc),
+                          hipHostMallocDefault) != hipSuccess ||
+            hipEventCreateWithFlags(&b->copied[q], hipEventDisableTiming) != hipSuccess) {
+            rec_batch_destroy(b);
+            return REC_ENOMEM;
+        }
+    }
+    // default geometry: the automatic choice for the largest stream
+    int r, w, k;
+    const rec_ctx* big = ctxs[0];
+    for (int i = 1; i < n; ++i)
+        if ((int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H > (int64_t)big->fr.W * big->fr.H) big = ctxs[i];
+    choose_shape(&big->prm, &r, &w, &k);
+    if (!rec::batch_shape_supported(r, w)) {
+        r = 8;
+        w = 4;
+        if (k > 15) k = 15;
+    }
+    b->shape = Shape{r, w, k};
+    int rc = REC_OK;
+    // all streams' pending work must be on the stream before timing reads it
+    if (hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
+    if (!rc && tune_iters > 0) {
+        // autotuner: time every candidate geometry; keep the one that runs
+        // tune_iters iterations fastest (ceil(iters / K) launches)
+        double best = 1e300;
+        Shape pick = b->shape;
+        for (const Shape& sh : batch_candidates()) {
+            if (batch_tiles(ctxs, n, sh) > b->work_cap) continue;
+            b->shape = sh;
+            double us = 0.0;
+            rc = time_shape(b, 5, &us);
+            if (rc) break;
+            const double est = us * ((tune_iters + sh.k - 1) / sh.k);
+            if (est < best) {
+                best = est;
+                pick = sh;
+                b->tuned_us = us;
+            }
+        }
+        b->shape = pick;
+    }
+    if (!rc) rc = upload_work(b);
+    if (rc) {
+        rec_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return REC_OK;
+}
+
+int rec_batch_solve(rec_batch* b, int32_t iters) {
+    if (!b || iters < 1) return REC_EINVAL;
+    int rc;
+    // pushes the first launch cannot fold are scattered first
+    for (rec_ctx* c : b->ctx) {
+        const int64_t tiles = rec::fused_tiles(c->fr, b->shape.rows, b->shape.waves, b->shape.k);
+        if (c->deferred_events > kFoldMaxEvents || c->deferred_events * tiles > kFoldMaxWork) {
+            rc = flush_deferred(c);
+            if (rc) return rc;
+        }
+    }
+    const int q = b->parity;
+    if (b->copy_used[q] && hipEventSynchronize(b->copied[q]) != hipSuccess) return REC_EDEVICE;
+    bool fold = false;
+    fill_desc(b, b->h_desc[q], &fold);
+    const size_t n = b->ctx.size();
+    if (hipMemcpyAsync(b->d_desc[q], b->h_desc[q], n * sizeof(rec::StreamDesc),
+                       hipMemcpyHostToDevice, b->stream) != hipSuccess ||
+        hipEventRecord(b->copied[q], b->stream) != hipSuccess)
+        return REC_EDEVICE;
+    b->copy_used[q] = true;
+    b->parity ^= 1;
+    const int K = b->shape.k;
+    const int nl = (iters + K - 1) / K;
+    rec_ctx* c0 = b->ctx[0];
+    for (int li = 0; li < nl; ++li) {
+        const int m = iters / nl + (li < iters % nl ? 1 : 0);
+        int64_t work = 0;
+        if (c0->prof_on)
+            for (rec_ctx* c : b->ctx) work += (int64_t)c->fr.W * c->fr.H * m;
+        rc = timed(c0, 2, work, [&](rec::LaunchEv ev) {
+            return rec::launch_pd_batch(b->d_desc[q], b->d_work, b->nwork, m, K, li, fold && li == 0,
+                                        b->shape.rows, b->shape.waves, b->storage, b->stream, ev);
+        });
+        if (rc) return rc;
+    }
+    if (nl == 1 && hipSuccess != rec::launch_finish_batch(b->d_desc[q], (int)n, b->max_np, b->stream))
+        return REC_EDEVICE;
+    for (rec_ctx* c : b->ctx) {
+        c->cur ^= (nl & 1);
+        c->deferred.clear();
+        c->deferred_events = 0;
+        c->counts_dirty = false;
+        c->gap_samples = 0;
+    }
+    return REC_OK;
+}
+
+int rec_batch_config(const rec_batch* b, int32_t* rows, int32_t* waves, int32_t* kiters,
+                     double* launch_us) {
+    if (!b) return REC_EINVAL;
+    if (rows) *rows = b->shape.rows;
+    if (waves) *waves = b->shape.waves;
+    if (kiters) *kiters = b->shape.k;
+    if (launch_us) *launch_us = b->tuned_us;
+    return REC_OK;
+}
+
+int rec_batch_destroy(rec_batch* b) {
+    if (!b) return REC_OK;
+    int rc = REC_OK;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
+    for (int q = 0; q < 2; ++q) {
+        if (b->copied[q]) (void)hipEventDestroy(b->copied[q]);
+        if (b->h_desc[q]) (void)hipHostFree(b->h_desc[q]);
+    }
+    delete b;
+    return rc;
+}
+
+}  // extern "C"

@@ -72,7 +72,27 @@ EXPORTS = (
     "rec_default_params", "rec_check_params", "rec_workspace_bytes", "rec_check_events",
     "rec_init", "rec_push_events", "rec_solve", "rec_get_image", "rec_gap_history",
     "rec_sync", "rec_profile", "rec_profile_read", "rec_destroy", "rec_strerror",
+    "rec_batch_workspace_bytes", "rec_batch_init", "rec_batch_solve", "rec_batch_config",
+    "rec_batch_destroy", "rec_diff_workspace_bytes", "rec_diff_forward", "rec_diff_backward",
 )
+
+
+class rec_diff_desc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("batch", ctypes.c_int32),
+        ("iters", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
+        ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
+    ]
+
+
+class rec_diff_inputs(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in
+                ("u0", "p0", "npos", "nneg", "tx", "ty", "w", "theta")]
+
+
+class rec_diff_grads(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_void_p) for n in ("u0", "p0", "w", "theta")]
 
 _lib = None
 _vp = ctypes.c_void_p
@@ -116,6 +136,27 @@ def load() -> ctypes.CDLL:
     lib.rec_destroy.argtypes = [_vp]
     lib.rec_strerror.restype = ctypes.c_char_p
     lib.rec_strerror.argtypes = [ctypes.c_int]
+    lib.rec_batch_workspace_bytes.restype = ctypes.c_size_t
+    lib.rec_batch_workspace_bytes.argtypes = [_vp, ctypes.c_int32]
+    lib.rec_batch_init.restype = ctypes.c_int
+    lib.rec_batch_init.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_size_t, ctypes.c_int32,
+                                   ctypes.POINTER(_vp)]
+    lib.rec_batch_solve.restype = ctypes.c_int
+    lib.rec_batch_solve.argtypes = [_vp, ctypes.c_int32]
+    lib.rec_batch_config.restype = ctypes.c_int
+    lib.rec_batch_config.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 3 + [
+        ctypes.POINTER(ctypes.c_double)]
+    lib.rec_batch_destroy.restype = ctypes.c_int
+    lib.rec_batch_destroy.argtypes = [_vp]
+    D = ctypes.POINTER(rec_diff_desc)
+    lib.rec_diff_workspace_bytes.restype = ctypes.c_size_t
+    lib.rec_diff_workspace_bytes.argtypes = [D]
+    lib.rec_diff_forward.restype = ctypes.c_int
+    lib.rec_diff_forward.argtypes = [D, ctypes.POINTER(rec_diff_inputs), _vp, _vp, _vp,
+                                     ctypes.c_size_t, _vp]
+    lib.rec_diff_backward.restype = ctypes.c_int
+    lib.rec_diff_backward.argtypes = [D, ctypes.POINTER(rec_diff_inputs), _vp, _vp,
+                                      ctypes.POINTER(rec_diff_grads), _vp, ctypes.c_size_t, _vp]
     _lib = lib
     return lib
 
@@ -319,4 +360,193 @@ class Reconstructor:
         _check(rc, "rec_sync")
 
 
+def _ctx_array(ctxs):
+    arr = (_vp * len(ctxs))(*ctxs)
+    return arr
+
+
+def rec_batch_workspace_bytes(ctxs) -> int:
+    return load().rec_batch_workspace_bytes(_ctx_array(ctxs), len(ctxs))
+
+
+def rec_batch_init(ctxs, workspace_ptr: int, workspace_bytes: int, tune_iters: int):
+    h = _vp()
+    rc = load().rec_batch_init(_ctx_array(ctxs), len(ctxs), workspace_ptr, int(workspace_bytes),
+                               int(tune_iters), ctypes.byref(h))
+    return rc, h.value
+
+
+def rec_batch_solve(batch: int, iters: int) -> int:
+    return load().rec_batch_solve(batch, int(iters))
+
+
+def rec_batch_config(batch: int):
+    r, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    us = ctypes.c_double()
+    _check(load().rec_batch_config(batch, ctypes.byref(r), ctypes.byref(w), ctypes.byref(k),
+                                   ctypes.byref(us)), "rec_batch_config")
+    return r.value, w.value, k.value, us.value
+
+
+def rec_batch_destroy(batch: Optional[int]) -> int:
+    return load().rec_batch_destroy(batch)
+
+
+class Batch:
+    """Several Reconstructors solved together (one launch per block of
+    iterations for all of them)."""
+
+    def __init__(self, recs, tune_iters: int = 50):
+        import torch
+
+        self.recs = list(recs)
+        ctxs = [r.ctx for r in self.recs]
+        nbytes = rec_batch_workspace_bytes(ctxs)
+        if nbytes == 0:
+            raise RecError(REC_EINVAL, "rec_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.recs[0].device)
+        rc, h = rec_batch_init(ctxs, self.workspace.data_ptr(), nbytes, tune_iters)
+        _check(rc, "rec_batch_init")
+        self.handle = h
+
+    def solve(self, iters: int) -> None:
+        rc = rec_batch_solve(self.handle, iters)
+        for r in self.recs:
+            r._pending.clear()
+        _check(rc, "rec_batch_solve")
+
+    def config(self):
+        return rec_batch_config(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            rec_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 DEFAULT_STEP = 1.0 / math.sqrt(8.0 + 4.0 * math.sqrt(2.0))
+
+
+# ---------------------------------------------------------------------------
+# Differentiable unrolled solve
+# ---------------------------------------------------------------------------
+
+def rec_diff_desc_make(width: int, height: int, batch: int, iters: int, ckpt_every: int = 10,
+                       tau: float = DEFAULT_STEP, sigma: float = DEFAULT_STEP,
+                       u_min: float = 1.0, u_max: float = math.e) -> rec_diff_desc:
+    k = max(1, min(int(ckpt_every), max(int(iters), 1)))
+    return rec_diff_desc(int(width), int(height), int(batch), int(iters), k, 0, float(tau),
+                         float(sigma), float(u_min), float(u_max))
+
+
+def rec_diff_workspace_bytes(desc: rec_diff_desc) -> int:
+    return load().rec_diff_workspace_bytes(ctypes.byref(desc))
+
+
+def _diff_inputs(u0, p0, npos, nneg, tx, ty, w, theta) -> rec_diff_inputs:
+    return rec_diff_inputs(*[_addr(a) for a in (u0, p0, npos, nneg, tx, ty, w, theta)])
+
+
+def rec_diff_forward(desc: rec_diff_desc, inputs: rec_diff_inputs, u_out, p_out, workspace_ptr,
+                     workspace_bytes: int, stream_ptr) -> int:
+    return load().rec_diff_forward(ctypes.byref(desc), ctypes.byref(inputs), _addr(u_out),
+                                   _addr(p_out), workspace_ptr, int(workspace_bytes), stream_ptr)
+
+
+def rec_diff_backward(desc: rec_diff_desc, inputs: rec_diff_inputs, g_u, g_p,
+                      grads: rec_diff_grads, workspace_ptr, workspace_bytes: int,
+                      stream_ptr) -> int:
+    return load().rec_diff_backward(ctypes.byref(desc), ctypes.byref(inputs), _addr(g_u),
+                                    _addr(g_p), ctypes.byref(grads), workspace_ptr,
+                                    int(workspace_bytes), stream_ptr)
+
+
+def _unrolled_function():
+    import torch
+
+    class UnrolledPD(torch.autograd.Function):
+        """(u_K, p_K) of the unrolled loop; gradients by the library's reverse
+        sweep with checkpoints (rec_diff_forward / rec_diff_backward)."""
+
+        @staticmethod
+        def forward(ctx, u0, w, theta, p0, npos, nneg, tx, ty, desc):
+            dev = u0.device
+            B, H, W = desc.batch, desc.height, desc.width
+            f32 = lambda a: None if a is None else a.detach().to(dev, torch.float32).contiguous()
+            i32 = lambda a: a.detach().to(dev, torch.int32).contiguous()
+            t = dict(u0=f32(u0), w=f32(w), p0=f32(p0), npos=i32(npos), nneg=i32(nneg),
+                     tx=f32(tx), ty=f32(ty),
+                     theta=theta.detach().to(dev, torch.float64).contiguous())
+            if t["u0"].shape != (B, H, W) or (t["p0"] is not None and t["p0"].shape != (B, 3, H, W)):
+                raise ValueError("u0 must be [B, H, W] and p0 [B, 3, H, W]")
+            for k in ("w", "npos", "nneg", "tx", "ty"):
+                if t[k] is not None and t[k].shape != (B, H, W):
+                    raise ValueError(f"{k} must be [B, H, W]")
+            if t["theta"].shape != (3,):
+                raise ValueError("theta must hold (lambda, delta_pos, delta_neg)")
+            nbytes = rec_diff_workspace_bytes(desc)
+            if nbytes == 0:
+                raise RecError(REC_EINVAL, "rec_diff_workspace_bytes")
+            ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+            u_out = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+            p_out = torch.empty((B, 3, H, W), dtype=torch.float32, device=dev)
+            inputs = _diff_inputs(t["u0"], t["p0"], t["npos"], t["nneg"], t["tx"], t["ty"],
+                                  t["w"], t["theta"])
+            stream = torch.cuda.current_stream(dev).cuda_stream
+            with torch.cuda.device(dev):
+                _check(rec_diff_forward(desc, inputs, u_out, p_out, ws.data_ptr(), nbytes,
+                                        stream), "rec_diff_forward")
+            ctx.desc, ctx.ws, ctx.nbytes, ctx.t = desc, ws, nbytes, t
+            return u_out, p_out
+
+        @staticmethod
+        @torch.autograd.function.once_differentiable
+        def backward(ctx, g_u, g_p):
+            t, desc = ctx.t, ctx.desc
+            dev = t["u0"].device
+            B, H, W = desc.batch, desc.height, desc.width
+            need_u0, need_w, need_th, need_p0 = ctx.needs_input_grad[:4]
+            g_u = None if g_u is None else g_u.to(torch.float32).contiguous()
+            g_p = None if g_p is None else g_p.to(torch.float32).contiguous()
+            gu0 = torch.empty((B, H, W), dtype=torch.float32, device=dev) if need_u0 else None
+            gw = torch.empty((B, H, W), dtype=torch.float32, device=dev) if need_w else None
+            gp0 = torch.empty((B, 3, H, W), dtype=torch.float32, device=dev) if need_p0 else None
+            gth = torch.empty(3, dtype=torch.float64, device=dev) if need_th else None
+            grads = rec_diff_grads(_addr(gu0), _addr(gp0), _addr(gw), _addr(gth))
+            inputs = _diff_inputs(t["u0"], t["p0"], t["npos"], t["nneg"], t["tx"], t["ty"],
+                                  t["w"], t["theta"])
+            stream = torch.cuda.current_stream(dev).cuda_stream
+            with torch.cuda.device(dev):
+                _check(rec_diff_backward(desc, inputs, g_u, g_p, grads, ctx.ws.data_ptr(),
+                                         ctx.nbytes, stream), "rec_diff_backward")
+            return gu0, gw, gth, gp0, None, None, None, None, None
+
+    return UnrolledPD
+
+
+_UNROLLED = None
+
+
+def unrolled(u0, npos, nneg, tx, ty, theta, iters: int, w=None, p0=None, ckpt_every: int = 10,
+             tau: float = DEFAULT_STEP, sigma: float = DEFAULT_STEP, u_min: float = 1.0,
+             u_max: float = math.e):
+    """K = iters primal-dual iterations on a batch of blocks, differentiable
+    in u0, w, theta = (lambda, delta_pos, delta_neg) and p0.
+
+    u0, npos, nneg, tx, ty, w: [B, H, W] (w None = all 1); p0: [B, 3, H, W]
+    (None = 0); theta: float64 tensor of 3 on the device.  Returns
+    (u_K [B, H, W], p_K [B, 3, H, W]) as float32 device tensors."""
+    global _UNROLLED
+    if _UNROLLED is None:
+        _UNROLLED = _unrolled_function()
+    if u0.dim() != 3:
+        raise ValueError("u0 must be [B, H, W]")
+    B, H, W = u0.shape
+    desc = rec_diff_desc_make(W, H, B, iters, ckpt_every, tau, sigma, u_min, u_max)
+    return _UNROLLED.apply(u0, w, theta, p0, npos, nneg, tx, ty, desc)

@@ -147,3 +147,50 @@ def test_null_context_calls():
     assert rec.rec_solve(None, 5)[0] == rec.REC_EINVAL
     assert rec.rec_sync(None) == rec.REC_EINVAL
     assert rec.rec_destroy(None) == rec.REC_OK
+
+
+def _diff_desc(**kw):
+    d = rec.rec_diff_desc_make(70, 37, 2, 30, 7)
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_diff_desc_layout_and_workspace():
+    import ctypes
+    assert ctypes.sizeof(rec.rec_diff_desc) == 56
+    assert ctypes.sizeof(rec.rec_diff_inputs) == 64
+    assert ctypes.sizeof(rec.rec_diff_grads) == 32
+    d = _diff_desc()
+    a = lambda x: (x + 255) // 256 * 256
+    plane = a(70 * 37 * 2 * 4)
+    C = math.ceil(30 / 7)
+    blocks = 2 * 10 * 2  # ceil(70/64) x ceil(37/4) x images
+    want = plane * (1 + 4 * (C + 1) + 4 * (7 - 1) + 7) + a(blocks * 3 * 8)
+    assert rec.rec_diff_workspace_bytes(d) == want
+
+
+@pytest.mark.parametrize("field,value", [
+    ("width", 0), ("height", 70000), ("batch", 0), ("iters", -1), ("ckpt_every", 0),
+    ("ckpt_every", 31), ("reserved", 1), ("tau", 0.0), ("sigma", float("nan")),
+    ("tau", 0.5), ("u_min", 0.0), ("u_max", 0.5),
+])
+def test_diff_bad_desc(field, value):
+    d = _diff_desc(**{field: value})
+    assert rec.rec_diff_workspace_bytes(d) == 0
+    inp = rec.rec_diff_inputs(0x1000, None, 0x1000, 0x1000, 0x1000, 0x1000, None, 0x1000)
+    assert rec.rec_diff_forward(d, inp, 0x1000, None, 0x10000, 1 << 30, None) == rec.REC_EINVAL
+
+
+def test_diff_rejects_without_touching_device():
+    d = _diff_desc()
+    n = rec.rec_diff_workspace_bytes(d)
+    inp = rec.rec_diff_inputs(0x1000, None, 0x1000, 0x1000, 0x1000, 0x1000, None, 0x1000)
+    missing = rec.rec_diff_inputs(0x1000, None, 0x1000, None, 0x1000, 0x1000, None, 0x1000)
+    assert rec.rec_diff_forward(d, missing, 0x1000, None, 0x10000, n, None) == rec.REC_EINVAL
+    assert rec.rec_diff_forward(d, inp, None, None, 0x10000, n, None) == rec.REC_EINVAL
+    assert rec.rec_diff_forward(d, inp, 0x1000, None, 0x10001, n, None) == rec.REC_EINVAL
+    assert rec.rec_diff_forward(d, inp, 0x1000, None, 0x10000, n - 1, None) == rec.REC_ENOMEM
+    g = rec.rec_diff_grads(None, None, None, None)
+    assert rec.rec_diff_backward(d, inp, None, None, g, 0x10000, n - 1, None) == rec.REC_ENOMEM
+    assert rec.rec_diff_backward(d, inp, None, None, g, None, n, None) == rec.REC_EINVAL

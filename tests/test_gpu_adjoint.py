@@ -1,0 +1,209 @@
+"""Differentiable unrolled solve on the GPU (rec_diff_forward / _backward
+through the torch.autograd.Function) against the FP64 autograd reference
+and central finite differences of the FP64 C oracle."""
+import math
+
+import numpy as np
+import pytest
+
+import evgen
+import oracle
+from oracle import autodiff
+from paper_1607_06283_amd import rec
+
+pytestmark = pytest.mark.gpu
+
+LAM, DPOS, DNEG = 90.0, 0.2, 0.25
+GRAD_RTOL = 1e-3
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _dev(inp):
+    torch = _torch()
+    return {k: torch.from_numpy(v).cuda() for k, v in inp.items()}
+
+
+def _rel(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _gpu_grads(inp, iters, ckpt, p0=None, seed=5, use_w=True):
+    """Forward + backward on the GPU of J = <gu, u_K> + <gp, p_K>."""
+    torch = _torch()
+    d = _dev(inp)
+    B, H, W = inp["u0"].shape
+    rng = np.random.default_rng(seed)
+    gu = rng.standard_normal((B, H, W))
+    gp = rng.standard_normal((B, 3, H, W))
+    u0 = d["u0"].clone().requires_grad_()
+    w = d["w"].clone().requires_grad_() if use_w else None
+    th = torch.tensor([LAM, DPOS, DNEG], dtype=torch.float64, device="cuda", requires_grad=True)
+    p0t = None if p0 is None else torch.from_numpy(p0.astype(np.float32)).cuda().requires_grad_()
+    print(f"gpu diff B={B} H={H} W={W} iters={iters} ckpt={ckpt}", flush=True)
+    u, p = rec.unrolled(u0, d["npos"], d["nneg"], d["tx"], d["ty"], th, iters, w=w, p0=p0t,
+                        ckpt_every=ckpt)
+    J = (torch.from_numpy(gu).cuda() * u.double()).sum() + \
+        (torch.from_numpy(gp).cuda() * p.double()).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    out = dict(u=u.detach().cpu().numpy(), p=p.detach().cpu().numpy(),
+               u0=u0.grad.cpu().numpy(), theta=th.grad.cpu().numpy(), gu=gu, gp=gp)
+    if use_w:
+        out["w"] = w.grad.cpu().numpy()
+    if p0t is not None:
+        out["p0"] = p0t.grad.cpu().numpy()
+    return out
+
+
+def _ref_grads(inp, iters, gu, gp, p0=None, use_w=True):
+    import torch
+    t = lambda a: torch.from_numpy(np.asarray(a, np.float64))
+    u0 = t(inp["u0"]).requires_grad_()
+    w = t(inp["w"]).requires_grad_() if use_w else None
+    th = torch.tensor([LAM, DPOS, DNEG], dtype=torch.float64, requires_grad=True)
+    p0t = None if p0 is None else t(p0.astype(np.float32)).requires_grad_()
+    u, p = autodiff.unrolled(u0, t(inp["npos"]), t(inp["nneg"]), t(inp["tx"]), t(inp["ty"]),
+                             w, th[0], th[1], th[2], iters, p0=p0t)
+    ((t(gu) * u).sum() + (t(gp) * p).sum()).backward()
+    out = dict(u=u.detach().numpy(), p=p.detach().numpy(), u0=u0.grad.numpy(),
+               theta=th.grad.numpy())
+    if use_w:
+        out["w"] = w.grad.numpy()
+    if p0t is not None:
+        out["p0"] = p0t.grad.numpy()
+    return out
+
+
+@pytest.fixture(scope="module")
+def ragged():
+    # 70 columns (one full 64-wide tile and a ragged one), 37 rows (ragged
+    # against 4-row workgroups), two images
+    return evgen.diff_inputs(21, 2, 37, 70)
+
+
+@pytest.mark.parametrize("ckpt", [7, 30])
+def test_gradients_match_fp64_autograd(ragged, ckpt):
+    rng = np.random.default_rng(9)
+    p0 = 0.05 * rng.standard_normal((2, 3, 37, 70))
+    g = _gpu_grads(ragged, 30, ckpt, p0=p0)
+    r = _ref_grads(ragged, 30, g["gu"], g["gp"], p0=p0)
+    assert np.abs(g["u"] - r["u"]).max() <= 1e-4
+    for k in ("u0", "w", "p0"):
+        e = _rel(g[k], r[k])
+        print(f"  d/d{k}: relative error {e:.2e}")
+        assert e <= GRAD_RTOL, k
+    for i, name in enumerate(("lambda", "dpos", "dneg")):
+        e = abs(g["theta"][i] - r["theta"][i]) / abs(r["theta"][i])
+        print(f"  d/d{name}: {g['theta'][i]:.6e} vs {r['theta'][i]:.6e} ({e:.2e})")
+        assert e <= GRAD_RTOL, name
+
+
+def test_checkpoint_interval_does_not_change_bits(ragged):
+    """Recomputed segments reproduce the forward bit for bit, so every
+    checkpoint interval gives the same gradients."""
+    outs = [_gpu_grads(ragged, 24, k) for k in (1, 5, 24)]
+    for o in outs[1:]:
+        for key in ("u", "p", "u0", "w", "theta"):
+            assert np.array_equal(o[key], outs[0][key]), key
+
+
+def test_scalar_gradients_match_finite_differences(ragged):
+    """dJ/d(lambda, dpos, dneg) vs central differences of the FP64 C oracle."""
+    iters = 20
+    g = _gpu_grads(ragged, iters, 10, use_w=False)
+    B, H, W = ragged["u0"].shape
+
+    def J(lam, dpos, dneg):
+        tot = 0.0
+        for b in range(B):
+            o = oracle.Oracle(oracle.Params(W, H, lam=lam, delta_pos=dpos, delta_neg=dneg))
+            u = ragged["u0"][b].astype(np.float64)
+            o.set_state(u)
+            o.set_data(u * np.exp(dpos * ragged["npos"][b] - dneg * ragged["nneg"][b]),
+                       ragged["tx"][b].astype(np.float64), ragged["ty"][b].astype(np.float64))
+            o.iterate(iters)
+            tot += (g["gu"][b] * o.u).sum() + (g["gp"][b] * o.p).sum()
+            o.close()
+        return tot
+
+    base = [LAM, DPOS, DNEG]
+    for i, name in enumerate(("lambda", "dpos", "dneg")):
+        h = 1e-6 * max(abs(base[i]), 1.0)
+        up, dn = list(base), list(base)
+        up[i] += h
+        dn[i] -= h
+        fd = (J(*up) - J(*dn)) / (2 * h)
+        e = abs(g["theta"][i] - fd) / abs(fd)
+        print(f"  d/d{name}: gpu {g['theta'][i]:.6e} fd {fd:.6e} ({e:.2e})")
+        assert e <= GRAD_RTOL, name
+
+
+def test_forward_equals_stream_solve_bitwise():
+    """With w = 1 and p0 = 0 the unrolled forward is the library's solve of
+    the first block: same f, same metric, same bits."""
+    torch = _torch()
+    spec = evgen.StreamSpec(96, 70, 31, duration_us=30_000)
+    ev = evgen.generate(spec).events
+    blk = ev.slice(0, 3000)
+    r = rec.Reconstructor(96, 70, fuse_iters=0)
+    r.push(blk.t, blk.x, blk.y, blk.p)
+    npos, nneg = r.image(rec.REC_COUNT_POS), r.image(rec.REC_COUNT_NEG)
+    r.solve(25)
+    u_ref, tx, ty = r.image(rec.REC_U), r.image(rec.REC_TX), r.image(rec.REC_TY)
+    u0 = torch.full((1, 70, 96), r.prm.u_init, dtype=torch.float32, device="cuda")
+    th = torch.tensor([r.prm.lambda_, r.prm.delta_pos, r.prm.delta_neg], dtype=torch.float64,
+                      device="cuda")
+    c = lambda a: torch.from_numpy(np.ascontiguousarray(a)[None]).cuda()
+    u, p = rec.unrolled(u0, c(npos), c(nneg), c(tx), c(ty), th, 25, ckpt_every=10,
+                        tau=r.prm.tau, sigma=r.prm.sigma, u_min=r.prm.u_min, u_max=r.prm.u_max)
+    assert np.array_equal(u[0].cpu().numpy(), u_ref)
+    assert np.array_equal(p[0].cpu().numpy(), r.image(rec.REC_STATE_P))
+    r.close()
+
+
+def test_log_intensity_loss_through_autograd(ragged):
+    """The training loss 1/2 sum (log u_K - L)^2 differentiated end to end by
+    torch (its own log and square, the library's reverse sweep)."""
+    T = _torch()
+    d = _dev(ragged)
+    L = np.log(ragged["u0"].astype(np.float64)) + 0.05
+    iters = 25
+    th = T.tensor([LAM, DPOS, DNEG], dtype=T.float64, device="cuda", requires_grad=True)
+    w = d["w"].clone().requires_grad_()
+    u, _ = rec.unrolled(d["u0"], d["npos"], d["nneg"], d["tx"], d["ty"], th, iters, w=w)
+    loss = 0.5 * ((T.log(u.double()) - T.from_numpy(L).cuda()) ** 2).sum()
+    loss.backward()
+    t = lambda a: T.from_numpy(np.asarray(a, np.float64))
+    thr = T.tensor([LAM, DPOS, DNEG], dtype=T.float64, requires_grad=True)
+    wr = t(ragged["w"]).requires_grad_()
+    ur, _ = autodiff.unrolled(t(ragged["u0"]), t(ragged["npos"]), t(ragged["nneg"]),
+                              t(ragged["tx"]), t(ragged["ty"]), wr, thr[0], thr[1], thr[2], iters)
+    lr = 0.5 * ((T.log(ur) - t(L)) ** 2).sum()
+    lr.backward()
+    assert abs(loss.item() - lr.item()) <= 1e-4 * abs(lr.item())
+    assert _rel(th.grad.cpu().numpy(), thr.grad.numpy()) <= GRAD_RTOL
+    assert _rel(w.grad.cpu().numpy(), wr.grad.numpy()) <= GRAD_RTOL
+
+
+def test_zero_iterations_pass_gradients_through(ragged):
+    g = _gpu_grads(ragged, 0, 1, p0=np.zeros((2, 3, 37, 70)))
+    assert np.array_equal(g["u"], ragged["u0"])
+    assert np.allclose(g["u0"], g["gu"].astype(np.float32), rtol=0, atol=0)
+    assert np.allclose(g["p0"], g["gp"].astype(np.float32), rtol=0, atol=0)
+    assert not g["w"].any() and not g["theta"].any()
+
+
+def test_bad_descriptors_rejected():
+    torch = _torch()
+    d = _dev(evgen.diff_inputs(1, 1, 8, 8))
+    th = torch.tensor([LAM, DPOS, DNEG], dtype=torch.float64, device="cuda")
+    with pytest.raises(rec.RecError):
+        rec.unrolled(d["u0"], d["npos"], d["nneg"], d["tx"], d["ty"], th, 5, tau=1.0, sigma=1.0)

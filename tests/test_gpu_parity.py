@@ -37,7 +37,8 @@ def c1():
 def oracle_params(prm: rec.rec_params) -> oracle.Params:
     return oracle.Params(prm.width, prm.height, lam=prm.lambda_, delta_pos=prm.delta_pos,
                          delta_neg=prm.delta_neg, u_min=prm.u_min, u_max=prm.u_max, tau=prm.tau,
-                         sigma=prm.sigma, time_unit_us=prm.time_unit_us, u_init=prm.u_init)
+                         sigma=prm.sigma, time_unit_us=prm.time_unit_us, u_init=prm.u_init,
+                         tvl1_iters=prm.tvl1_iters, tvl1_lambda=prm.tvl1_lambda)
 
 
 def make(W, H, u0=None, **kw):
@@ -440,3 +441,54 @@ def test_denoising_flattens_noise_spikes(noisy):
     big_raw = (np.abs(raw.image(rec.REC_TX)) > 5.0).sum()
     big_den = (np.abs(den.image(rec.REC_TX)) > 5.0).sum()
     assert big_den < 0.5 * big_raw
+
+
+# --------------------------------------------------------------------------
+# Batched solves of several streams
+# --------------------------------------------------------------------------
+
+BATCH_SHAPES = [(128, 128), (240, 180), (67, 45), (346, 260), (1, 37), (200, 7)]
+
+
+def test_batch_equals_individual_solves():
+    """A batched solve gives each stream the same bits as solving it alone
+    with the same iterations per launch; the autotuner leaves state alone."""
+    import torch
+    rng = np.random.default_rng(4)
+    streams = []
+    for (W, H) in BATCH_SHAPES:
+        n = int(rng.integers(200, 3000))
+        streams.append(_random_stream(W, H, 3 * n, seed=W * 31 + H))
+    recs = [rec.Reconstructor(W, H) for (W, H) in BATCH_SHAPES]
+    u_before = [r.image(rec.REC_U) for r in recs]
+    batch = rec.Batch(recs, tune_iters=50)
+    rows, waves, K, us = batch.config()
+    assert rows * waves > 2 * K and us > 0
+    for r, u in zip(recs, u_before):
+        assert np.array_equal(r.image(rec.REC_U), u)
+    solo = [rec.Reconstructor(W, H, fuse_iters=K) for (W, H) in BATCH_SHAPES]
+    for step in range(3):
+        for (t, x, y, p), r, s in zip(streams, recs, solo):
+            n = len(t) // 3
+            sl = slice(step * n, (step + 1) * n)
+            ev = evgen.Events(t[sl], x[sl], y[sl], p[sl], np.zeros(n, np.uint8))
+            r.push(*device_events(ev), on_device=True)
+            s.push(*device_events(ev), on_device=True)
+        batch.solve(37)
+        for s in solo:
+            s.solve(37)
+    for r, s in zip(recs, solo):
+        assert np.array_equal(r.image(rec.REC_U), s.image(rec.REC_U))
+        assert np.array_equal(r.image(rec.REC_STATE_P), s.image(rec.REC_STATE_P))
+        assert np.array_equal(r.image(rec.REC_T_LAST), s.image(rec.REC_T_LAST))
+    batch.close()
+
+
+def test_batch_rejects_mixed_contexts():
+    a = rec.Reconstructor(64, 32)
+    b = rec.Reconstructor(64, 32, storage=rec.REC_STORE_F16)
+    c = rec.Reconstructor(64, 32, fuse_iters=0)
+    for group in ([a, b], [a, c], [a, a]):
+        with pytest.raises(rec.RecError) as e:
+            rec.Batch(group, tune_iters=0)
+        assert e.value.code == rec.REC_EINVAL
