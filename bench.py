@@ -47,6 +47,7 @@ WORKLOADS = {
     "hd720": (1280, 720, 20000, 100),
     "probe": (5120, 5760, 20000, 50),
     "streams64": (0, 0, 0, 50),
+    "diff16": (346, 260, 2000, 100),
 }
 #   streams64  64 independent cameras: 16 each of 128x128, 240x180, 346x260 and
 #          640x480 (7.3 Mpx, ~440 MB of state: beyond the Infinity Cache);
@@ -297,7 +298,110 @@ def main_streams64(args):
     print(json.dumps(out), flush=True)
 
 
+# Algorithmic bytes per pixel-iteration of the differentiable solve's kernels
+# (FP32 planes): forward primal (u, p, f, tx, ty, w read; u written) 36,
+# forward dual (u twice, p, tx, ty read; p written) 40; reverse dual (u
+# twice, p, tx, ty, q, ub read; q written) 56; reverse primal (u, p, f, tx,
+# ty, w, q, uh, two sums read; ub, uh, two sums written) 72.
+DIFF_FWD_B = 76
+DIFF_REV_B = 128
+
+
+def main_diff16(args):
+    """16 x 346x260 blocks of 2000 events, 100 unrolled iterations, loss
+    1/2 sum (log u_100 - L_gt(t_end))^2, checkpoints every 10: forward +
+    backward against the library's batched forward solve of the same size."""
+    import torch
+    import evgen
+    from paper_1607_06283_amd import rec
+
+    K, CK, W, H, NB = 100, 10, 346, 260, 16
+    steps = max(1, min(args.steps, 20))
+    warmup = max(1, min(args.warmup, 3))
+    log("bench: diff16 inputs")
+    blocks = evgen.diff_blocks(500, NB, W, H, 2000)
+    dev = torch.device("cuda", 0)
+    npos, nneg, tx, ty = [], [], [], []
+    recs = []
+    for spec, blk, _, _ in blocks:
+        r = rec.Reconstructor(W, H)
+        r.push(blk.t, blk.x, blk.y, blk.p)
+        npos.append(r.image(rec.REC_COUNT_POS))
+        nneg.append(r.image(rec.REC_COUNT_NEG))
+        r.solve(1)
+        tx.append(r.image(rec.REC_TX))
+        ty.append(r.image(rec.REC_TY))
+        recs.append(r)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(np.stack(a))).to(dev)
+    npos, nneg, tx, ty = T(npos), T(nneg), T(tx), T(ty)
+    u0 = T([np.exp(b[2]).astype(np.float32) for b in blocks])
+    L = T([b[3] for b in blocks])
+    theta = torch.tensor([90.0, 0.2, 0.2], dtype=torch.float64, device=dev, requires_grad=True)
+    w = torch.ones((NB, H, W), dtype=torch.float32, device=dev, requires_grad=True)
+    out = {}
+
+    def fwd_bwd():
+        theta.grad = None
+        w.grad = None
+        u, _ = rec.unrolled(u0, npos, nneg, tx, ty, theta, K, w=w, ckpt_every=CK)
+        loss = 0.5 * ((torch.log(u.double()) - L) ** 2).sum()
+        loss.backward()
+        out["loss"] = loss
+
+    def fwd():
+        with torch.no_grad():
+            rec.unrolled(u0, npos, nneg, tx, ty, theta, K, w=w, ckpt_every=CK)
+
+    batch = rec.Batch(recs, tune_iters=K)
+
+    def plain():
+        batch.solve(K)
+
+    def timeit(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    log("bench: diff16 forward+backward")
+    t_fb = timeit(fwd_bwd)
+    t_f = timeit(fwd)
+    log("bench: diff16 plain batched forward")
+    t_p = timeit(plain)
+    g_th = theta.grad.cpu().numpy()
+    px = NB * W * H
+    C = math.ceil(K / CK)
+    bytes_fb = px * (K * DIFF_FWD_B + (K - C) * DIFF_FWD_B + K * DIFF_REV_B)
+    achieved = bytes_fb / t_fb / 1e9
+    res = {
+        "metric": METRIC, "value": round(px * K / t_fb / 1e6, 2), "unit": "PD iter*Mpix/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(t_fb * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT["diff16"], "images": NB, "width": W, "height": H,
+                   "iters": K, "ckpt_every": CK},
+        "fwd_bwd_ms": round(t_fb * 1e3, 3), "diff_fwd_ms": round(t_f * 1e3, 3),
+        "plain_fwd_ms": round(t_p * 1e3, 3), "fwd_bwd_over_plain": round(t_fb / t_p, 2),
+        "loss": float(out["loss"].item()),
+        "grad_theta": [float(v) for v in g_th],
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "all kernels of forward + reverse sweep (wall clock)"},
+    }
+    batch.close()
+    for r in recs:
+        r.close()
+    print(json.dumps(res), flush=True)
+
+
 WORKLOAD_TEXT = {
+    "diff16": "16 blocks of 2000 events from 346x260 streams (seeds 500-515), 100 unrolled FP32 "
+              "primal-dual iterations from u0 = exp(L_gt(t0)), loss 1/2 sum (log u - L_gt)^2, "
+              "gradients for lambda, Delta+, Delta- and per-pixel weights, checkpoints every 10",
     "streams64": "64 cameras (16 each of 128x128, 240x180, 346x260, 640x480), rates log-uniform "
                  "in [1e5, 5e6] events/s, blocks log-uniform in [200, 5000] events, uniform random "
                  "events, 50 FP32 primal-dual iterations per block, all cameras in one batched "
@@ -343,6 +447,8 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.workload == "diff16":
+        return main_diff16(args)
     if args.workload == "streams64":
         return main_streams64(args)
     need = args.warmup + args.steps

@@ -268,7 +268,7 @@ def hd720(seed: int = 3, duration_us: int = 500_000, rate: float = 2e7):
     return s, 20000, (len(s.events) + 19999) // 20000, 100
 
 
-def diff_inputs(seed: int, batch: int, height: int, width: int, iters_hint: int = 0) -> dict:
+def diff_inputs(seed: int, batch: int, height: int, width: int) -> dict:
     """Random inputs of the differentiable unrolled solve (no method
     arithmetic here): a smooth initial image u0 inside (1, e), small signed
     event counts, a smooth time-surface slope field (tx, ty) with a little
@@ -294,3 +294,24 @@ def diff_inputs(seed: int, batch: int, height: int, width: int, iters_hint: int 
     w = rng.uniform(0.5, 1.5, fired.shape).astype(np.float32)
     return {"u0": u0, "npos": npos.astype(np.int32), "nneg": nneg.astype(np.int32),
             "tx": tx, "ty": ty, "w": w}
+
+
+def diff_blocks(seed0: int = 500, n: int = 16, width: int = 346, height: int = 260,
+                events: int = 2000):
+    """n independent 346x260 streams (seeds seed0 ...), the first `events`
+    events of each: for a training batch of the differentiable solve.
+    Returns a list of (spec, block, L_start, L_end): the ground-truth
+    log-intensity frames at the stream start and at the block's last event."""
+    out = []
+    for i in range(n):
+        dur = 20000
+        while True:
+            spec = StreamSpec(width, height, seed0 + i, duration_us=dur, speed_px_s=200.0)
+            ev = generate(spec).events
+            if len(ev) >= events:
+                break
+            dur *= 2
+        blk = ev.slice(0, events)
+        t_end = int(blk.t[-1]) - spec.t0_us
+        out.append((spec, blk, frame(spec, 0), frame(spec, t_end)))
+    return out

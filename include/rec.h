@@ -227,8 +227,8 @@ size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n);
  * tune_iters > 0 an autotuner times every candidate tile geometry (rows
  * per lane, wavefronts, iterations per launch) on the streams' current
  * state without changing it, and keeps the one that runs tune_iters
- * iterations fastest (synchronises); with 0 the automatic geometry of the
- * largest stream is used. */
+ * iterations fastest (synchronises); with 0 the automatic geometry for a
+ * frame of the batch's total pixel count is used. */
 int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t ws_bytes,
                    int32_t tune_iters, rec_batch** out);
 

@@ -107,7 +107,7 @@ __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_le
                                         const Coef& c, float tau, float umin, float umax) {
     float r;
     const float un = prox_root(u, qx, qy, qx_left, qy_up, c, tau, r);
-    return __builtin_fminf(__builtin_fmaxf(un, umin), umax);
+    return __builtin_amdgcn_fmed3f(un, umin, umax);  // clamp (umin <= umax, un not NaN)
 }
 
 // Over-relaxed primal 2 u_{k+1} - u_k.

@@ -205,8 +205,7 @@ int flush_deferred(rec_ctx* c) {
 // latency, so they take thin tiles (many workgroups) and long launches;
 // large frames are limited by HBM and VALU, so they take taller tiles and
 // short launches (less halo recomputation).
-void choose_shape(const rec_params* prm, int* rows, int* waves, int* kiters) {
-    const int64_t np = (int64_t)prm->width * prm->height;
+void choose_shape(const rec_params* prm, int64_t np, int* rows, int* waves, int* kiters) {
     int r = prm->tile_rows, w = prm->tile_waves, k;
     if (np <= 250000) {
         if (!r) { r = 2; w = 16; }
@@ -332,7 +331,7 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     c->kc.umax = (float)prm->u_max;
     c->stream = (hipStream_t)hip_stream;
     c->cur = 0;
-    choose_shape(prm, &c->rows, &c->waves, &c->kmax);
+    choose_shape(prm, (int64_t)prm->width * prm->height, &c->rows, &c->waves, &c->kmax);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return REC_EDEVICE;
@@ -898,12 +897,12 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
             return REC_ENOMEM;
         }
     }
-    // default geometry: the automatic choice for the largest stream
+    // default geometry: the automatic choice for the batch's total pixel
+    // count (the launches cover every stream's tiles at once)
     int r, w, k;
-    const rec_ctx* big = ctxs[0];
-    for (int i = 1; i < n; ++i)
-        if ((int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H > (int64_t)big->fr.W * big->fr.H) big = ctxs[i];
-    choose_shape(&big->prm, &r, &w, &k);
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) total += (int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
+    choose_shape(&ctxs[0]->prm, total, &r, &w, &k);
     if (!rec::batch_shape_supported(r, w)) {
         r = 8;
         w = 4;

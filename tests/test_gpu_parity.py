@@ -381,6 +381,43 @@ def test_reduced_storage_error_vs_oracle(c1, storage, bound):
     assert worst <= bound
 
 
+@pytest.fixture(scope="module")
+def hd720_oracle():
+    """First 10 blocks of the 1280x720 stream (20000 events, 100 iterations
+    each) and the FP64 oracle's image after every block."""
+    s, bs, _, iters = evgen.hd720(duration_us=15_000)
+    blocks = evgen.batches(s.events, bs)[:10]
+    o = oracle.Oracle(oracle.Params(1280, 720))
+    us = []
+    for b in blocks:
+        o.push_events(b)
+        o.solve(iters)
+        us.append(o.u)
+    o.close()
+    return blocks, iters, us
+
+
+@pytest.mark.parametrize("storage,bound", [(rec.REC_STORE_F32, 1e-4), (rec.REC_STORE_F16, 2e-3),
+                                           (rec.REC_STORE_BF16, 2e-2)])
+def test_hd720_precision_vs_oracle(hd720_oracle, storage, bound):
+    """1280x720 at 2e7 events/s, 100 iterations per block: max-abs and mean-abs
+    error of u against the FP64 oracle over the first 10 blocks, per storage
+    of the dual field and time differences."""
+    blocks, iters, us = hd720_oracle
+    r = rec.Reconstructor(1280, 720, storage=storage)
+    worst, mean = 0.0, 0.0
+    for b, uo in zip(blocks, us):
+        r.push(*device_events(b), on_device=True)
+        r.solve(iters)
+        d = np.abs(r.image(rec.REC_U).astype(np.float64) - uo)
+        worst = max(worst, float(d.max()))
+        mean = max(mean, float(d.mean()))
+    r.close()
+    print(f"hd720 storage={storage}: max-abs {worst:.3e}, worst mean-abs {mean:.3e} "
+          f"over 10 blocks")
+    assert worst <= bound
+
+
 @pytest.mark.parametrize("storage", [rec.REC_STORE_F16, rec.REC_STORE_BF16])
 def test_reduced_storage_tile_independent(storage):
     """With the same iterations per launch, the 16-bit form gives the same
