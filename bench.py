@@ -33,6 +33,30 @@ METRIC = "PD iter*Mpix/s and events/s at 50 it/batch; fwd+bwd vs plain; %HBM BW"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_PX_ITER = 44  # u 4 + p 12 + f 4 + tx/ty 8 read, u 4 + p 12 written
 BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
+# HBM traffic of the fused kernel from rocprofv3 --pmc runs (FETCH_SIZE and
+# WRITE_SIZE in separate runs, KiB per dispatch averaged over the kernel's
+# dispatches), scaled by the same counters' reading for a 256 MiB device
+# copy: FETCH_SIZE read 131084 KiB and WRITE_SIZE 262144 KiB for 262144 KiB
+# moved each way, so fetched bytes = 2 x 1024 x FETCH_SIZE and written bytes
+# = 1024 x WRITE_SIZE.  Each entry holds for the kernel sources it was taken
+# with (hash of kernels.hip, pd_math.h, kernels.h); after a change the bench
+# reports traffic null until the counters are taken again.
+TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h")
+MEASURED_TRAFFIC = {
+    # (workload, storage): (source hash, fetched bytes, written bytes) per launch
+    ("davis240", "f32"): ("714e7be292ad542f", 2 * 1024 * 1231.3, 1024 * 889.2),
+    ("probe", "f32"): ("714e7be292ad542f", 2 * 1024 * 536217.7, 1024 * 513659.6),
+}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_1607_06283_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 W_, H_ = 240, 180
 EVENTS_PER_BATCH = 1000
 ITERS = 50
@@ -489,13 +513,21 @@ def main():
         pd_launches = int(prof.launches[2])
         bpi = BYTES_PER_PX_ITER if storage == 0 else BYTES_PER_PX_ITER_16
         achieved = bpi * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
+        avg_us = pd_ms / pd_launches * 1e3
+        traffic, tb = None, None
+        m = MEASURED_TRAFFIC.get((args.workload, args.storage))
+        if m and args.fuse == -1 and not args.rows and m[0] == kernel_source_hash():
+            tb = m[1] + m[2]
+            traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
         out["roofline"] = {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "kernel": "k_pd_fused" if args.fuse else "k_primal+k_dual",
-            "avg_launch_us": round(pd_ms / pd_launches * 1e3, 3),
+            "avg_launch_us": round(avg_us, 3),
             "launches": pd_launches,
             "bytes_per_px_iter": bpi,
+            "algorithmic_bytes_per_launch": round(bpi * prof.pd_pixel_iters / pd_launches),
+            "hbm_bytes_per_launch": None if tb is None else round(tb),
         }
         out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),
                             "pd": round(pd_ms, 3)}
