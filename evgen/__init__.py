@@ -268,10 +268,12 @@ def hd720(seed: int = 3, duration_us: int = 500_000, rate: float = 2e7):
     return s, 20000, (len(s.events) + 19999) // 20000, 100
 
 
-def diff_inputs(seed: int, batch: int, height: int, width: int) -> dict:
+def diff_inputs(seed: int, batch: int, height: int, width: int, levels=(0.25, 0.75),
+                max_count: int = 3) -> dict:
     """Random inputs of the differentiable unrolled solve (no method
-    arithmetic here): a smooth initial image u0 inside (1, e), small signed
-    event counts, a smooth time-surface slope field (tx, ty) with a little
+    arithmetic here): a smooth initial image u0 = exp(level), level in
+    `levels` (inside (0, 1), so u0 is inside (1, e)), signed event counts up
+    to max_count, a smooth time-surface slope field (tx, ty) with a little
     noise, and data weights w around 1.  Float planes are float32 so the GPU
     and the FP64 references see identical values.  Shapes [batch, H, W]."""
     rng = np.random.default_rng(seed)
@@ -285,10 +287,11 @@ def diff_inputs(seed: int, batch: int, height: int, width: int) -> dict:
                 acc[b] += np.sin(kx * xx + ky * yy + ph)
         acc = (acc - acc.min()) / max(acc.max() - acc.min(), 1e-12)
         return lo + (hi - lo) * acc
-    u0 = np.exp(smooth(0.25, 0.75)).astype(np.float32)
+    u0 = np.exp(smooth(*levels)).astype(np.float32)
     fired = rng.random((batch, height, width)) < 0.3
-    npos = np.where(fired & (rng.random(fired.shape) < 0.5), rng.integers(1, 4, fired.shape), 0)
-    nneg = np.where(fired & (npos == 0), rng.integers(1, 4, fired.shape), 0)
+    npos = np.where(fired & (rng.random(fired.shape) < 0.5),
+                    rng.integers(1, max_count + 1, fired.shape), 0)
+    nneg = np.where(fired & (npos == 0), rng.integers(1, max_count + 1, fired.shape), 0)
     tx = (smooth(-1.5, 1.5) + 0.05 * rng.standard_normal(fired.shape)).astype(np.float32)
     ty = (smooth(-1.5, 1.5) + 0.05 * rng.standard_normal(fired.shape)).astype(np.float32)
     w = rng.uniform(0.5, 1.5, fired.shape).astype(np.float32)

@@ -281,7 +281,9 @@ typedef struct rec_diff_desc {
     int32_t batch;          /* images, 1..65535 */
     int32_t iters;          /* unrolled iterations K >= 0 */
     int32_t ckpt_every;     /* checkpoint interval, 1..max(K, 1) */
-    int32_t reserved;       /* must be 0 */
+    int32_t unfused;        /* 0: fused register-tile kernels (several
+                               iterations per launch); 1: one launch per
+                               half-step (reference form, same bits) */
     double tau, sigma;      /* steps: tau sigma (8 + 4 sqrt 2) <= 1 */
     double u_min, u_max;    /* 0 < u_min < u_max */
 } rec_diff_desc;

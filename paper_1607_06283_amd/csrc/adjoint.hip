@@ -25,8 +25,15 @@
 // recomputed, bit for bit, by the same forward kernels before the segment's
 // reverse steps run.
 //
-// Kernels are one thread per pixel, 64 x 4 pixels per workgroup (a
-// wavefront covers 64 consecutive pixels of a row), blockIdx.z = image.
+// Two forms, same bits:
+//  - fused (default): register tiles as in the forward solve.  The forward
+//    runs a segment's iterations per launch; the recomputation of a segment
+//    also records every intermediate state; the reverse sweep runs several
+//    reverse steps per launch on a tile with the adjoint state in registers
+//    (a K-step launch reads a K-pixel halo; each step reads the recorded
+//    state it needs).
+//  - unfused (reference): one thread per pixel, 64 x 4 pixels per
+//    workgroup, blockIdx.z = image, one launch per half-step.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -34,6 +41,7 @@
 
 #include "pd_math.h"
 #include "rec.h"
+#include "tile.h"
 
 namespace rec {
 namespace {
@@ -360,6 +368,321 @@ __global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restric
     if (t < 3) out[t] = red[t][0];
 }
 
+// ------------------------------------------------------------------ fused
+
+// Tiles of a fused launch: each image is cut into tiles_x x tiles_y regions
+// of 64 x RH pixels whose interiors (the region minus a KG-pixel border)
+// partition the image.
+struct TileGrid {
+    int tiles_x, per_image, total;
+    int kg;  // halo = iterations (or reverse steps) of the launch
+};
+
+// Intermediate states recorded by a forward launch: the state after
+// iteration it (it < K - 1) goes to (u + it * stride, p + it * stride).
+struct Trail {
+    float* u;
+    float* p;
+    size_t stride;
+};
+
+// Where a tile sits; interior(): the pixel is written by this tile.
+struct TilePos {
+    int lane, wave, gx, gy0, b;
+    size_t img, fld;  // offsets of image b in an image plane / a 3-plane field
+    bool col_in, col_out;
+};
+
+template <int R, int NW>
+__device__ __forceinline__ TilePos tile_pos(const Dims& d, const TileGrid& g) {
+    constexpr int RH = NW * R;
+    TilePos t;
+    t.lane = threadIdx.x & 63;
+    t.wave = threadIdx.x >> 6;
+    const int tile = xcd_tile(blockIdx.x, g.total);
+    t.b = tile / g.per_image;
+    const int tt = tile - t.b * g.per_image;
+    const int tyi = tt / g.tiles_x, txi = tt - tyi * g.tiles_x;
+    const int OW = 64 - 2 * g.kg, OH = RH - 2 * g.kg;
+    t.gx = txi * OW - g.kg + t.lane;
+    t.gy0 = tyi * OH - g.kg + t.wave * R;
+    t.img = (size_t)t.b * d.np;
+    t.fld = 3 * t.img;
+    t.col_in = t.gx >= 0 && t.gx < d.W;
+    t.col_out = t.col_in && t.lane >= g.kg && t.lane < 64 - g.kg;
+    return t;
+}
+
+template <int R, int NW>
+__device__ __forceinline__ bool interior(const Dims& d, const TileGrid& g, const TilePos& t,
+                                         int r) {
+    constexpr int RH = NW * R;
+    const int row = t.wave * R + r, gy = t.gy0 + r;
+    return t.col_out && row >= g.kg && row < RH - g.kg && gy >= 0 && gy < d.H;
+}
+
+template <int R, int NW>
+__device__ __forceinline__ void store_state(const Dims& d, const TileGrid& g, const TilePos& t,
+                                            float* U, float* P, const float (&u)[R],
+                                            const float (&p1)[R], const float (&p2)[R],
+                                            const float (&p3)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!interior<R, NW>(d, g, t, r)) continue;
+        const size_t k = (size_t)(t.gy0 + r) * d.W + t.gx;
+        U[t.img + k] = u[r];
+        P[t.fld + k] = p1[r];
+        P[t.fld + d.np + k] = p2[r];
+        P[t.fld + 2 * d.np + k] = p3[r];
+    }
+}
+
+// Metric constants of a tile's rows (pixels outside the image: zero M,
+// f = 1, as in the forward solve's tiles).
+template <int R>
+__device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, const float* f,
+                                           const float* tx, const float* ty, const float* w,
+                                           float tl, Coef (&c)[R], float (&fr)[R]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = t.gy0 + r;
+        const bool in = t.col_in && gy >= 0 && gy < d.H;
+        float ff = 1.0f, x = 0.0f, y = 0.0f, tlw = tl;
+        if (in) {
+            const size_t k = t.img + (size_t)gy * d.W + t.gx;
+            ff = f[k];
+            x = tx[k];
+            y = ty[k];
+            if (w) tlw = tl * w[k];
+        }
+        fr[r] = ff;
+        c[r] = make_coef(x, y, ff, tlw, in && t.gx < d.W - 1, in && gy < d.H - 1);
+    }
+}
+
+// Forward: K iterations from state `in` to state `out`; with rec.u set,
+// also the K - 1 intermediate states.
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, State in, State out,
+                                                        Trail rec, const float* __restrict__ f,
+                                                        const float* __restrict__ tx,
+                                                        const float* __restrict__ ty,
+                                                        const float* __restrict__ w,
+                                                        const double* __restrict__ theta,
+                                                        Steps st) {
+    const TilePos t = tile_pos<R, NW>(d, g);
+    const int K = g.kg;
+    float u[R], p1[R], p2[R], p3[R], fr[R];
+    Coef c[R];
+    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), c, fr);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = t.gy0 + r;
+        u[r] = 1.0f;
+        p1[r] = p2[r] = p3[r] = 0.0f;
+        if (t.col_in && gy >= 0 && gy < d.H) {
+            const size_t k = (size_t)gy * d.W + t.gx;
+            u[r] = in.u[t.img + k];
+            p1[r] = in.p[t.fld + k];
+            p2[r] = in.p[t.fld + d.np + k];
+            p3[r] = in.p[t.fld + 2 * d.np + k];
+        }
+    }
+    __shared__ float xq[NW][64];
+    __shared__ float xu[NW][64];
+    for (int it = 0; it < K; ++it) {
+        tile_iteration<R, NW>(u, p1, p2, p3, c, st.tau, st.sigma, st.umin, st.umax, t.lane,
+                              t.wave, xq, xu);
+        if (rec.u && it < K - 1)
+            store_state<R, NW>(d, g, t, rec.u + it * rec.stride, rec.p + it * rec.stride, u, p1,
+                               p2, p3);
+    }
+    store_state<R, NW>(d, g, t, out.u, out.p, u, p1, p2, p3);
+}
+
+// States j0 .. j0 + K of a reverse launch (local index 0 .. K).
+constexpr int kMaxRev = 8;
+struct StateSeq {
+    float* u[kMaxRev + 1];
+    float* p[kMaxRev + 1];
+};
+
+// Adjoint planes read or written by a reverse launch (ping-pong between
+// launches: tiles read their halo from `in` while others write `out`).
+struct AdjIO {
+    float* q;   // [B][3][np]
+    float* ub;  // [B][np]
+    float* uh;  // [B][np]
+};
+
+// Reverse steps j0 + K - 1 down to j0 on a register tile: the adjoint state
+// (q, ub_hat, hat u) comes from `ain` (or from g_p, 0, g_u when `first`)
+// and goes to `aout`; the sums of beta_hat and f_hat are accumulated into
+// gbeta, gf (interior pixels, in place).
+template <int R, int NW>
+__global__ __launch_bounds__(64 * NW) void k_adj_fused(
+    Dims d, TileGrid g, StateSeq S, AdjIO ain, AdjIO aout, float* __restrict__ gbeta,
+    float* __restrict__ gf, const float* __restrict__ g_u, const float* __restrict__ g_p,
+    int first, const float* __restrict__ f, const float* __restrict__ tx,
+    const float* __restrict__ ty, const float* __restrict__ w, const double* __restrict__ theta,
+    Steps st) {
+    const TilePos t = tile_pos<R, NW>(d, g);
+    const int K = g.kg;
+    const int lane = t.lane, wave = t.wave;
+    float fr[R];
+    Coef c[R];
+    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), c, fr);
+    float u1[R], Q1[R], Q2[R], Q3[R], UB[R], UH[R], GB[R], GF[R];
+    bool inside[R];
+    size_t kk[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = t.gy0 + r;
+        inside[r] = t.col_in && gy >= 0 && gy < d.H;
+        kk[r] = inside[r] ? (size_t)gy * d.W + t.gx : 0;
+        const size_t k = kk[r];
+        u1[r] = inside[r] ? S.u[K][t.img + k] : 1.0f;
+        Q1[r] = Q2[r] = Q3[r] = UB[r] = UH[r] = 0.0f;
+        if (inside[r]) {
+            if (first) {
+                if (g_p) {
+                    Q1[r] = g_p[t.fld + k];
+                    Q2[r] = g_p[t.fld + d.np + k];
+                    Q3[r] = g_p[t.fld + 2 * d.np + k];
+                }
+                if (g_u) UH[r] = g_u[t.img + k];
+            } else {
+                Q1[r] = ain.q[t.fld + k];
+                Q2[r] = ain.q[t.fld + d.np + k];
+                Q3[r] = ain.q[t.fld + 2 * d.np + k];
+                UB[r] = ain.ub[t.img + k];
+                UH[r] = ain.uh[t.img + k];
+            }
+        }
+        const bool own = interior<R, NW>(d, g, t, r);
+        GB[r] = own ? gbeta[t.img + k] : 0.0f;
+        GF[r] = own ? gf[t.img + k] : 0.0f;
+    }
+    __shared__ float xa[NW][64], xb[NW][64], xc[NW][64], xd[NW][64];
+    // the state of the next step is loaded one step ahead
+    float nu[R], na[R], nb[R], nc[R];
+    auto load_state = [&](int j) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const size_t k = kk[r];
+            nu[r] = inside[r] ? S.u[j][t.img + k] : 1.0f;
+            na[r] = inside[r] ? S.p[j][t.fld + k] : 0.0f;
+            nb[r] = inside[r] ? S.p[j][t.fld + d.np + k] : 0.0f;
+            nc[r] = inside[r] ? S.p[j][t.fld + 2 * d.np + k] : 0.0f;
+        }
+    };
+    load_state(K - 1);
+    for (int s = 0; s < K; ++s) {
+        float u0[R], pa[R], pb[R], pc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            u0[r] = nu[r];
+            pa[r] = na[r];
+            pb[r] = nb[r];
+            pc[r] = nc[r];
+        }
+        if (s + 1 < K) load_state(K - 2 - s);
+        // reverse of the dual half-step: needs ub_hat and the extrapolated
+        // primal at the right and lower neighbours
+        float ut[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ut[r] = extrapolate(u1[r], u0[r]);
+        float ub_bot = 0.0f, ut_bot = 0.0f;
+        if constexpr (NW > 1) {
+            xa[wave][lane] = UB[0];
+            xb[wave][lane] = ut[0];
+            __syncthreads();
+            if (wave < NW - 1) {
+                ub_bot = xa[wave + 1][lane];
+                ut_bot = xb[wave + 1][lane];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const Coef& cc = c[r];
+            const float ubr = lane_from_right(UB[r]);
+            const float ubd = r < R - 1 ? UB[r + 1] : ub_bot;
+            const float gx = ubr - UB[r], gy = ubd - UB[r];
+            float h1 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b12, gy, cc.a11 * gx), Q1[r]);
+            float h2 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b22, gy, cc.a21 * gx), Q2[r]);
+            float h3 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b32, gy, cc.a31 * gx), Q3[r]);
+            const float utr = lane_from_right(ut[r]);
+            const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
+            const float ex = utr - ut[r], ey = utd - ut[r];
+            const float b1 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b12, ey, cc.a11 * ex), pa[r]);
+            const float b2 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b22, ey, cc.a21 * ex), pb[r]);
+            const float b3 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b32, ey, cc.a31 * ex), pc[r]);
+            const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
+            const float sc = cc.s * rsq(n2);
+            if (sc < 1.0f) {
+                const float tt = __builtin_fmaf(b3, h3, __builtin_fmaf(b2, h2, b1 * h1)) * rcp(n2);
+                h1 = sc * __builtin_fmaf(-tt, b1, h1);
+                h2 = sc * __builtin_fmaf(-tt, b2, h2);
+                h3 = sc * __builtin_fmaf(-tt, b3, h3);
+            }
+            Q1[r] = h1;
+            Q2[r] = h2;
+            Q3[r] = h3;
+        }
+        // reverse of the primal half-step: needs M^T q and M^T p at the left
+        // and upper neighbours
+        float qxq[R], qyq[R], qxp[R], qyp[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            qxq[r] = q_x(c[r], Q1[r], Q2[r], Q3[r]);
+            qyq[r] = q_y(c[r], Q1[r], Q2[r], Q3[r]);
+            qxp[r] = q_x(c[r], pa[r], pb[r], pc[r]);
+            qyp[r] = q_y(c[r], pa[r], pb[r], pc[r]);
+        }
+        float qyq_top = 0.0f, qyp_top = 0.0f;
+        if constexpr (NW > 1) {
+            xc[wave][lane] = qyq[R - 1];
+            xd[wave][lane] = qyp[R - 1];
+            __syncthreads();
+            if (wave > 0) {
+                qyq_top = xc[wave - 1][lane];
+                qyp_top = xd[wave - 1][lane];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float qxl = lane_from_left(qxq[r]);
+            const float qyu = r > 0 ? qyq[r - 1] : qyq_top;
+            const float ut_hat = -st.sigma * ((qxq[r] - qxl) + (qyq[r] - qyu));
+            const float H = __builtin_fmaf(2.0f, ut_hat, UH[r]);
+            const float pxl = lane_from_left(qxp[r]);
+            const float pyu = r > 0 ? qyp[r - 1] : qyp_top;
+            float rr;
+            const float un = prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r], st.tau, rr);
+            const bool active = un >= st.umin && un <= st.umax;
+            const float hr = active ? H * rcp(rr) : 0.0f;
+            const float ub = un * hr;
+            UB[r] = ub;
+            UH[r] = ub - ut_hat;
+            GB[r] += (fr[r] - un) * hr;
+            GF[r] += c[r].beta * hr;
+            u1[r] = u0[r];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!interior<R, NW>(d, g, t, r)) continue;
+        const size_t k = kk[r];
+        aout.q[t.fld + k] = Q1[r];
+        aout.q[t.fld + d.np + k] = Q2[r];
+        aout.q[t.fld + 2 * d.np + k] = Q3[r];
+        aout.ub[t.img + k] = UB[r];
+        aout.uh[t.img + k] = UH[r];
+        gbeta[t.img + k] = GB[r];
+        gf[t.img + k] = GF[r];
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 constexpr size_t kAlign = 256;
@@ -369,7 +692,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 bool desc_ok(const rec_diff_desc* d) {
     if (!d) return false;
     if (d->width < 1 || d->width > 65535 || d->height < 1 || d->height > 65535) return false;
-    if (d->batch < 1 || d->batch > 65535 || d->iters < 0 || d->reserved != 0) return false;
+    if (d->batch < 1 || d->batch > 65535 || d->iters < 0) return false;
+    if (d->unfused != 0 && d->unfused != 1) return false;
     if (d->ckpt_every < 1 || d->ckpt_every > (d->iters > 0 ? d->iters : 1)) return false;
     if (!(d->tau > 0.0) || !(d->sigma > 0.0) || !isfinite(d->tau) || !isfinite(d->sigma))
         return false;
@@ -393,13 +717,15 @@ size_t blocks_of(const rec_diff_desc* d) {
 }
 
 // Workspace carve: f | checkpoints (C + 1 states) | segment (k - 1 states) |
-// adjoint planes | partial sums.
+// adjoint planes (q, ub, uh twice for the fused ping-pong; the two sums) |
+// partial sums.
 struct Carve {
     float* f;
     State ck0;        // checkpoint c at ck0 + c * state_stride
     State seg0;       // segment slot j at seg0 + j * state_stride
     size_t state_floats;
-    Adj A;
+    Adj A;            // q, ub, uh of side 0 and the sums
+    AdjIO B;          // q, ub, uh of side 1
     double* part;
     size_t bytes;
 };
@@ -429,6 +755,12 @@ Carve carve(const rec_diff_desc* d, char* base) {
     off += plane;
     c.A.gf = (float*)(base + off);
     off += plane;
+    c.B.q = (float*)(base + off);
+    off += 3 * plane;
+    c.B.ub = (float*)(base + off);
+    off += plane;
+    c.B.uh = (float*)(base + off);
+    off += plane;
     c.part = (double*)(base + off);
     off += align_up(blocks_of(d) * 3 * sizeof(double));
     c.bytes = off;
@@ -439,6 +771,26 @@ State at(State s0, size_t stride, int k) {
     return State{s0.u + (size_t)k * stride, s0.p + (size_t)k * stride};
 }
 
+// Fused tile shapes: forward (rows per lane, wavefronts) by the batch's
+// pixel count, as the forward solve chooses; the reverse keeps its adjoint
+// state in registers (about 3x the forward's per row) on 2 rows per lane.
+struct FusedShape {
+    int fr, fw, fk;  // forward rows, waves, max iterations per launch
+    int rr, rw, rk;  // reverse rows, waves, max steps per launch
+};
+
+FusedShape fused_shape(const rec_diff_desc* d) {
+    const size_t n = (size_t)d->width * d->height * d->batch;
+    FusedShape f;
+    if (n > 250000) {
+        f.fr = 4; f.fw = 16; f.fk = 16;
+    } else {
+        f.fr = 2; f.fw = 16; f.fk = 15;
+    }
+    f.rr = 2; f.rw = 16; f.rk = 5;
+    return f;
+}
+
 struct Ctx {
     const rec_diff_desc* d;
     const rec_diff_inputs* in;
@@ -446,8 +798,34 @@ struct Ctx {
     Dims dims;
     Steps st;
     dim3 grid;
+    FusedShape fs;
     hipStream_t s;
 };
+
+TileGrid tile_grid(const Ctx& x, int rh, int kg) {
+    TileGrid g;
+    const int ow = 64 - 2 * kg, oh = rh - 2 * kg;
+    g.tiles_x = (x.d->width + ow - 1) / ow;
+    const int ty = (x.d->height + oh - 1) / oh;
+    g.per_image = g.tiles_x * ty;
+    g.total = g.per_image * x.d->batch;
+    g.kg = kg;
+    return g;
+}
+
+// K fused forward iterations from `a` into `b`, recording the K - 1
+// intermediate states into rec (if rec.u).
+void fwd_fused(const Ctx& x, State a, State b, int K, Trail rec) {
+    const TileGrid g = tile_grid(x, x.fs.fr * x.fs.fw, K);
+    const dim3 grid((unsigned)g.total), blk(64 * x.fs.fw);
+    const rec_diff_inputs* in = x.in;
+    if (x.fs.fr == 4)
+        hipLaunchKernelGGL((k_dfwd_fused<4, 16>), grid, blk, 0, x.s, x.dims, g, a, b, rec,
+                           x.cv.f, in->tx, in->ty, in->w, in->theta, x.st);
+    else
+        hipLaunchKernelGGL((k_dfwd_fused<2, 16>), grid, blk, 0, x.s, x.dims, g, a, b, rec,
+                           x.cv.f, in->tx, in->ty, in->w, in->theta, x.st);
+}
 
 int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size_t bytes,
                Ctx& x) {
@@ -462,6 +840,7 @@ int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size
     x.dims = Dims{d->width, d->height, (size_t)d->width * d->height};
     x.st = Steps{d->tau, (float)d->tau, (float)d->sigma, (float)d->u_min, (float)d->u_max};
     x.grid = grid_of(d);
+    x.fs = fused_shape(d);
     return REC_OK;
 }
 
@@ -478,6 +857,41 @@ State seg_state(const Ctx& x, int c, int j, int m) {
     if (j == 0) return at(x.cv.ck0, x.cv.state_floats, c);
     if (j == m) return at(x.cv.ck0, x.cv.state_floats, c + 1);
     return at(x.cv.seg0, x.cv.state_floats, j - 1);
+}
+
+// States a -> b of segment c by fused launches of at most fk iterations;
+// with `record`, every state in between is written to its segment slot.
+void fwd_segment(const Ctx& x, int c, int a, int b, int m, bool record) {
+    while (a < b) {
+        const int K = b - a < x.fs.fk ? b - a : x.fs.fk;
+        Trail rec{nullptr, nullptr, 0};
+        if (record && K > 1) {
+            const State r0 = seg_state(x, c, a + 1, m);  // a + 1 < b <= m: a slot
+            rec = Trail{r0.u, r0.p, x.cv.state_floats};
+        }
+        fwd_fused(x, seg_state(x, c, a, m), seg_state(x, c, a + K, m), K, rec);
+        a += K;
+    }
+}
+
+// Reverse steps j = jtop - 1 down to j0 of segment c in one fused launch.
+void rev_fused(const Ctx& x, int c, int j0, int jtop, int m, const float* g_u, const float* g_p,
+               int first, int& side) {
+    const int K = jtop - j0;
+    StateSeq S;
+    for (int i = 0; i <= K; ++i) {
+        const State st = seg_state(x, c, j0 + i, m);
+        S.u[i] = st.u;
+        S.p[i] = st.p;
+    }
+    const AdjIO A0{x.cv.A.q, x.cv.A.ub, x.cv.A.uh};
+    const AdjIO ain = side ? x.cv.B : A0, aout = side ? A0 : x.cv.B;
+    const TileGrid g = tile_grid(x, x.fs.rr * x.fs.rw, K);
+    const rec_diff_inputs* in = x.in;
+    hipLaunchKernelGGL((k_adj_fused<2, 16>), dim3((unsigned)g.total), dim3(64 * 16), 0, x.s,
+                       x.dims, g, S, ain, aout, x.cv.A.gbeta, x.cv.A.gf, g_u, g_p, first, x.cv.f,
+                       in->tx, in->ty, in->w, in->theta, x.st);
+    side ^= 1;
 }
 
 }  // namespace
@@ -505,7 +919,12 @@ int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u
     const int C = segments(d), k = d->ckpt_every;
     for (int c = 0; c < C; ++c) {
         const int m = (d->iters - c * k) < k ? d->iters - c * k : k;
-        for (int j = 0; j < m; ++j) step(x, seg_state(x, c, j, m), seg_state(x, c, j + 1, m));
+        if (d->unfused) {
+            for (int j = 0; j < m; ++j)
+                step(x, seg_state(x, c, j, m), seg_state(x, c, j + 1, m));
+        } else {
+            fwd_segment(x, c, 0, m, m, false);
+        }
     }
     hipLaunchKernelGGL(k_diff_out, x.grid, dim3(kThreads), 0, x.s, x.dims,
                        at(x.cv.ck0, x.cv.state_floats, C), u_out, p_out);
@@ -524,8 +943,18 @@ int rec_diff_backward(const rec_diff_desc* d, const rec_diff_inputs* in, const f
     const dim3 blk(kThreads);
     hipLaunchKernelGGL(k_adj_zero, x.grid, blk, 0, x.s, x.dims, x.cv.A);
     const int C = segments(d), k = d->ckpt_every;
-    int first = 1;
-    for (int c = C - 1; c >= 0; --c) {
+    int first = 1, side = 0;
+    for (int c = C - 1; c >= 0 && !d->unfused; --c) {
+        const int m = (d->iters - c * k) < k ? d->iters - c * k : k;
+        if (m >= 2) fwd_segment(x, c, 0, m - 1, m, true);  // states 1 .. m-1
+        for (int jtop = m; jtop > 0;) {
+            const int j0 = jtop > x.fs.rk ? jtop - x.fs.rk : 0;
+            rev_fused(x, c, j0, jtop, m, g_u, g_p, first, side);
+            first = 0;
+            jtop = j0;
+        }
+    }
+    for (int c = C - 1; c >= 0 && d->unfused; --c) {
         const int m = (d->iters - c * k) < k ? d->iters - c * k : k;
         for (int j = 0; j + 1 < m; ++j)  // recompute the states inside the segment
             step(x, seg_state(x, c, j, m), seg_state(x, c, j + 1, m));
@@ -538,8 +967,14 @@ int rec_diff_backward(const rec_diff_desc* d, const rec_diff_inputs* in, const f
             first = 0;
         }
     }
+    Adj cur = x.cv.A;  // the side holding the latest adjoint state
+    if (side) {
+        cur.q = x.cv.B.q;
+        cur.ub = x.cv.B.ub;
+        cur.uh = x.cv.B.uh;
+    }
     hipLaunchKernelGGL(k_adj_final, x.grid, blk, 0, x.s, x.dims, x.cv.f, in->tx, in->ty, in->w,
-                       in->npos, in->nneg, in->theta, x.cv.A, g_u, g_p, first, x.st, out->u0,
+                       in->npos, in->nneg, in->theta, cur, g_u, g_p, first, x.st, out->u0,
                        out->p0, out->w, x.cv.part);
     if (out->theta)
         hipLaunchKernelGGL(k_adj_reduce, dim3(1), blk, 0, x.s, x.cv.part, blocks_of(d),

@@ -15,6 +15,7 @@
 
 #include "kernels.h"
 #include "pd_math.h"
+#include "tile.h"
 
 namespace rec {
 
@@ -30,15 +31,6 @@ __device__ __forceinline__ int32_t event_error(int64_t t, int64_t prev, uint16_t
 
 __device__ __forceinline__ int64_t resolved_last(int64_t tl, int64_t t_first) {
     return tl == kNever ? t_first : tl;
-}
-
-// blockIdx -> tile such that each of the 8 XCDs (which receive blocks
-// round-robin) works on one contiguous run of tiles, so halo rows shared by
-// neighbouring tiles are fetched into the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
-    const int q = ntiles >> 3, rem = ntiles & 7;
-    const int xcd = b & 7, idx = b >> 3;
-    return xcd * q + min(xcd, rem) + idx;
 }
 
 // Launch with optional timing events carried by the dispatch itself.
@@ -414,15 +406,6 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
 }
 
 // ---------------------------------------------------------------- fused loop
-
-// Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1);
-// the lane without a source receives 0.
-__device__ __forceinline__ float lane_from_left(float v) {   // value of lane - 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
-}
-__device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 1
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
-}
 
 // Folded events of the first launch, binned for one tile region (LDS).
 struct TileBins {

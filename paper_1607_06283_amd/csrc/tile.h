@@ -1,0 +1,79 @@
+// Register-tile building blocks shared by the fused loops: the forward
+// primal-dual iteration of a tile and the lane / XCD helpers.
+//
+// Tile layout: a workgroup of NW wavefronts covers 64 columns x (NW * R)
+// rows; lane = column, each lane holds R consecutive rows in registers and
+// wavefront w holds rows [w R, w R + R).  Horizontal neighbours come from
+// adjacent lanes (DPP), vertical ones from the lane's own registers or,
+// across wavefronts, through LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pd_math.h"
+
+namespace rec {
+
+// blockIdx -> tile such that each of the 8 XCDs (which receive blocks
+// round-robin) works on one contiguous run of tiles, so halo rows shared by
+// neighbouring tiles are fetched into the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int ntiles) {
+    const int q = ntiles >> 3, rem = ntiles & 7;
+    const int xcd = b & 7, idx = b >> 3;
+    return xcd * q + min(xcd, rem) + idx;
+}
+
+// Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1);
+// the lane without a source receives 0.
+__device__ __forceinline__ float lane_from_left(float v) {   // value of lane - 1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 1
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+
+// One primal-dual iteration of a tile held in registers (u, p, metric
+// constants c per row).  xq, xu: NW x 64 floats of LDS each, for the rows
+// that cross wavefronts.  Pixels outside the image carry all-zero M, so
+// every neighbour term they contribute is 0.
+template <int R, int NW>
+__device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
+                                               float (&p3)[R], const Coef (&c)[R], float tau,
+                                               float sigma, float umin, float umax, int lane,
+                                               int wave, float (*xq)[64], float (*xu)[64]) {
+    float qx[R], qy[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        qx[r] = q_x(c[r], p1[r], p2[r], p3[r]);
+        qy[r] = q_y(c[r], p1[r], p2[r], p3[r]);
+    }
+    float qy_top = 0.0f;
+    if constexpr (NW > 1) {
+        xq[wave][lane] = qy[R - 1];
+        __syncthreads();
+        if (wave > 0) qy_top = xq[wave - 1][lane];
+    }
+    float un[R], ut[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float qxl = lane_from_left(qx[r]);
+        const float qyu = r > 0 ? qy[r - 1] : qy_top;
+        un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], tau, umin, umax);
+        ut[r] = extrapolate(un[r], u[r]);
+    }
+    float ut_bot = 0.0f;
+    if constexpr (NW > 1) {
+        xu[wave][lane] = ut[0];
+        __syncthreads();
+        if (wave < NW - 1) ut_bot = xu[wave + 1][lane];
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float utr = lane_from_right(ut[r]);
+        const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
+        dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r], sigma);
+        u[r] = un[r];
+    }
+}
+
+}  // namespace rec

@@ -80,7 +80,7 @@ EXPORTS = (
 class rec_diff_desc(ctypes.Structure):
     _fields_ = [
         ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("batch", ctypes.c_int32),
-        ("iters", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("iters", ctypes.c_int32), ("ckpt_every", ctypes.c_int32), ("unfused", ctypes.c_int32),
         ("tau", ctypes.c_double), ("sigma", ctypes.c_double),
         ("u_min", ctypes.c_double), ("u_max", ctypes.c_double),
     ]
@@ -439,10 +439,11 @@ DEFAULT_STEP = 1.0 / math.sqrt(8.0 + 4.0 * math.sqrt(2.0))
 
 def rec_diff_desc_make(width: int, height: int, batch: int, iters: int, ckpt_every: int = 10,
                        tau: float = DEFAULT_STEP, sigma: float = DEFAULT_STEP,
-                       u_min: float = 1.0, u_max: float = math.e) -> rec_diff_desc:
+                       u_min: float = 1.0, u_max: float = math.e,
+                       unfused: bool = False) -> rec_diff_desc:
     k = max(1, min(int(ckpt_every), max(int(iters), 1)))
-    return rec_diff_desc(int(width), int(height), int(batch), int(iters), k, 0, float(tau),
-                         float(sigma), float(u_min), float(u_max))
+    return rec_diff_desc(int(width), int(height), int(batch), int(iters), k, int(bool(unfused)),
+                         float(tau), float(sigma), float(u_min), float(u_max))
 
 
 def rec_diff_workspace_bytes(desc: rec_diff_desc) -> int:
@@ -535,7 +536,7 @@ _UNROLLED = None
 
 def unrolled(u0, npos, nneg, tx, ty, theta, iters: int, w=None, p0=None, ckpt_every: int = 10,
              tau: float = DEFAULT_STEP, sigma: float = DEFAULT_STEP, u_min: float = 1.0,
-             u_max: float = math.e):
+             u_max: float = math.e, unfused: bool = False):
     """K = iters primal-dual iterations on a batch of blocks, differentiable
     in u0, w, theta = (lambda, delta_pos, delta_neg) and p0.
 
@@ -548,5 +549,5 @@ def unrolled(u0, npos, nneg, tx, ty, theta, iters: int, w=None, p0=None, ckpt_ev
     if u0.dim() != 3:
         raise ValueError("u0 must be [B, H, W]")
     B, H, W = u0.shape
-    desc = rec_diff_desc_make(W, H, B, iters, ckpt_every, tau, sigma, u_min, u_max)
+    desc = rec_diff_desc_make(W, H, B, iters, ckpt_every, tau, sigma, u_min, u_max, unfused)
     return _UNROLLED.apply(u0, w, theta, p0, npos, nneg, tx, ty, desc)

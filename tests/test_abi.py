@@ -166,13 +166,13 @@ def test_diff_desc_layout_and_workspace():
     plane = a(70 * 37 * 2 * 4)
     C = math.ceil(30 / 7)
     blocks = 2 * 10 * 2  # ceil(70/64) x ceil(37/4) x images
-    want = plane * (1 + 4 * (C + 1) + 4 * (7 - 1) + 7) + a(blocks * 3 * 8)
+    want = plane * (1 + 4 * (C + 1) + 4 * (7 - 1) + 7 + 5) + a(blocks * 3 * 8)
     assert rec.rec_diff_workspace_bytes(d) == want
 
 
 @pytest.mark.parametrize("field,value", [
     ("width", 0), ("height", 70000), ("batch", 0), ("iters", -1), ("ckpt_every", 0),
-    ("ckpt_every", 31), ("reserved", 1), ("tau", 0.0), ("sigma", float("nan")),
+    ("ckpt_every", 31), ("unfused", 2), ("tau", 0.0), ("sigma", float("nan")),
     ("tau", 0.5), ("u_min", 0.0), ("u_max", 0.5),
 ])
 def test_diff_bad_desc(field, value):

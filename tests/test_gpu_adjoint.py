@@ -35,21 +35,22 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
-def _gpu_grads(inp, iters, ckpt, p0=None, seed=5, use_w=True):
+def _gpu_grads(inp, iters, ckpt, p0=None, seed=5, use_w=True, unfused=False, gu=None, gp=None):
     """Forward + backward on the GPU of J = <gu, u_K> + <gp, p_K>."""
     torch = _torch()
     d = _dev(inp)
     B, H, W = inp["u0"].shape
     rng = np.random.default_rng(seed)
-    gu = rng.standard_normal((B, H, W))
-    gp = rng.standard_normal((B, 3, H, W))
+    if gu is None:
+        gu = rng.standard_normal((B, H, W))
+        gp = rng.standard_normal((B, 3, H, W))
     u0 = d["u0"].clone().requires_grad_()
     w = d["w"].clone().requires_grad_() if use_w else None
     th = torch.tensor([LAM, DPOS, DNEG], dtype=torch.float64, device="cuda", requires_grad=True)
     p0t = None if p0 is None else torch.from_numpy(p0.astype(np.float32)).cuda().requires_grad_()
-    print(f"gpu diff B={B} H={H} W={W} iters={iters} ckpt={ckpt}", flush=True)
+    print(f"gpu diff B={B} H={H} W={W} iters={iters} ckpt={ckpt} unfused={unfused}", flush=True)
     u, p = rec.unrolled(u0, d["npos"], d["nneg"], d["tx"], d["ty"], th, iters, w=w, p0=p0t,
-                        ckpt_every=ckpt)
+                        ckpt_every=ckpt, unfused=unfused)
     J = (torch.from_numpy(gu).cuda() * u.double()).sum() + \
         (torch.from_numpy(gp).cuda() * p.double()).sum()
     J.backward()
@@ -106,13 +107,60 @@ def test_gradients_match_fp64_autograd(ragged, ckpt):
         assert e <= GRAD_RTOL, name
 
 
-def test_checkpoint_interval_does_not_change_bits(ragged):
-    """Recomputed segments reproduce the forward bit for bit, so every
-    checkpoint interval gives the same gradients."""
-    outs = [_gpu_grads(ragged, 24, k) for k in (1, 5, 24)]
+def test_checkpoint_interval_and_form_do_not_change_bits(ragged):
+    """Recomputed segments reproduce the forward bit for bit, and the fused
+    register-tile kernels run the same per-pixel arithmetic as the one-launch-
+    per-half-step form, so every checkpoint interval and both forms give the
+    same bits."""
+    outs = [_gpu_grads(ragged, 24, k, unfused=uf) for uf in (True, False)
+            for k in (1, 5, 7, 24)]
     for o in outs[1:]:
         for key in ("u", "p", "u0", "w", "theta"):
             assert np.array_equal(o[key], outs[0][key]), key
+
+
+@pytest.mark.slow
+def test_full_size_fused_equals_unfused_and_fp64():
+    """The differentiation workload's size (16 x 346x260, 100 iterations,
+    checkpoints every 10) in the fused form the benchmark times: bit-equal to
+    the two-kernel form; and, with the loss on two sampled images (the
+    images are independent), the gradients against FP64 autograd of those
+    two images.  Inputs keep f inside (1, e), away from the clamp's kinks."""
+    inp = evgen.diff_inputs(500, 16, 260, 346, levels=(0.35, 0.65), max_count=1)
+    iters = 100
+    B, H, W = inp["u0"].shape
+    rng = np.random.default_rng(8)
+    gu = np.zeros((B, H, W))
+    gp = np.zeros((B, 3, H, W))
+    pick = [0, 9]
+    for b in pick:
+        gu[b] = rng.standard_normal((H, W))
+        gp[b] = rng.standard_normal((3, H, W))
+    gf = _gpu_grads(inp, iters, 10, gu=gu, gp=gp)
+    gx = _gpu_grads(inp, iters, 10, gu=gu, gp=gp, unfused=True)
+    for key in ("u", "p", "u0", "w", "theta"):
+        assert np.array_equal(gf[key], gx[key]), key
+    sub = {k: v[pick] for k, v in inp.items()}
+    r = _ref_grads(sub, iters, gu[pick], gp[pick])
+    assert np.abs(gf["u"][pick] - r["u"]).max() <= 1e-4
+    for k in ("u0", "w"):
+        e = _rel(gf[k][pick], r[k])
+        print(f"  full size d/d{k}: relative error {e:.2e}")
+        assert e <= GRAD_RTOL, k
+    for i, name in enumerate(("lambda", "dpos", "dneg")):
+        e = abs(gf["theta"][i] - r["theta"][i]) / abs(r["theta"][i])
+        print(f"  full size d/d{name}: {gf['theta'][i]:.6e} vs {r['theta'][i]:.6e} ({e:.2e})")
+        assert e <= GRAD_RTOL, name
+
+
+def test_fused_large_tile_shape_equals_unfused():
+    """Above 250k pixels the fused forward uses 64-row tiles; ragged
+    segments (10, 10, 3) and reverse chunks (5, 5, 3)."""
+    inp = evgen.diff_inputs(33, 2, 301, 455)
+    a = _gpu_grads(inp, 23, 10)
+    b = _gpu_grads(inp, 23, 10, unfused=True)
+    for key in ("u", "p", "u0", "w", "theta"):
+        assert np.array_equal(a[key], b[key]), key
 
 
 def test_scalar_gradients_match_finite_differences(ragged):
