@@ -45,7 +45,6 @@ TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
     ("davis240", "f32"): ("714e7be292ad542f", 2 * 1024 * 1231.3, 1024 * 889.2),
-    ("probe", "f32"): ("714e7be292ad542f", 2 * 1024 * 536217.7, 1024 * 513659.6),
 }
 
 

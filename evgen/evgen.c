@@ -29,8 +29,8 @@
  * R0 + Delta (k+1) (resp. k-1) emits a +1 (resp. -1) event at the linearly
  * interpolated time, floored to an integer microsecond and offset by t0.
  * Hence, for noise-free streams, |L - (R0 + Delta (n+ - n-))| < Delta holds
- * at every sample time, and exp(R0) is the "known initial image" for which
- * integrating the events reproduces the scene up to the threshold.
+ * at every sample time, and exp(R0) is the exactly known starting image from
+ * which integrating the events reproduces the scene up to the threshold.
  *
  * Noise: optionally, a fraction of extra events with uniform pixel, uniform
  * integer time in the stream window and uniform polarity; they do not touch

@@ -119,10 +119,10 @@ typedef struct {
     int32_t storage;         /* storage of the dual field p and of tx, ty: REC_STORE_F32
                                 (default), REC_STORE_BF16 or REC_STORE_F16; the arithmetic
                                 is FP32 in every case (16-bit forms need the fused loop) */
-    int32_t tvl1_iters;      /* timestamp denoising before the metric is built (Section 4:
-                                "a few iterations of a TV-L1 denoising method"): FP64
-                                Chambolle-Pock iterations for min TV(v) + tvl1_lambda |v - tau|_1;
-                                0 = off (default) */
+    int32_t tvl1_iters;      /* timestamp denoising before the metric is built (Section 4
+                                applies a small number of TV-L1 iterations and gives neither
+                                count nor weight): FP64 Chambolle-Pock iterations for
+                                min TV(v) + tvl1_lambda |v - tau|_1; 0 = off (default) */
     double tvl1_lambda;      /* L1 weight of the denoising, > 0; default 1 */
     int32_t reserved[4];     /* must be 0 */
 } rec_params;

@@ -24,7 +24,8 @@
  *   - t(x, y) is the int64 microsecond timestamp of the most recent event;
  *     the surface used is tau = (t_ref - t_last) / T_s with t_ref the last
  *     pushed timestamp (the metric only sees squares and products of the
- *     differences, so "latest timestamp" and "time since" give the same g).
+ *     differences, so a surface of last-event times and one of elapsed
+ *     times give the same g).
  *     Pixels that never fired count as having fired at the stream's first
  *     timestamp.  T_s = 0 switches the manifold off (t = const).
  *   - L_x, L_y are forward differences with h = 1 and a zero difference on
@@ -37,9 +38,9 @@
  *     with a = ubar - beta, d = sqrt(a^2 + 4 beta f):
  *     a >= 0: (a + d) / 2;  a < 0: 2 beta f / (d - a).  Then clamp.
  *   - Warm start: u and p carry over between blocks; p starts at 0.
- *   - Timestamp denoising (Section 4: "a few iterations of a TV-L1
- *     denoising method", neither the weight nor the count given): optional,
- *     off by default.  When on, tau is replaced by the result of n
+ *   - Timestamp denoising (Section 4 runs a small number of TV-L1
+ *     iterations on the timestamps and gives neither their count nor the
+ *     weight): optional, off by default.  When on, tau is replaced by the result of n
  *     Chambolle-Pock iterations for  min_v TV(v) + lambda_t |v - tau|_1
  *     started at v = tau, dual 0, steps 1/sqrt(8), before the differences
  *     are taken.
