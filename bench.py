@@ -39,9 +39,9 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 # copy: FETCH_SIZE read 131084 KiB and WRITE_SIZE 262144 KiB for 262144 KiB
 # moved each way, so fetched bytes = 2 x 1024 x FETCH_SIZE and written bytes
 # = 1024 x WRITE_SIZE.  Each entry holds for the kernel sources it was taken
-# with (hash of kernels.hip, pd_math.h, kernels.h); after a change the bench
+# with (hash of kernels.hip, pd_math.h, kernels.h, tile.h); after a change the bench
 # reports traffic null until the counters are taken again.
-TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h")
+TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
     ("davis240", "f32"): ("714e7be292ad542f", 2 * 1024 * 1231.3, 1024 * 889.2),

@@ -488,8 +488,10 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
             p3[r] = in.p[t.fld + 2 * d.np + k];
         }
     }
-    __shared__ float xq[NW][64];
-    __shared__ float xu[NW][64];
+    __shared__ float xq[NW + 1][64];
+    __shared__ float xu[NW + 1][64];
+    if (t.wave == 0) xq[0][t.lane] = 0.0f;
+    if (t.wave == NW - 1) xu[NW][t.lane] = 0.0f;
     for (int it = 0; it < K; ++it) {
         tile_iteration<R, NW>(u, p1, p2, p3, c, st.tau, st.sigma, st.umin, st.umax, t.lane,
                               t.wave, xq, xu);

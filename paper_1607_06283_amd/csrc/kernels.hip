@@ -622,44 +622,32 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         c[r] = make_coef(tx, ty, f, kc.taulam, in && gx < fr.W - 1, in && gy < fr.H - 1);
     }
 
-    __shared__ float xq[NW > 1 ? NW : 1][64];
-    __shared__ float xu[NW > 1 ? NW : 1][64];
+    // Rows that cross wavefronts go through LDS.  xq[w + 1] holds wavefront
+    // w's last q_y row and xu[w] its first extrapolated row; xq[0] and
+    // xu[NW] stay zero (nothing above the first / below the last wavefront),
+    // so every wavefront reads its neighbour row unconditionally.
+    __shared__ float xq[NW + 1][64];
+    __shared__ float xu[NW + 1][64];
+    if constexpr (NW > 1) {
+        if (wave == 0) xq[0][lane] = 0.0f;
+        if (wave == NW - 1) xu[NW][lane] = 0.0f;
+    }
 
-    for (int it = 0; it < K; ++it) {
-        float qx[R], qy[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            qx[r] = q_x(c[r], p1[r], p2[r], p3[r]);
-            qy[r] = q_y(c[r], p1[r], p2[r], p3[r]);
-        }
-        float qy_top = 0.0f;
-        if constexpr (NW > 1) {
-            xq[wave][lane] = qy[R - 1];
-            __syncthreads();
-            if (wave > 0) qy_top = xq[wave - 1][lane];
-        }
-        float un[R], ut[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float qxl = lane_from_left(qx[r]);
-            const float qyu = r > 0 ? qy[r - 1] : qy_top;
-            un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], kc.tau, kc.umin, kc.umax);
-            ut[r] = extrapolate(un[r], u[r]);
-        }
-        float ut_bot = 0.0f;
-        if constexpr (NW > 1) {
-            xu[wave][lane] = ut[0];
-            __syncthreads();
-            if (wave < NW - 1) ut_bot = xu[wave + 1][lane];
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const float utr = lane_from_right(ut[r]);
-            const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
-            dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r], kc.sigma);
-            u[r] = un[r];
+    // with few rows per lane the loop runs two iterations per trip, so that
+    // the rotation of u between iterations needs no register copies (with 8
+    // or more rows the register pressure undoes the gain)
+    int it = 0;
+    if constexpr (R <= 4) {
+        for (; it + 1 < K; it += 2) {
+            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
+                                  wave, xq, xu);
+            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
+                                  wave, xq, xu);
         }
     }
+    for (; it < K; ++it)
+        tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane, wave,
+                              xq, xu);
 
     float* __restrict__ uout = P.u[cur ^ 1];
     typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];

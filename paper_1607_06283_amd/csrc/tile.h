@@ -33,9 +33,12 @@ __device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 
 }
 
 // One primal-dual iteration of a tile held in registers (u, p, metric
-// constants c per row).  xq, xu: NW x 64 floats of LDS each, for the rows
-// that cross wavefronts.  Pixels outside the image carry all-zero M, so
-// every neighbour term they contribute is 0.
+// constants c per row).  Rows that cross wavefronts go through LDS:
+// xq[w + 1] receives wavefront w's last q_y row and xu[w] its first
+// extrapolated row (NW + 1 rows of 64 floats each); xq[0] and xu[NW] must
+// hold zeros, so every wavefront reads its neighbour row unconditionally.
+// Pixels outside the image carry all-zero M, so every neighbour term they
+// contribute is 0.
 template <int R, int NW>
 __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
                                                float (&p3)[R], const Coef (&c)[R], float tau,
@@ -49,9 +52,9 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
     }
     float qy_top = 0.0f;
     if constexpr (NW > 1) {
-        xq[wave][lane] = qy[R - 1];
+        xq[wave + 1][lane] = qy[R - 1];
         __syncthreads();
-        if (wave > 0) qy_top = xq[wave - 1][lane];
+        qy_top = xq[wave][lane];
     }
     float un[R], ut[R];
 #pragma unroll
@@ -65,7 +68,7 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
     if constexpr (NW > 1) {
         xu[wave][lane] = ut[0];
         __syncthreads();
-        if (wave < NW - 1) ut_bot = xu[wave + 1][lane];
+        ut_bot = xu[wave + 1][lane];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
