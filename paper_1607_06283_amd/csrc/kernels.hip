@@ -633,21 +633,28 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         if (wave == NW - 1) xu[NW][lane] = 0.0f;
     }
 
-    // with few rows per lane the loop runs two iterations per trip, so that
+    // With few rows per lane the loop runs two iterations per trip, so that
     // the rotation of u between iterations needs no register copies (with 8
-    // or more rows the register pressure undoes the gain)
+    // or more rows the register pressure undoes the gain).  With 2 rows per
+    // lane (many wavefronts) a wavefront skips the iterations that cannot
+    // reach the exact interior (about a third of them at K = 13).
+    constexpr bool kSkip = R <= 2 && NW > 1;
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    auto step = [&](int it1) {
+        if (!kSkip || tile_rows_active<R, NW>(wv, it1))
+            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
+                                  wave, xq, xu);
+        else
+            tile_skip<NW>();
+    };
     int it = 0;
     if constexpr (R <= 4) {
         for (; it + 1 < K; it += 2) {
-            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
-                                  wave, xq, xu);
-            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
-                                  wave, xq, xu);
+            step(it + 1);
+            step(it + 2);
         }
     }
-    for (; it < K; ++it)
-        tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane, wave,
-                              xq, xu);
+    for (; it < K; ++it) step(it + 1);
 
     float* __restrict__ uout = P.u[cur ^ 1];
     typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];

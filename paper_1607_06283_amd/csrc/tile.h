@@ -32,13 +32,34 @@ __device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
+// Whether wavefront `wave` must compute iteration `it` (1-based) of a
+// launch.  After `it` iterations of a tile started from exact values
+// everywhere, rows [it, RH - it) are exact (each iteration reads one row
+// above and below), so a wavefront whose rows all lie outside
+// [it - 1, RH - it + 1) cannot influence any row that will be exact later.
+// It may skip the iteration's arithmetic but must still take part in its
+// two barriers (tile_skip); the LDS rows it leaves stale are read only by
+// rows that are themselves outside the exact region.
+template <int R, int NW>
+__device__ __forceinline__ bool tile_rows_active(int wave, int it) {
+    constexpr int RH = NW * R;
+    return wave * R + R >= it && wave * R <= RH - it;
+}
+
+template <int NW>
+__device__ __forceinline__ void tile_skip() {
+    if constexpr (NW > 1) {
+        __syncthreads();
+        __syncthreads();
+    }
+}
+
 // One primal-dual iteration of a tile held in registers (u, p, metric
 // constants c per row).  Rows that cross wavefronts go through LDS:
 // xq[w + 1] receives wavefront w's last q_y row and xu[w] its first
 // extrapolated row (NW + 1 rows of 64 floats each); xq[0] and xu[NW] must
-// hold zeros, so every wavefront reads its neighbour row unconditionally.
-// Pixels outside the image carry all-zero M, so every neighbour term they
-// contribute is 0.
+// hold zeros.  Pixels outside the image carry all-zero M, so every
+// neighbour term they contribute is 0.
 template <int R, int NW>
 __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
                                                float (&p3)[R], const Coef (&c)[R], float tau,
