@@ -211,9 +211,10 @@ void choose_shape(const rec_params* prm, int64_t np, int* rows, int* waves, int*
         if (!r) { r = 2; w = 16; }
         k = 13;
     } else {
-        // 1280x720: 214 G pixel-iterations/s against 206 for (8, 8), K = 8;
-        // 5120x5760: 328 against 309 for K = 4
-        if (!r) { r = 8; w = 4; }
+        // 4 rows x 8 wavefronts, 6 iterations per launch: 1280x720 252 G
+        // pixel-iterations/s, 5120x5760 391 G; 8 x 4 tiles 209 and 329 G,
+        // 4 x 16 tiles 219-255 and 277-303 G
+        if (!r) { r = 4; w = 8; }
         k = 6;
     }
     if (prm->fuse_iters > 0) k = prm->fuse_iters;
