@@ -200,6 +200,30 @@ def test_small_and_ragged_parity(W, H):
         assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
 
 
+@pytest.mark.parametrize("W,H", [(65535, 2), (2, 65535)])
+def test_largest_width_and_height(W, H):
+    """The largest frame side the ABI accepts (65535), with the other side 2:
+    thousands of tiles along one axis; fused and two-kernel loops give the
+    same bits and stay within the tolerance of the FP64 oracle."""
+    t, x, y, p = _random_stream(W, H, 20000, seed=W + H)
+    r, o = make(W, H)
+    r0 = rec.Reconstructor(W, H, fuse_iters=0)
+    for a in (0, 10000):
+        sl = slice(a, a + 10000)
+        print(f"largest side W={W} H={H} block at {a}", flush=True)
+        r.push(t[sl], x[sl], y[sl], p[sl])
+        r0.push(t[sl], x[sl], y[sl], p[sl])
+        o.push(t[sl], x[sl], y[sl], p[sl])
+        r.solve(50)
+        r0.solve(50)
+        o.solve(50)
+        u = r.image(rec.REC_U)
+        assert np.array_equal(u, r0.image(rec.REC_U))
+        assert np.abs(u.astype(np.float64) - o.u).max() <= U_TOL
+    r.close()
+    r0.close()
+
+
 def test_empty_block_and_known_initial_image(c1):
     spec = c1.spec
     u0 = np.exp(evgen.ref0(spec)).astype(np.float32)
