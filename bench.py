@@ -295,8 +295,9 @@ def main_streams64(args):
     warmup = min(args.warmup, 5)
     IT = WORKLOADS["streams64"][3]
     log("bench: 64 cameras, batched")
-    dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False)
-    _, prof, _, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True)
+    tune = not args.no_tune
+    dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False, tune=tune)
+    _, prof, _, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True, tune=tune)
     log("bench: 64 cameras, one solve per camera")
     dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
     value = steps * IT * px / dt / 1e6
@@ -308,7 +309,8 @@ def main_streams64(args):
         "storage": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["streams64"], "cameras": 64, "pixels": px,
                    "events_per_step": evs, "iters_per_batch": IT,
-                   "tile_rows": cfg[0], "tile_waves": cfg[1], "fuse_iters": cfg[2]},
+                   "tile_rows": cfg[0], "tile_waves": cfg[1], "fuse_iters": cfg[2],
+                   "autotuned": tune},
         "events_per_s": round(steps * evs / dt, 1),
         "per_camera_solves": {"value": round(steps * IT * px / dt_solo / 1e6, 2),
                               "ms_per_step": round(dt_solo / steps * 1e3, 4)},
@@ -454,6 +456,8 @@ def main():
                     help="storage of the dual field and time differences (arithmetic is FP32)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="streams64: keep the default tile geometry instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
