@@ -931,8 +931,8 @@ bool fused_shape_supported(int rows, int waves, int storage) {
     if (storage != kStoreF32)
         return key == 216 || key == 416 || key == 804 || key == 808 || key == 408;
     switch (key) {
-        case 202: case 204: case 208: case 216:
-        case 401: case 402: case 404: case 408: case 416:
+        case 202: case 204: case 208: case 216: case 316:
+        case 401: case 402: case 404: case 408: case 416: case 508: case 608:
         case 801: case 802: case 804: case 808:
         case 1601: case 1602: case 1604:
             return true;
@@ -968,11 +968,14 @@ hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts
         REC_FUSED_CASE(2, 4)
         REC_FUSED_CASE(2, 8)
         REC_FUSED_CASE(2, 16)
+        REC_FUSED_CASE(3, 16)
         REC_FUSED_CASE(4, 1)
         REC_FUSED_CASE(4, 2)
         REC_FUSED_CASE(4, 4)
         REC_FUSED_CASE(4, 8)
         REC_FUSED_CASE(4, 16)
+        REC_FUSED_CASE(5, 8)
+        REC_FUSED_CASE(6, 8)
         REC_FUSED_CASE(8, 1)
         REC_FUSED_CASE(8, 2)
         REC_FUSED_CASE(8, 4)

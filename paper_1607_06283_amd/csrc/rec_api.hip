@@ -211,10 +211,15 @@ void choose_shape(const rec_params* prm, int64_t np, int* rows, int* waves, int*
         if (!r) { r = 2; w = 16; }
         k = 13;
     } else {
-        // 4 rows x 8 wavefronts, 6 iterations per launch: 1280x720 252 G
-        // pixel-iterations/s, 5120x5760 391 G; 8 x 4 tiles 209 and 329 G,
-        // 4 x 16 tiles 219-255 and 277-303 G
-        if (!r) { r = 4; w = 8; }
+        // 6 iterations per launch on 6 rows x 8 wavefronts (FP32; 16-bit
+        // storage has no 6-row variant and takes 4 rows): 1280x720 268 G
+        // pixel-iterations/s, 5120x5760 396 G; 4 x 8 tiles 239-252 and
+        // 387-391 G, 8 x 4 tiles 209 and 329 G, 4 x 16 tiles 219-255 and
+        // 277-303 G
+        if (!r) {
+            r = prm->storage == rec::kStoreF32 ? 6 : 4;
+            w = 8;
+        }
         k = 6;
     }
     if (prm->fuse_iters > 0) k = prm->fuse_iters;
@@ -904,8 +909,8 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
     for (int i = 0; i < n; ++i) total += (int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
     choose_shape(&ctxs[0]->prm, total, &r, &w, &k);
     if (!rec::batch_shape_supported(r, w)) {
-        r = 8;
-        w = 4;
+        r = 4;
+        w = 8;
         if (k > 15) k = 15;
     }
     b->shape = Shape{r, w, k};

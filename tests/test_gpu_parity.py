@@ -161,6 +161,8 @@ def test_fused_equals_plain_bitwise(W, H):
             dict(fuse_iters=3, tile_rows=2, tile_waves=8), dict(fuse_iters=1, tile_rows=8, tile_waves=1),
             dict(fuse_iters=15, tile_rows=8, tile_waves=4), dict(fuse_iters=-1),
             dict(fuse_iters=12, tile_rows=2, tile_waves=16, gap_every=5),
+            dict(fuse_iters=6, tile_rows=6, tile_waves=8), dict(fuse_iters=7, tile_rows=5, tile_waves=8),
+            dict(fuse_iters=9, tile_rows=3, tile_waves=16), dict(fuse_iters=6, tile_rows=4, tile_waves=8),
             dict(fuse_iters=0, gap_every=7)]
     for cfg in cfgs:
         r = rec.Reconstructor(W, H, **cfg)
