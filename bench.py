@@ -44,9 +44,12 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("b46dc8f62c016298", 2 * 1024 * 1240.4, 1024 * 889.2),
-    ("probe", "f32"): ("b46dc8f62c016298", 2 * 1024 * 618327.9, 1024 * 526042.2),
+    ("davis240", "f32"): ("9c5419fbfa6433a3", 2 * 1024 * 1240.4, 1024 * 889.2),
+    ("probe", "f32"): ("9c5419fbfa6433a3", 2 * 1024 * 534509.0, 1024 * 525843.9),
+    # the batched launch of all 64 cameras, 6 rows x 8 wavefronts, 6 iterations
+    ("streams64", "f32"): ("9c5419fbfa6433a3", 2 * 1024 * 99231.9, 1024 * 130304.4),
 }
+STREAMS64_MEASURED_SHAPE = (6, 8, 6)
 
 
 def kernel_source_hash() -> str:
@@ -297,11 +300,17 @@ def main_streams64(args):
     log("bench: 64 cameras, batched")
     tune = not args.no_tune
     dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False, tune=tune)
-    _, prof, _, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True, tune=tune)
+    _, prof, cfg_p, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True, tune=tune)
     log("bench: 64 cameras, one solve per camera")
     dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
     value = steps * IT * px / dt / 1e6
     achieved = BYTES_PER_PX_ITER * prof.pd_pixel_iters / (prof.ms[2] * 1e-3) / 1e9
+    avg_us = prof.ms[2] / prof.launches[2] * 1e3
+    traffic, tb = None, None
+    m = MEASURED_TRAFFIC.get(("streams64", "f32"))
+    if m and tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE and m[0] == kernel_source_hash():
+        tb = m[1] + m[2]
+        traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": round(dt / steps * 1e3, 4),
@@ -316,10 +325,11 @@ def main_streams64(args):
                               "ms_per_step": round(dt_solo / steps * 1e3, 4)},
         "batched_speedup": round(dt_solo / dt, 3),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_pd_fused_batch",
-                     "avg_launch_us": round(prof.ms[2] / prof.launches[2] * 1e3, 3),
-                     "launches": int(prof.launches[2]), "bytes_per_px_iter": BYTES_PER_PX_ITER},
+                     "avg_launch_us": round(avg_us, 3),
+                     "launches": int(prof.launches[2]), "bytes_per_px_iter": BYTES_PER_PX_ITER,
+                     "hbm_bytes_per_launch": None if tb is None else round(tb)},
     }
     print(json.dumps(out), flush=True)
 

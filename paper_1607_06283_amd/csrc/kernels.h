@@ -154,7 +154,7 @@ hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipS
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
                            int li, bool bins, int rows, int waves, int storage, hipStream_t s,
                            LaunchEv ev = {});
-bool batch_shape_supported(int rows, int waves);
+bool batch_shape_supported(int rows, int waves, int storage);
 hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max_np,
                                hipStream_t s);
 

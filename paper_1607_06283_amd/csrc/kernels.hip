@@ -648,7 +648,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
             tile_skip<NW>();
     };
     int it = 0;
-    if constexpr (R <= 4) {
+    if constexpr (R <= 6) {
         for (; it + 1 < K; it += 2) {
             step(it + 1);
             step(it + 2);
@@ -1015,6 +1015,7 @@ hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork,
         REC_BATCH_CASE(2, 16)
         REC_BATCH_CASE(4, 8)
         REC_BATCH_CASE(4, 16)
+        REC_BATCH_CASE(6, 8)
         REC_BATCH_CASE(8, 4)
         REC_BATCH_CASE(8, 8)
         default: return hipErrorInvalidValue;
@@ -1023,8 +1024,9 @@ hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork,
 #undef REC_BATCH_CASE
 #undef REC_BATCH_CASE16
 
-bool batch_shape_supported(int rows, int waves) {
+bool batch_shape_supported(int rows, int waves, int storage) {
     const int key = rows * 100 + waves;
+    if (storage == kStoreF32 && key == 608) return true;
     return key == 216 || key == 408 || key == 416 || key == 804 || key == 808;
 }
 

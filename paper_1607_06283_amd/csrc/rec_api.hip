@@ -726,13 +726,15 @@ struct Shape {
 };
 
 // Candidate tile geometries of the batched launch.
-std::vector<Shape> batch_candidates() {
+std::vector<Shape> batch_candidates(int storage) {
     std::vector<Shape> v;
-    const int shapes[][2] = {{2, 16}, {4, 8}, {4, 16}, {8, 4}, {8, 8}};
+    const int shapes[][2] = {{2, 16}, {4, 8}, {4, 16}, {6, 8}, {8, 4}, {8, 8}};
     const int ks[] = {4, 6, 8, 10, 13, 15};
-    for (auto& sh : shapes)
+    for (auto& sh : shapes) {
+        if (!rec::batch_shape_supported(sh[0], sh[1], storage)) continue;
         for (int k : ks)
             if (k <= (sh[0] * sh[1] - 1) / 2 && k <= 31) v.push_back(Shape{sh[0], sh[1], k});
+    }
     return v;
 }
 
@@ -856,7 +858,7 @@ size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n) {
     for (int i = 0; i < n; ++i)
         if (!ctxs[i]) return 0;
     int64_t tiles = 0;
-    for (const Shape& sh : batch_candidates()) {
+    for (const Shape& sh : batch_candidates(ctxs[0]->prm.storage)) {
         const int64_t t = batch_tiles(ctxs, n, sh);
         if (t > tiles) tiles = t;
     }
@@ -908,7 +910,7 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
     int64_t total = 0;
     for (int i = 0; i < n; ++i) total += (int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
     choose_shape(&ctxs[0]->prm, total, &r, &w, &k);
-    if (!rec::batch_shape_supported(r, w)) {
+    if (!rec::batch_shape_supported(r, w, ctxs[0]->prm.storage)) {
         r = 4;
         w = 8;
         if (k > 15) k = 15;
@@ -922,7 +924,7 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
         // tune_iters iterations fastest (ceil(iters / K) launches)
         double best = 1e300;
         Shape pick = b->shape;
-        for (const Shape& sh : batch_candidates()) {
+        for (const Shape& sh : batch_candidates(ctxs[0]->prm.storage)) {
             if (batch_tiles(ctxs, n, sh) > b->work_cap) continue;
             b->shape = sh;
             double us = 0.0;
