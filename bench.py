@@ -388,6 +388,12 @@ def main_diff16(args):
         with torch.no_grad():
             rec.unrolled(u0, npos, nneg, tx, ty, theta, K, w=w, ckpt_every=CK)
 
+    def fwd_bwd_all_states():
+        theta.grad = None
+        w.grad = None
+        u, _ = rec.unrolled(u0, npos, nneg, tx, ty, theta, K, w=w, ckpt_every=1)
+        (0.5 * ((torch.log(u.double()) - L) ** 2).sum()).backward()
+
     batch = rec.Batch(recs, tune_iters=K)
 
     def plain():
@@ -406,6 +412,7 @@ def main_diff16(args):
     log("bench: diff16 forward+backward")
     t_fb = timeit(fwd_bwd)
     t_f = timeit(fwd)
+    t_all = timeit(fwd_bwd_all_states)
     log("bench: diff16 plain batched forward")
     t_p = timeit(plain)
     g_th = theta.grad.cpu().numpy()
@@ -422,6 +429,7 @@ def main_diff16(args):
                    "iters": K, "ckpt_every": CK},
         "fwd_bwd_ms": round(t_fb * 1e3, 3), "diff_fwd_ms": round(t_f * 1e3, 3),
         "plain_fwd_ms": round(t_p * 1e3, 3), "fwd_bwd_over_plain": round(t_fb / t_p, 2),
+        "fwd_bwd_ms_every_state_kept": round(t_all * 1e3, 3),
         "loss": float(out["loss"].item()),
         "grad_theta": [float(v) for v in g_th],
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,

@@ -280,7 +280,9 @@ typedef struct rec_diff_desc {
     int32_t width, height;  /* 1..65535 */
     int32_t batch;          /* images, 1..65535 */
     int32_t iters;          /* unrolled iterations K >= 0 */
-    int32_t ckpt_every;     /* checkpoint interval, 1..max(K, 1) */
+    int32_t ckpt_every;     /* checkpoint interval, 1..max(K, 1); 1 keeps every
+                               state (16 bytes per pixel per iteration) and
+                               the backward recomputes nothing */
     int32_t unfused;        /* 0: fused register-tile kernels (several
                                iterations per launch); 1: one launch per
                                half-step (reference form, same bits) */
