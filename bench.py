@@ -139,7 +139,7 @@ def hd720_stream(n_batches):
 
 
 def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_BATCH,
-            iters=ITERS, rows=0, waves=0, storage=0):
+            iters=ITERS, rows=0, waves=0, storage=0, tvl1=0):
     import torch
     from paper_1607_06283_amd import rec
 
@@ -149,7 +149,7 @@ def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_B
     y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
     p = torch.from_numpy(ev.p).to(dev)
     r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves,
-                          storage=storage)
+                          storage=storage, tvl1_iters=tvl1)
     B = batch
 
     def step(i):
@@ -472,6 +472,8 @@ def main():
     ap.add_argument("--workload", default="davis240", choices=sorted(WORKLOADS))
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage of the dual field and time differences (arithmetic is FP32)")
+    ap.add_argument("--tvl1", type=int, default=0,
+                    help="TV-L1 timestamp-denoising iterations before each block's metric")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--no-tune", action="store_true",
@@ -509,7 +511,8 @@ def main():
     if len(ev) < need * B:
         raise SystemExit("stream too short")
     storage = {"f32": 0, "bf16": 1, "f16": 2}[args.storage]
-    kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves, storage=storage)
+    kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves, storage=storage,
+              tvl1=args.tvl1)
     log("bench: timed pass")
     dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False, **kw)
     px_iters = args.steps * IT * W * H
@@ -523,7 +526,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "width": W, "height": H, "events_per_batch": B,
-                   "iters_per_batch": IT, "fuse_iters": args.fuse,
+                   "iters_per_batch": IT, "fuse_iters": args.fuse, "tvl1_iters": args.tvl1,
                    "tile_rows": args.rows, "tile_waves": args.waves},
         "events_per_s": round(ev_rate, 1),
         "realtime_factor": round(ev_rate / 1e6, 3),
@@ -538,7 +541,7 @@ def main():
         avg_us = pd_ms / pd_launches * 1e3
         traffic, tb = None, None
         m = MEASURED_TRAFFIC.get((args.workload, args.storage))
-        if m and args.fuse == -1 and not args.rows and m[0] == kernel_source_hash():
+        if m and args.fuse == -1 and not args.rows and not args.tvl1 and m[0] == kernel_source_hash():
             tb = m[1] + m[2]
             traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
         out["roofline"] = {

@@ -202,6 +202,65 @@ def test_small_and_ragged_parity(W, H):
         assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
 
 
+@pytest.fixture(scope="module")
+def davis():
+    """The benchmark's 240x180 stream (2 s at 1e6 events/s plus 1 % noise)."""
+    s, bs, nb, iters = evgen.davis240(seed=2)
+    return s.events, bs, iters
+
+
+def test_davis240_benchmark_path_parity(davis):
+    """The first 40 blocks of the benchmark stream through the benchmark's
+    path (device-resident pushes folded into the first fused launch, default
+    tile and launch split): u after every block within 1e-4 of the FP64
+    oracle."""
+    ev, bs, iters = davis
+    r, o = make(240, 180)
+    worst = 0.0
+    for b in evgen.batches(ev, bs)[:40]:
+        r.push(*device_events(b), on_device=True)
+        o.push_events(b)
+        r.solve(iters)
+        o.solve(iters)
+        worst = max(worst, float(np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max()))
+    print(f"240x180 benchmark path, 40 blocks: max-abs {worst:.3e}")
+    assert worst <= U_TOL
+
+
+def test_davis240_full_stream_properties(davis):
+    """All ~2000 blocks of the benchmark stream (the oracle cannot follow the
+    whole stream in test time): every block's events are consumed, the image
+    stays in [u_min, u_max], the dual field stays in its ball, and the gap
+    sampled at the end of the blocks is finite and non-negative."""
+    ev, bs, iters = davis
+    r = rec.Reconstructor(240, 180, gap_every=iters)
+    t, x, y, p = device_events(ev)
+    blocks = evgen.batches(ev, bs)
+    a = 0
+    for i, b in enumerate(blocks):
+        n = len(b)
+        r.push(t[a:a + n], x[a:a + n], y[a:a + n], p[a:a + n], on_device=True)
+        check = i % 250 == 249 or i == len(blocks) - 1
+        st = r.solve(iters, stats=check)
+        if check:
+            assert st.iters_run == iters and st.events_in_batch == n
+            assert np.isfinite(st.gap) and st.gap >= -1e-9 * abs(st.energy)
+        a += n
+    assert a == len(ev)
+    st = r.solve(iters, stats=True)  # an empty block smooths and consumes nothing
+    assert st.events_in_batch == 0
+    u = r.image(rec.REC_U)
+    assert np.isfinite(u).all() and u.min() >= 1.0 and u.max() <= np.float32(np.e)
+    pp = r.image(rec.REC_STATE_P).astype(np.float64)
+    tx = r.image(rec.REC_TX).astype(np.float64)
+    ty = r.image(rec.REC_TY).astype(np.float64)
+    s = np.sqrt(1.0 + tx * tx + ty * ty)
+    assert (np.sqrt((pp * pp).sum(axis=0)) <= s * (1 + 1e-6)).all()
+    print(f"240x180 full stream: {a} events in {len(blocks)} blocks, final gap {st.gap:.3e}, "
+          f"energy {st.energy:.6e}")
+    r.close()
+
+
 @pytest.mark.parametrize("W,H", [(65535, 2), (2, 65535)])
 def test_largest_width_and_height(W, H):
     """The largest frame side the ABI accepts (65535), with the other side 2:
