@@ -354,6 +354,114 @@ __global__ void k_tvl1_finish(Planes P, Frame fr, int cur) {
     S::st((typename S::T*)P.ty, k, dy);
 }
 
+// The same denoising in one launch for up to kTvl1FusedMax iterations: a
+// 64 x 32 register tile (2 rows per lane, 16 wavefronts) with a halo of
+// iters + 1 pixels runs every iteration in registers (neighbours through DPP
+// and LDS, as in the primal-dual tile) and writes tx, ty of its interior.
+// Each pixel's arithmetic and its order are those of the kernels above.
+constexpr int kTvl1FusedMax = 14;
+
+__device__ __forceinline__ double lane_from_left_d(double v) {
+    return __hiloint2double(__float_as_int(lane_from_left(__int_as_float(__double2hiint(v)))),
+                            __float_as_int(lane_from_left(__int_as_float(__double2loint(v)))));
+}
+__device__ __forceinline__ double lane_from_right_d(double v) {
+    return __hiloint2double(__float_as_int(lane_from_right(__int_as_float(__double2hiint(v)))),
+                            __float_as_int(lane_from_right(__int_as_float(__double2loint(v)))));
+}
+
+template <class S>
+__global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double ts, int iters,
+                                                     double lambda, int tiles_x, int ntiles) {
+    constexpr int R = 2, NW = 16, RH = R * NW;
+    const int KH = iters + 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int tile = xcd_tile(blockIdx.x, ntiles);
+    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int gx = txi * (64 - 2 * KH) - KH + lane;
+    const int gy0 = tyi * (RH - 2 * KH) - KH + wave * R;
+    const bool col_in = gx >= 0 && gx < fr.W;
+    const bool hx = gx < fr.W - 1, lx = gx > 0;
+    const DevState* st = P.st;
+    const int64_t t_ref = st->t_ref, t_first = st->t_first;
+    const double s = 0.35355339059327373;  // 1 / sqrt(8)
+    const double tl = s * lambda;
+    double v0[R], v[R], q1[R], q2[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int gy = gy0 + r;
+        v0[r] = 0.0;
+        if (col_in && gy >= 0 && gy < fr.H)
+            v0[r] = (double)(t_ref - resolved_last(P.t_last[(size_t)gy * fr.W + gx], t_first)) / ts;
+        v[r] = v0[r];
+        q1[r] = 0.0;
+        q2[r] = 0.0;
+    }
+    // xq[w + 1]: wavefront w's last q2 row; xb[w]: its first row of 2 vn - v
+    // (then of v); xq[0] and xb[NW] stay zero
+    __shared__ double xq[NW + 1][64];
+    __shared__ double xb[NW + 1][64];
+    if (wave == 0) xq[0][lane] = 0.0;
+    if (wave == NW - 1) xb[NW][lane] = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        double qxl[R], vn[R], b[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) qxl[r] = lane_from_left_d(q1[r]);
+        xq[wave + 1][lane] = q2[R - 1];
+        __syncthreads();
+        const double qy_top = xq[wave][lane];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            double d = 0.0;
+            if (hx) d += q1[r];
+            if (lx) d -= qxl[r];
+            if (gy < fr.H - 1) d += q2[r];
+            if (gy > 0) d -= r > 0 ? q2[r - 1] : qy_top;
+            const double w = v[r] + s * d - v0[r];
+            const double rr = w > tl ? w - tl : (w < -tl ? w + tl : 0.0);
+            vn[r] = v0[r] + rr;
+            b[r] = 2.0 * vn[r] - v[r];
+        }
+        xb[wave][lane] = b[0];
+        __syncthreads();
+        const double b_bot = xb[wave + 1][lane];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            const double br = lane_from_right_d(b[r]);
+            const double bd = r < R - 1 ? b[r + 1] : b_bot;
+            const double gxx = hx ? br - b[r] : 0.0;
+            const double gyy = gy < fr.H - 1 ? bd - b[r] : 0.0;
+            const double a = q1[r] + s * gxx, c = q2[r] + s * gyy;
+            double m = sqrt(a * a + c * c);
+            if (m < 1.0) m = 1.0;
+            q1[r] = a / m;
+            q2[r] = c / m;
+            v[r] = vn[r];
+        }
+        // the next iteration writes xq and xb only after its first barrier,
+        // which every wavefront reaches after reading them here
+    }
+    __syncthreads();  // every wavefront has read xb before it is reused
+    xb[wave][lane] = v[0];
+    __syncthreads();
+    const double v_bot = xb[wave + 1][lane];
+    const bool col_out = col_in && lane >= KH && lane < 64 - KH;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int row = wave * R + r, gy = gy0 + r;
+        const double vr = lane_from_right_d(v[r]);
+        const double vd = r < R - 1 ? v[r + 1] : v_bot;
+        if (!(col_out && row >= KH && row < RH - KH && gy >= 0 && gy < fr.H)) continue;
+        const size_t k = (size_t)gy * fr.W + gx;
+        const float dx = hx ? (float)(vr - v[r]) : 0.0f;
+        const float dy = gy < fr.H - 1 ? (float)(vd - v[r]) : 0.0f;
+        S::st((typename S::T*)P.tx, k, dx);
+        S::st((typename S::T*)P.ty, k, dy);
+    }
+}
+
 // ---------------------------------------------------------------- plain loop
 
 // Primal half-step for every pixel: needs q = M^T p here, at the left and
@@ -894,6 +1002,21 @@ hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool
 hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
                        int storage, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
+    if (iters <= kTvl1FusedMax) {
+        const int kh = iters + 1;
+        const int tiles_x = (fr.W + 64 - 2 * kh - 1) / (64 - 2 * kh);
+        const int tiles_y = (fr.H + 32 - 2 * kh - 1) / (32 - 2 * kh);
+        const int nt = tiles_x * tiles_y;
+        const dim3 gt(nt), bt(1024);
+        if (storage == kStoreF16)
+            return launch(k_tvl1_fused<StoreF16>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts, iters,
+                          lambda, tiles_x, nt);
+        if (storage == kStoreBF16)
+            return launch(k_tvl1_fused<StoreBF16>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts,
+                          iters, lambda, tiles_x, nt);
+        return launch(k_tvl1_fused<StoreF32>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts, iters,
+                      lambda, tiles_x, nt);
+    }
     const dim3 g(blocks_for(np, 256)), b(256);
     hipError_t e = launch(k_tvl1_init, g, b, 0, s, ev.start, nullptr, P, fr, ts);
     int cur = 0;

@@ -318,6 +318,16 @@ class Reconstructor:
         n = int(t.shape[0])
         if on_device is None:
             on_device = not isinstance(t, np.ndarray)
+        if on_device:
+            for a in (t, x, y, p):
+                if isinstance(a, np.ndarray) or getattr(a, "device", None) is None or \
+                        a.device.type != "cuda":
+                    raise ValueError("on_device pushes need device (HIP) tensors")
+                if not a.is_contiguous():
+                    raise ValueError("event tensors must be contiguous")
+            for a, size, name in ((t, 8, "t"), (x, 2, "x"), (y, 2, "y"), (p, 1, "p")):
+                if a.element_size() != size or int(a.shape[0]) < n:
+                    raise ValueError(f"{name} must hold n elements of {size} bytes")
         if not on_device:
             t = np.ascontiguousarray(t, np.int64)
             x = np.ascontiguousarray(x, np.uint16)
@@ -476,14 +486,23 @@ def _unrolled_function():
         sweep with checkpoints (rec_diff_forward / rec_diff_backward)."""
 
         @staticmethod
+        def _prep(u0, w, theta, p0, npos, nneg, tx, ty):
+            """Contiguous device tensors of the library's types (the same
+            values, so forward and backward see identical inputs)."""
+            dev = u0.device
+            if dev.type != "cuda":
+                raise ValueError("the inputs must be device (HIP) tensors")
+            f32 = lambda a: None if a is None else a.detach().to(dev, torch.float32).contiguous()
+            i32 = lambda a: a.detach().to(dev, torch.int32).contiguous()
+            return dict(u0=f32(u0), w=f32(w), p0=f32(p0), npos=i32(npos), nneg=i32(nneg),
+                        tx=f32(tx), ty=f32(ty),
+                        theta=theta.detach().to(dev, torch.float64).contiguous())
+
+        @staticmethod
         def forward(ctx, u0, w, theta, p0, npos, nneg, tx, ty, desc):
             dev = u0.device
             B, H, W = desc.batch, desc.height, desc.width
-            f32 = lambda a: None if a is None else a.detach().to(dev, torch.float32).contiguous()
-            i32 = lambda a: a.detach().to(dev, torch.int32).contiguous()
-            t = dict(u0=f32(u0), w=f32(w), p0=f32(p0), npos=i32(npos), nneg=i32(nneg),
-                     tx=f32(tx), ty=f32(ty),
-                     theta=theta.detach().to(dev, torch.float64).contiguous())
+            t = UnrolledPD._prep(u0, w, theta, p0, npos, nneg, tx, ty)
             if t["u0"].shape != (B, H, W) or (t["p0"] is not None and t["p0"].shape != (B, 3, H, W)):
                 raise ValueError("u0 must be [B, H, W] and p0 [B, 3, H, W]")
             for k in ("w", "npos", "nneg", "tx", "ty"):
@@ -503,13 +522,16 @@ def _unrolled_function():
             with torch.cuda.device(dev):
                 _check(rec_diff_forward(desc, inputs, u_out, p_out, ws.data_ptr(), nbytes,
                                         stream), "rec_diff_forward")
-            ctx.desc, ctx.ws, ctx.nbytes, ctx.t = desc, ws, nbytes, t
+            # the original inputs are saved so that autograd's version check
+            # rejects an in-place change between forward and backward
+            ctx.save_for_backward(u0, w, theta, p0, npos, nneg, tx, ty)
+            ctx.desc, ctx.ws, ctx.nbytes = desc, ws, nbytes
             return u_out, p_out
 
         @staticmethod
         @torch.autograd.function.once_differentiable
         def backward(ctx, g_u, g_p):
-            t, desc = ctx.t, ctx.desc
+            t, desc = UnrolledPD._prep(*ctx.saved_tensors), ctx.desc
             dev = t["u0"].device
             B, H, W = desc.batch, desc.height, desc.width
             need_u0, need_w, need_th, need_p0 = ctx.needs_input_grad[:4]

@@ -261,6 +261,29 @@ def test_davis240_full_stream_properties(davis):
     r.close()
 
 
+def test_binding_rejects_host_and_mistyped_tensors():
+    """Tensors that would hand the device a host pointer or a wrong element
+    size are refused in the binding, before any launch."""
+    import torch
+    r = rec.Reconstructor(16, 16)
+    t = torch.arange(5, dtype=torch.int64) + evgen.T0_US
+    x = torch.zeros(5, dtype=torch.int16)
+    pol = torch.ones(5, dtype=torch.int8)
+    with pytest.raises(ValueError):
+        r.push(t, x, x, pol)                           # CPU tensors
+    with pytest.raises(ValueError):
+        r.push(t.cuda().to(torch.int32), x.cuda(), x.cuda(), pol.cuda())
+    r.push(t.cuda(), x.cuda(), x.cuda(), pol.cuda())   # well-formed
+    r.solve(5)
+    assert np.isfinite(r.image(rec.REC_U)).all()
+    r.close()
+    inp = evgen.diff_inputs(3, 1, 8, 8)
+    th = torch.tensor([90.0, 0.2, 0.2], dtype=torch.float64)
+    c = {k: torch.from_numpy(v) for k, v in inp.items()}
+    with pytest.raises(ValueError):
+        rec.unrolled(c["u0"], c["npos"], c["nneg"], c["tx"], c["ty"], th, 3)
+
+
 @pytest.mark.parametrize("W,H", [(65535, 2), (2, 65535)])
 def test_largest_width_and_height(W, H):
     """The largest frame side the ABI accepts (65535), with the other side 2:
@@ -550,6 +573,26 @@ def test_denoised_time_differences_and_image(noisy, fuse):
         assert np.allclose(tx, o.get(oracle.TX32), rtol=1e-6, atol=1e-9)
         assert np.allclose(ty, o.get(oracle.TY32), rtol=1e-6, atol=1e-9)
         assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
+
+
+@pytest.mark.parametrize("iters", [1, 5, 14, 15, 20])
+def test_denoised_time_differences_exact(noisy, iters):
+    """Up to 14 iterations the denoising runs as one tiled launch, beyond as
+    one launch per half-step; both repeat the oracle's FP64 operations in
+    order, so the rounded time differences equal the oracle's bit for bit."""
+    r, o = make(96, 72, tvl1_iters=iters, tvl1_lambda=1.0)
+    n = len(noisy)
+    for a in range(0, n - n % 2, n // 2):
+        b = noisy.slice(a, a + n // 2)
+        r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(3)
+        o.solve(3)
+        for which, plane in ((rec.REC_TX, oracle.TX32), (rec.REC_TY, oracle.TY32)):
+            g, ref = r.image(which), o.get(plane)
+            print(f"tvl1 iters={iters}: max |d| {np.abs(g - ref).max():.3e}")
+            assert np.array_equal(g, ref)
+    r.close()
 
 
 def test_denoising_flattens_noise_spikes(noisy):
