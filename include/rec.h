@@ -113,9 +113,12 @@ typedef struct {
                                 most k (also capped by the tile height) */
     int32_t max_events;      /* largest host-pointer push handled in one piece (larger
                                 pushes are split); sizes the device staging; default 65536 */
-    int32_t tile_rows;       /* rows per lane in the fused kernel (2, 4, 8, 16); 0 = automatic */
-    int32_t tile_waves;      /* wavefronts per fused workgroup (1..16); 0 = automatic;
-                                set both or neither */
+    int32_t tile_rows;       /* fused tile: rows per lane x wavefronts per workgroup, one of */
+    int32_t tile_waves;      /*   2x2 2x4 2x8 2x16 3x16 4x1 4x2 4x4 4x8 4x16 5x8 6x8 8x1
+                                  8x2 8x4 8x8 16x1 16x2 16x4 (16-bit storage: 2x16 4x8 4x16
+                                  8x4 8x8); 0, 0 = automatic (frames up to 250k pixels 2x16,
+                                  larger 6x8, or 4x8 with 16-bit storage); set both or
+                                  neither */
     int32_t storage;         /* storage of the dual field p and of tx, ty: REC_STORE_F32
                                 (default), REC_STORE_BF16 or REC_STORE_F16; the arithmetic
                                 is FP32 in every case (16-bit forms need the fused loop) */
