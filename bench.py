@@ -139,7 +139,7 @@ def hd720_stream(n_batches):
 
 
 def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_BATCH,
-            iters=ITERS, rows=0, waves=0, storage=0, tvl1=0):
+            iters=ITERS, rows=0, waves=0, storage=0, tvl1=0, cols=0):
     import torch
     from paper_1607_06283_amd import rec
 
@@ -149,7 +149,7 @@ def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_B
     y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
     p = torch.from_numpy(ev.p).to(dev)
     r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves,
-                          storage=storage, tvl1_iters=tvl1)
+                          tile_cols=cols, storage=storage, tvl1_iters=tvl1)
     B = batch
 
     def step(i):
@@ -469,6 +469,8 @@ def main():
                     help="iterations per fused launch (-1: chosen by the library, 0: unfused)")
     ap.add_argument("--rows", type=int, default=0, help="rows per lane of the fused tile (0: auto)")
     ap.add_argument("--waves", type=int, default=0, help="wavefronts per fused workgroup (0: auto)")
+    ap.add_argument("--cols", type=int, default=0,
+                    help="fused tile width, 64 or 32 (0: auto; needs --rows/--waves)")
     ap.add_argument("--workload", default="davis240", choices=sorted(WORKLOADS))
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage of the dual field and time differences (arithmetic is FP32)")
@@ -512,7 +514,7 @@ def main():
         raise SystemExit("stream too short")
     storage = {"f32": 0, "bf16": 1, "f16": 2}[args.storage]
     kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves, storage=storage,
-              tvl1=args.tvl1)
+              tvl1=args.tvl1, cols=args.cols)
     log("bench: timed pass")
     dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False, **kw)
     px_iters = args.steps * IT * W * H
@@ -527,7 +529,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "width": W, "height": H, "events_per_batch": B,
                    "iters_per_batch": IT, "fuse_iters": args.fuse, "tvl1_iters": args.tvl1,
-                   "tile_rows": args.rows, "tile_waves": args.waves},
+                   "tile_rows": args.rows, "tile_waves": args.waves, "tile_cols": args.cols},
         "events_per_s": round(ev_rate, 1),
         "realtime_factor": round(ev_rate / 1e6, 3),
     }

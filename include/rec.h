@@ -116,9 +116,12 @@ typedef struct {
     int32_t tile_rows;       /* fused tile: rows per lane x wavefronts per workgroup, one of */
     int32_t tile_waves;      /*   2x2 2x4 2x8 2x16 3x16 4x1 4x2 4x4 4x8 4x16 5x8 6x8 8x1
                                   8x2 8x4 8x8 16x1 16x2 16x4 (16-bit storage: 2x16 4x8 4x16
-                                  8x4 8x8); 0, 0 = automatic (frames up to 250k pixels 2x16,
-                                  larger 6x8, or 4x8 with 16-bit storage); set both or
-                                  neither */
+                                  8x4 8x8) with 64 columns; set both or neither.  0, 0 =
+                                  automatic by frame size (tile_cols 0 too): up to 60k
+                                  pixels 1x16 of 32 columns, up to 120k 2x8 of 32 columns,
+                                  up to 400k 4x16, up to 600k 2x8 of 32 columns, larger 6x8
+                                  (16-bit storage: 2x8 of 32 columns for the 32-column
+                                  cases, 4x8 for the largest frames) */
     int32_t storage;         /* storage of the dual field p and of tx, ty: REC_STORE_F32
                                 (default), REC_STORE_BF16 or REC_STORE_F16; the arithmetic
                                 is FP32 in every case (16-bit forms need the fused loop) */
@@ -127,7 +130,12 @@ typedef struct {
                                 count nor weight): FP64 Chambolle-Pock iterations for
                                 min TV(v) + tvl1_lambda |v - tau|_1; 0 = off (default) */
     double tvl1_lambda;      /* L1 weight of the denoising, > 0; default 1 */
-    int32_t reserved[4];     /* must be 0 */
+    int32_t tile_cols;       /* fused tile width: 64 (one row of 64 lanes per wavefront) or
+                                32 (two rows of 32 lanes per wavefront; shapes 1x8 1x16 2x4
+                                2x8 2x16 3x8 4x4 4x8, 16-bit storage 2x8; the tile covers
+                                32 columns x 2 * rows * waves rows); 0 = 64 when tile_rows
+                                is set, automatic otherwise; set only with tile_rows */
+    int32_t reserved[3];     /* must be 0 */
 } rec_params;
 
 /* Statistics of one rec_solve (filled when stats are requested). */

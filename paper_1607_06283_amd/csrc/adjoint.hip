@@ -60,8 +60,9 @@ struct State {
 };
 
 struct Steps {
-    double tau_d;          // tau in FP64 (for tau * lambda, as the forward solve forms it)
-    float tau, sigma, umin, umax;
+    double tau_d;  // tau in FP64 (for tau * lambda, as the forward solve forms it)
+    float ts;      // tau / sigma (the primal step on the sigma-scaled coefficients)
+    float sigma, umin, umax;
 };
 
 __device__ __forceinline__ bool pixel(const Dims& d, int& i, int& j, size_t& o, size_t& b) {
@@ -81,19 +82,21 @@ __device__ __forceinline__ float taulam_w(const double* theta, double tau, const
 }
 
 // q_x of the left neighbour / q_y of the upper neighbour of field v
-// (3 planes of stride np starting at v), 0 outside the image.
+// (3 planes of stride np starting at v; coefficients sigma M), 0 outside the
+// image.
 __device__ __forceinline__ float qx_left(const Dims& d, int i, int j, size_t o, const float* tx,
-                                         const float* ty, const float* v1, size_t np) {
+                                         const float* ty, const float* v1, size_t np,
+                                         float sigma) {
     if (j == 0) return 0.0f;
     const size_t l = o - 1;
-    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, true, i < d.H - 1);
+    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, sigma, true, i < d.H - 1);
     return q_x(c, v1[l], v1[np + l], v1[2 * np + l]);
 }
 __device__ __forceinline__ float qy_up(const Dims& d, int i, int j, size_t o, const float* tx,
-                                       const float* ty, const float* v1, size_t np) {
+                                       const float* ty, const float* v1, size_t np, float sigma) {
     if (i == 0) return 0.0f;
     const size_t l = o - d.W;
-    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, j < d.W - 1, true);
+    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, sigma, j < d.W - 1, true);
     return q_y(c, v1[l], v1[np + l], v1[2 * np + l]);
 }
 
@@ -135,13 +138,13 @@ __global__ __launch_bounds__(kThreads) void k_diff_primal(Dims d, State a, State
     if (!pixel(d, i, j, o, b)) return;
     const size_t q = field(d, b, o);
     const float* p = a.p + (q - o);  // image b's field, indexed by o
-    const Coef c = make_coef(tx[o], ty[o], f[o], taulam_w(theta, st.tau_d, w, o), j < d.W - 1,
-                             i < d.H - 1);
+    const Coef c = make_coef(tx[o], ty[o], f[o], taulam_w(theta, st.tau_d, w, o), st.sigma,
+                             j < d.W - 1, i < d.H - 1);
     const float qx = q_x(c, p[o], p[d.np + o], p[2 * d.np + o]);
     const float qy = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
-    const float qxl = qx_left(d, i, j, o, tx, ty, p, d.np);
-    const float qyu = qy_up(d, i, j, o, tx, ty, p, d.np);
-    b_.u[o] = primal(a.u[o], qx, qy, qxl, qyu, c, st.tau, st.umin, st.umax);
+    const float qxl = qx_left(d, i, j, o, tx, ty, p, d.np, st.sigma);
+    const float qyu = qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma);
+    b_.u[o] = primal(a.u[o], qx, qy, qxl, qyu, c, st.ts, st.umin, st.umax);
 }
 
 // Dual half-step: p of state a, primal a.u -> b.u, into b.p.
@@ -155,10 +158,10 @@ __global__ __launch_bounds__(kThreads) void k_diff_dual(Dims d, State a, State b
     float gx = 0.0f, gy = 0.0f;
     if (j < d.W - 1) gx = extrapolate(b_.u[o + 1], a.u[o + 1]) - ut;
     if (i < d.H - 1) gy = extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut;
-    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
     const size_t q = field(d, b, o);
     float p1 = a.p[q], p2 = a.p[q + d.np], p3 = a.p[q + 2 * d.np];
-    dual(p1, p2, p3, gx, gy, c, st.sigma);
+    dual(p1, p2, p3, gx, gy, c);
     b_.p[q] = p1;
     b_.p[q + d.np] = p2;
     b_.p[q + 2 * d.np] = p3;
@@ -188,10 +191,11 @@ struct Adj {
 };
 
 // hat p of the state after the latest reverse step, at one pixel:
-// q - tau L_g ub_hat (first = no step yet: g_p, or 0).
+// q - tau L_g ub_hat = q - ts C grad ub_hat, ts = tau / sigma (first = no
+// step yet: g_p, or 0).
 __device__ __forceinline__ void adj_p(const Dims& d, int i, int j, size_t o, size_t q,
                                       const Coef& c, const Adj& A, const float* g_p, bool first,
-                                      float tau, float& h1, float& h2, float& h3) {
+                                      float ts, float& h1, float& h2, float& h3) {
     if (first) {
         h1 = g_p ? g_p[q] : 0.0f;
         h2 = g_p ? g_p[q + d.np] : 0.0f;
@@ -204,9 +208,9 @@ __device__ __forceinline__ void adj_p(const Dims& d, int i, int j, size_t o, siz
     const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
     const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
     const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
-    h1 = __builtin_fmaf(-tau, v1, A.q[q]);
-    h2 = __builtin_fmaf(-tau, v2, A.q[q + d.np]);
-    h3 = __builtin_fmaf(-tau, v3, A.q[q + 2 * d.np]);
+    h1 = __builtin_fmaf(-ts, v1, A.q[q]);
+    h2 = __builtin_fmaf(-ts, v2, A.q[q + d.np]);
+    h3 = __builtin_fmaf(-ts, v3, A.q[q + 2 * d.np]);
 }
 
 // Reverse of the dual half-step of the iteration a -> b: q = J_proj^T h_p.
@@ -219,19 +223,15 @@ __global__ __launch_bounds__(kThreads) void k_adj_dual(Dims d, State a, State b_
     size_t o, b;
     if (!pixel(d, i, j, o, b)) return;
     const size_t q = field(d, b, o);
-    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
     float h1, h2, h3;
-    adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.tau, h1, h2, h3);
+    adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.ts, h1, h2, h3);
     // pbar of the forward step, recomputed
     const float ut = extrapolate(b_.u[o], a.u[o]);
     const float gx = j < d.W - 1 ? extrapolate(b_.u[o + 1], a.u[o + 1]) - ut : 0.0f;
     const float gy = i < d.H - 1 ? extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut : 0.0f;
-    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
-    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
-    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
-    const float b1 = __builtin_fmaf(st.sigma, v1, a.p[q]);
-    const float b2 = __builtin_fmaf(st.sigma, v2, a.p[q + d.np]);
-    const float b3 = __builtin_fmaf(st.sigma, v3, a.p[q + 2 * d.np]);
+    float b1, b2, b3;
+    dual_ascent(c, gx, gy, a.p[q], a.p[q + d.np], a.p[q + 2 * d.np], b1, b2, b3);
     const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
     const float sc = c.s * rsq(n2);
     if (sc < 1.0f) {  // the forward projected this point (same test as its min)
@@ -262,22 +262,22 @@ __global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
     const float* qf = A.q + (q - o);
     const float* p = a.p + (q - o);
     const float fo = f[o];
-    const Coef c = make_coef(tx[o], ty[o], fo, taulam_w(theta, st.tau_d, w, o), j < d.W - 1,
-                             i < d.H - 1);
-    // ut_hat = sigma L_g^* q = -sigma div(M^T q)
+    const Coef c = make_coef(tx[o], ty[o], fo, taulam_w(theta, st.tau_d, w, o), st.sigma,
+                             j < d.W - 1, i < d.H - 1);
+    // ut_hat = sigma L_g^* q = -div(C^T q)
     const float qx = q_x(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
     const float qy = q_y(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
-    const float divq = (qx - qx_left(d, i, j, o, tx, ty, qf, d.np)) +
-                       (qy - qy_up(d, i, j, o, tx, ty, qf, d.np));
-    const float ut_hat = -st.sigma * divq;
+    const float divq = (qx - qx_left(d, i, j, o, tx, ty, qf, d.np, st.sigma)) +
+                       (qy - qy_up(d, i, j, o, tx, ty, qf, d.np, st.sigma));
+    const float ut_hat = -divq;
     const float hu = first ? (g_u ? g_u[o] : 0.0f) : A.uh[o];
     const float H = __builtin_fmaf(2.0f, ut_hat, hu);
     // the forward's root, recomputed
     const float px = q_x(c, p[o], p[d.np + o], p[2 * d.np + o]);
     const float py = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
     float r;
-    const float un = prox_root(a.u[o], px, py, qx_left(d, i, j, o, tx, ty, p, d.np),
-                               qy_up(d, i, j, o, tx, ty, p, d.np), c, st.tau, r);
+    const float un = prox_root(a.u[o], px, py, qx_left(d, i, j, o, tx, ty, p, d.np, st.sigma),
+                               qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma), c, st.ts, r);
     const bool active = un >= st.umin && un <= st.umax;
     const float hr = active ? H * rcp(r) : 0.0f;
     const float ub_hat = un * hr;
@@ -310,10 +310,10 @@ __global__ __launch_bounds__(kThreads) void k_adj_final(
     double s_lam = 0.0, s_dp = 0.0, s_dn = 0.0;
     if (pixel(d, i, j, o, b)) {
         const size_t q = field(d, b, o);
-        const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, j < d.W - 1, i < d.H - 1);
+        const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
         if (gp0) {
             float h1, h2, h3;
-            adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.tau, h1, h2, h3);
+            adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.ts, h1, h2, h3);
             gp0[q] = h1;
             gp0[q + d.np] = h2;
             gp0[q + 2 * d.np] = h3;
@@ -442,7 +442,7 @@ __device__ __forceinline__ void store_state(const Dims& d, const TileGrid& g, co
 template <int R>
 __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, const float* f,
                                            const float* tx, const float* ty, const float* w,
-                                           float tl, Coef (&c)[R], float (&fr)[R]) {
+                                           float tl, float sigma, Coef (&c)[R], float (&fr)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = t.gy0 + r;
@@ -456,7 +456,7 @@ __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, cons
             if (w) tlw = tl * w[k];
         }
         fr[r] = ff;
-        c[r] = make_coef(x, y, ff, tlw, in && t.gx < d.W - 1, in && gy < d.H - 1);
+        c[r] = make_coef(x, y, ff, tlw, sigma, in && t.gx < d.W - 1, in && gy < d.H - 1);
     }
 }
 
@@ -474,7 +474,8 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
     const int K = g.kg;
     float u[R], p1[R], p2[R], p3[R], fr[R];
     Coef c[R];
-    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), c, fr);
+    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), st.sigma, c,
+                 fr);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = t.gy0 + r;
@@ -493,8 +494,8 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
     if (t.wave == 0) xq[0][t.lane] = 0.0f;
     if (t.wave == NW - 1) xu[NW][t.lane] = 0.0f;
     for (int it = 0; it < K; ++it) {
-        tile_iteration<R, NW>(u, p1, p2, p3, c, st.tau, st.sigma, st.umin, st.umax, t.lane,
-                              t.wave, xq, xu);
+        tile_iteration<R, NW>(u, p1, p2, p3, c, st.ts, st.umin, st.umax, t.lane, t.wave, xq,
+                              xu);
         if (rec.u && it < K - 1)
             store_state<R, NW>(d, g, t, rec.u + it * rec.stride, rec.p + it * rec.stride, u, p1,
                                p2, p3);
@@ -535,7 +536,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
     const int lane = t.lane, wave = t.wave;
     float fr[R];
     Coef c[R];
-    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), c, fr);
+    tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), st.sigma, c,
+                 fr);
     float u1[R], Q1[R], Q2[R], Q3[R], UB[R], UH[R], GB[R], GF[R];
     bool inside[R];
     size_t kk[R];
@@ -612,15 +614,13 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
             const float ubr = lane_from_right(UB[r]);
             const float ubd = r < R - 1 ? UB[r + 1] : ub_bot;
             const float gx = ubr - UB[r], gy = ubd - UB[r];
-            float h1 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b12, gy, cc.a11 * gx), Q1[r]);
-            float h2 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b22, gy, cc.a21 * gx), Q2[r]);
-            float h3 = __builtin_fmaf(-st.tau, __builtin_fmaf(cc.b32, gy, cc.a31 * gx), Q3[r]);
+            float h1 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b12, gy, cc.a11 * gx), Q1[r]);
+            float h2 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b22, gy, cc.a21 * gx), Q2[r]);
+            float h3 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b32, gy, cc.a31 * gx), Q3[r]);
             const float utr = lane_from_right(ut[r]);
             const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
-            const float ex = utr - ut[r], ey = utd - ut[r];
-            const float b1 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b12, ey, cc.a11 * ex), pa[r]);
-            const float b2 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b22, ey, cc.a21 * ex), pb[r]);
-            const float b3 = __builtin_fmaf(st.sigma, __builtin_fmaf(cc.b32, ey, cc.a31 * ex), pc[r]);
+            float b1, b2, b3;
+            dual_ascent(cc, utr - ut[r], utd - ut[r], pa[r], pb[r], pc[r], b1, b2, b3);
             const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
             const float sc = cc.s * rsq(n2);
             if (sc < 1.0f) {
@@ -657,12 +657,12 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
         for (int r = 0; r < R; ++r) {
             const float qxl = lane_from_left(qxq[r]);
             const float qyu = r > 0 ? qyq[r - 1] : qyq_top;
-            const float ut_hat = -st.sigma * ((qxq[r] - qxl) + (qyq[r] - qyu));
+            const float ut_hat = -((qxq[r] - qxl) + (qyq[r] - qyu));
             const float H = __builtin_fmaf(2.0f, ut_hat, UH[r]);
             const float pxl = lane_from_left(qxp[r]);
             const float pyu = r > 0 ? qyp[r - 1] : qyp_top;
             float rr;
-            const float un = prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r], st.tau, rr);
+            const float un = prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r], st.ts, rr);
             const bool active = un >= st.umin && un <= st.umax;
             const float hr = active ? H * rcp(rr) : 0.0f;
             const float ub = un * hr;
@@ -845,7 +845,8 @@ int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size
     x.cv = carve(d, (char*)ws);
     if (bytes < x.cv.bytes) return REC_ENOMEM;
     x.dims = Dims{d->width, d->height, (size_t)d->width * d->height};
-    x.st = Steps{d->tau, (float)d->tau, (float)d->sigma, (float)d->u_min, (float)d->u_max};
+    x.st = Steps{d->tau, (float)(d->tau / d->sigma), (float)d->sigma, (float)d->u_min,
+                 (float)d->u_max};
     x.grid = grid_of(d);
     x.fs = fused_shape(d);
     return REC_OK;

@@ -61,9 +61,10 @@ struct Frame {
     int32_t W, H;
 };
 
-// FP32 constants of the iteration.
+// FP32 constants of the iteration: ts = tau / sigma (the primal step on the
+// sigma-scaled coefficients), sigma, tau * lambda, the clamp range.
 struct IterConsts {
-    float tau, sigma, taulam, umin, umax;
+    float ts, sigma, taulam, umin, umax;
 };
 
 // Constants of the data image and time-surface build (FP64).
@@ -120,8 +121,8 @@ struct LaunchEv {
 };
 
 size_t gap_blocks(size_t np);
-size_t fused_lds_bytes(int rows, int waves, int mode);
-int fused_tiles(Frame fr, int rows, int waves, int iters);
+size_t fused_lds_bytes(int rows, int waves, int cols, int mode);
+int fused_tiles(Frame fr, int rows, int waves, int cols, int iters);
 
 // Launchers: return the first HIP error (launch errors only; no sync).
 hipError_t launch_init(const Planes& P, Frame fr, float u_init, bool keep_u, hipStream_t s);
@@ -140,8 +141,8 @@ hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts k, int cur, hip
                            LaunchEv ev = {});
 hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts k, BuildConsts bc,
                            const EventSegs& segs, int cur, int iters, int mode, int rows,
-                           int waves, int storage, hipStream_t s, LaunchEv ev = {});
-bool fused_shape_supported(int rows, int waves, int storage);
+                           int waves, int cols, int storage, hipStream_t s, LaunchEv ev = {});
+bool fused_shape_supported(int rows, int waves, int cols, int storage);
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
                       int cur, int slot, int storage, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,

@@ -464,7 +464,7 @@ __global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double 
 
 // ---------------------------------------------------------------- plain loop
 
-// Primal half-step for every pixel: needs q = M^T p here, at the left and
+// Primal half-step for every pixel: needs q = C^T p here, at the left and
 // at the upper neighbour (0 where the neighbour is outside the image).
 __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts kc, int cur) {
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -473,21 +473,24 @@ __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts k
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)i * fr.W + j;
     const float* p = P.p[cur];
-    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, j < fr.W - 1, i < fr.H - 1);
+    const Coef c =
+        make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, kc.sigma, j < fr.W - 1, i < fr.H - 1);
     const float qx = q_x(c, p[k], p[np + k], p[2 * np + k]);
     const float qy = q_y(c, p[k], p[np + k], p[2 * np + k]);
     float qxl = 0.0f, qyu = 0.0f;
     if (j > 0) {
         const size_t kl = k - 1;
-        const Coef cl = make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam, true, i < fr.H - 1);
+        const Coef cl =
+            make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam, kc.sigma, true, i < fr.H - 1);
         qxl = q_x(cl, p[kl], p[np + kl], p[2 * np + kl]);
     }
     if (i > 0) {
         const size_t ku = k - fr.W;
-        const Coef cu = make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam, j < fr.W - 1, true);
+        const Coef cu =
+            make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam, kc.sigma, j < fr.W - 1, true);
         qyu = q_y(cu, p[ku], p[np + ku], p[2 * np + ku]);
     }
-    P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, c, kc.tau, kc.umin, kc.umax);
+    P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, c, kc.ts, kc.umin, kc.umax);
 }
 
 // Dual half-step: needs the extrapolated primal here, right and below.
@@ -503,10 +506,11 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
     float gx = 0.0f, gy = 0.0f;
     if (j < fr.W - 1) gx = extrapolate(un[k + 1], uo[k + 1]) - ut;
     if (i < fr.H - 1) gy = extrapolate(un[k + fr.W], uo[k + fr.W]) - ut;
-    const Coef c = make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, j < fr.W - 1, i < fr.H - 1);
+    const Coef c =
+        make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, kc.sigma, j < fr.W - 1, i < fr.H - 1);
     const float* p = P.p[cur];
     float p1 = p[k], p2 = p[np + k], p3 = p[2 * np + k];
-    dual(p1, p2, p3, gx, gy, c, kc.sigma);
+    dual(p1, p2, p3, gx, gy, c);
     float* po = P.p[cur ^ 1];
     po[k] = p1;
     po[np + k] = p2;
@@ -516,103 +520,166 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
 // ---------------------------------------------------------------- fused loop
 
 // Folded events of the first launch, binned for one tile region (LDS).
+struct ScanState {
+    unsigned long long seg_bad[kMaxSegs];  // first event failing its own checks, per push
+    int seg_ok[kMaxSegs];                  // push accepted
+    int all_ok;                            // every push accepted
+    long long t_first;
+};
+
 struct TileBins {
-    int32_t* pos;     // RH x 64 counts
+    ScanState* ss;
+    int32_t* pos;     // RH x CW counts
     int32_t* neg;
-    long long* tmax;  // (RH + 1) x 65 latest timestamps (one extra column and row)
+    long long* tmax;  // (RH + 1) x (CW + 1) latest timestamps (one extra column and row)
     int64_t t_first;  // stream's first timestamp after this block's events
 };
 
-// Validates the folded pushes in order (each all-or-nothing, with the same
-// error codes as a scattered push) and bins the accepted events that fall
-// into the tile region [rx0, rx0 + 64] x [ry0, ry0 + RH].  Every workgroup
-// takes the same decisions; block 0 records the outcome as pending state.
-__device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int RH, int rx0,
-                           int ry0, bool lead, unsigned char* lds, TileBins& tb) {
-    __shared__ unsigned long long seg_bad[kMaxSegs];
-    __shared__ int seg_ok[kMaxSegs];
-    __shared__ long long s_first;
+// Binning of the folded pushes of a solve's first launch, for the tile
+// region [rx0, rx0 + CW] x [ry0, ry0 + RH], in two calls:
+//  bin_clear  lays out and zeroes the LDS bins;
+//  bin_scan   validates the pushes in order (each all-or-nothing, with the
+//             same error codes as a scattered push) and bins the accepted
+//             events.
+// The scan reads every event once: it bins each event while checking it and
+// only when a push turns out to be rejected (rare) clears the bins and bins
+// the accepted pushes again.  The caller issues its per-pixel loads between
+// the two calls, so their latency overlaps the event loads.  Every
+// workgroup takes the same decisions; the lead workgroup records the
+// outcome as pending state.
+__device__ void bin_clear(int RH, int CW, unsigned char* lds, TileBins& tb) {
+    __shared__ ScanState ss;
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < kMaxSegs) ss.seg_bad[tid] = (unsigned long long)kNoBad;
+    tb.ss = &ss;
     tb.pos = (int32_t*)lds;
-    tb.neg = tb.pos + RH * 64;
-    tb.tmax = (long long*)(tb.neg + RH * 64);
-    for (int q = tid; q < RH * 64; q += nt) {
+    tb.neg = tb.pos + RH * CW;
+    tb.tmax = (long long*)(tb.neg + RH * CW);
+    for (int q = tid; q < RH * CW; q += nt) {
         tb.pos[q] = 0;
         tb.neg[q] = 0;
     }
-    for (int q = tid; q < (RH + 1) * 65; q += nt) tb.tmax[q] = kNever;
-    if (tid < kMaxSegs) seg_bad[tid] = (unsigned long long)kNoBad;
+    for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
     __syncthreads();
-    // per-event checks; each push's first event is checked against the
-    // running reference time in sequence below
+}
+
+__device__ __forceinline__ void bin_one(const EventSegs& segs, int s, int64_t i, int RH, int CW,
+                                        int rx0, int ry0, TileBins& tb) {
+    const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
+    if (lc < 0 || lc > CW || lr < 0 || lr > RH) return;
+    atomicMax(&tb.tmax[lr * (CW + 1) + lc], (long long)segs.t[s][i]);
+    if (lc < CW && lr < RH)
+        atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * CW + lc] : &tb.neg[lr * CW + lc], 1);
+}
+
+__device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int RH, int CW,
+                         int rx0, int ry0, bool lead, TileBins& tb) {
+    ScanState& ss = *tb.ss;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    DevState* st = P.st;
+    // what the in-order decisions below need for the first push (nearly
+    // always the only one), loaded by thread 0 ahead of the event pass so
+    // that the loads overlap it
+    int32_t started = 0;
+    int64_t st_ref = 0, st_first = 0, st_events = 0, t0 = 0, tn = 0;
+    uint16_t x0 = 0, y0 = 0;
+    int8_t p0 = 0;
+    if (tid == 0) {
+        started = st->started;
+        st_ref = st->t_ref;
+        st_first = st->t_first;
+        st_events = st->batch_events;
+        if (segs.count > 0) {
+            t0 = segs.t[0][0];
+            tn = segs.t[0][segs.n[0] - 1];
+            x0 = segs.x[0][0];
+            y0 = segs.y[0][0];
+            p0 = segs.p[0][0];
+        }
+    }
+    // per-event checks (each push's first event is checked against the
+    // running reference time in sequence below), binning as we go
     for (int s = 0; s < segs.count; ++s) {
         const int64_t* t = segs.t[s];
         for (int64_t i = tid; i < segs.n[s]; i += nt) {
             const int64_t prev = i ? t[i - 1] : INT64_MIN;
             if (event_error(t[i], prev, segs.x[s][i], segs.y[s][i], segs.p[s][i], fr.W, fr.H))
-                atomicMin(&seg_bad[s], (unsigned long long)i);
+                atomicMin(&ss.seg_bad[s], (unsigned long long)i);
+            else
+                bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
         }
     }
     __syncthreads();
-    DevState* st = P.st;
     if (tid == 0) {
-        int64_t ref = st->started ? st->t_ref : INT64_MIN;
+        int64_t ref = started ? st_ref : INT64_MIN;
         int64_t first = kNever, last = 0, accepted = 0;
         int32_t err = 0;
+        int ok_all = 1;
         for (int s = 0; s < segs.count; ++s) {
-            const int64_t fb = (int64_t)seg_bad[s];
             const int64_t* t = segs.t[s];
+            const int64_t ts0 = s == 0 ? t0 : t[0];
+            const int64_t fb = (int64_t)ss.seg_bad[s];
             int32_t code = 0;
             if (fb == 0)
-                code = event_error(t[0], INT64_MIN, segs.x[s][0], segs.y[s][0], segs.p[s][0],
-                                   fr.W, fr.H);
-            else if (t[0] < ref)
+                code = s == 0 ? event_error(t0, INT64_MIN, x0, y0, p0, fr.W, fr.H)
+                              : event_error(t[0], INT64_MIN, segs.x[s][0], segs.y[s][0],
+                                            segs.p[s][0], fr.W, fr.H);
+            else if (ts0 < ref)
                 code = kErrOrder;
             else if (fb != kNoBad)
-                code = event_error(t[fb], t[fb - 1], segs.x[s][fb], segs.y[s][fb], segs.p[s][fb],
-                                   fr.W, fr.H);
-            seg_ok[s] = code == 0;
+                code = event_error(segs.t[s][fb], segs.t[s][fb - 1], segs.x[s][fb],
+                                   segs.y[s][fb], segs.p[s][fb], fr.W, fr.H);
+            ss.seg_ok[s] = code == 0;
             if (code == 0) {
-                if (first == kNever) first = t[0];
-                ref = t[segs.n[s] - 1];
+                if (first == kNever) first = ts0;
+                ref = s == 0 ? tn : t[segs.n[s] - 1];
                 last = ref;
                 accepted += segs.n[s];
-            } else if (err == 0) {
-                err = code;
+            } else {
+                ok_all = 0;
+                if (err == 0) err = code;
             }
         }
-        s_first = st->started ? st->t_first : (first == kNever ? 0 : first);
+        ss.all_ok = ok_all;
+        ss.t_first = started ? st_first : (first == kNever ? 0 : first);
         if (lead) {
             st->pend_t_ref = last;
             st->pend_t_first = first;
             st->pend_accepted = accepted > 0;
-            st->pend_events = st->batch_events + accepted;
+            st->pend_events = st_events + accepted;
             st->pend_err = err;
         }
     }
     __syncthreads();
-    for (int s = 0; s < segs.count; ++s) {
-        if (!seg_ok[s]) continue;
-        for (int64_t i = tid; i < segs.n[s]; i += nt) {
-            const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
-            if (lc < 0 || lc > 64 || lr < 0 || lr > RH) continue;
-            atomicMax(&tb.tmax[lr * 65 + lc], (long long)segs.t[s][i]);
-            if (lc < 64 && lr < RH)
-                atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * 64 + lc] : &tb.neg[lr * 64 + lc], 1);
+    if (!ss.all_ok) {
+        // a rejected push: bin the accepted pushes again from clear bins
+        for (int q = tid; q < RH * CW; q += nt) {
+            tb.pos[q] = 0;
+            tb.neg[q] = 0;
         }
+        for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
+        __syncthreads();
+        for (int s = 0; s < segs.count; ++s) {
+            if (!ss.seg_ok[s]) continue;
+            for (int64_t i = tid; i < segs.n[s]; i += nt) bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    tb.t_first = s_first;
+    tb.t_first = ss.t_first;
 }
 
 // K primal-dual iterations per launch on a register tile.  A workgroup of
-// NW wavefronts covers a 64-column x (NW*R)-row region: lane = column, each
-// lane holds R consecutive rows in registers, wavefront w holds rows
-// [w*R, w*R + R).  Horizontal neighbours come from adjacent lanes (DPP),
-// vertical ones from the lane's own registers or, across wavefronts,
-// through LDS.  Each iteration widens the dependency cone by one pixel, so
-// after K iterations the region minus a K-pixel border is exact; only that
-// interior is written.  Reads (u, p) from buffer `cur`, writes `cur ^ 1`.
+// NW wavefronts forms NV = NW * 64 / CW lane rows of CW lanes (CW = 64 or
+// 32) and covers a CW-column x (NV*R)-row region: lane = column within its
+// lane row, each lane holds R consecutive rows in registers, lane row v
+// holds rows [v*R, v*R + R).  Horizontal neighbours come from adjacent
+// lanes (DPP), vertical ones from the lane's own registers or, across lane
+// rows, through LDS.  Each iteration widens the dependency cone by one
+// pixel, so after K iterations the region minus a K-pixel border is exact;
+// only that interior is written.  Reads (u, p) from buffer `cur`, writes
+// `cur ^ 1`.  (32-column tiles halve the pixels per workgroup of a tile
+// of the same height: small frames, whose time goes into the latency of
+// each iteration on one compute unit, run faster on them.)
 //
 // mode & kBuild (the solve's first launch): instead of loading f, tx, ty, the
 //   tile forms them from u (still u_prev), the event counts and the latest
@@ -625,20 +692,23 @@ __device__ void bin_events(const Planes& P, Frame fr, const EventSegs& segs, int
 //
 // The tile geometry uses a halo of KG >= K pixels (the batched launch keeps
 // one geometry for all launches of a solve); tile (txi, tyi) covers the
-// region whose interior starts at (txi, tyi) * (64 - 2 KG, NW R - 2 KG).
+// region whose interior starts at (txi, tyi) * (CW - 2 KG, NV R - 2 KG).
 // `lead`: this tile does the per-stream duties (commit, pending state).
-template <int R, int NW, class S>
+template <int R, int NW, int CW, class S>
 __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterConsts& kc,
                                         const BuildConsts& bc, const EventSegs& segs, int cur,
                                         int K, int KG, int mode, int txi, int tyi, bool lead,
                                         unsigned char* dyn_lds) {
-    constexpr int RH = NW * R;
-    const int lane = threadIdx.x & 63;
+    static_assert(CW == 64 || CW == 32, "lane rows of 64 or 32 lanes");
+    constexpr int NV = NW * (64 / CW);  // lane rows
+    constexpr int RH = NV * R;
+    const int col = threadIdx.x & (CW - 1);
+    const int v = threadIdx.x / CW;
     const int wave = threadIdx.x >> 6;
-    const int OW = 64 - 2 * KG, OH = RH - 2 * KG;
+    const int OW = CW - 2 * KG, OH = RH - 2 * KG;
     const int rx0 = txi * OW - KG, ry0 = tyi * OH - KG;
-    const int gx = rx0 + lane;
-    const int gy0 = ry0 + wave * R;
+    const int gx = rx0 + col;
+    const int gy0 = ry0 + v * R;
     const size_t np = (size_t)fr.W * fr.H;
     const float* __restrict__ uin = P.u[cur];
     const typename S::T* __restrict__ pin = (const typename S::T*)P.p[cur];
@@ -648,28 +718,29 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     if ((mode & kCommit) && lead && threadIdx.x == 0) commit_pending(P.st);
 
     const bool build = (mode & kBuild) != 0;
+    const bool events = build && (mode & kEvents) != 0;
     TileBins tb;
+    tb.ss = nullptr;
     tb.pos = tb.neg = nullptr;
     tb.tmax = nullptr;
     tb.t_first = 0;
-    if (build) {
-        if (mode & kEvents) {
-            bin_events(P, fr, segs, RH, rx0, ry0, lead, dyn_lds, tb);
-        } else {
-            tb.t_first = P.st->t_first;
-            if (lead && threadIdx.x == 0) {
-                DevState* st = P.st;
-                st->pend_accepted = 0;
-                st->pend_err = 0;
-                st->pend_events = st->batch_events;
-            }
+    if (events) {
+        bin_clear(RH, CW, dyn_lds, tb);
+        bin_scan(P, fr, segs, RH, CW, rx0, ry0, lead, tb);
+    } else if (build) {
+        tb.t_first = P.st->t_first;
+        if (lead && threadIdx.x == 0) {
+            DevState* st = P.st;
+            st->pend_accepted = 0;
+            st->pend_err = 0;
+            st->pend_events = st->batch_events;
         }
     }
 
     float u[R], p1[R], p2[R], p3[R];
     Coef c[R];
     const bool col_in = gx >= 0 && gx < fr.W;
-    const bool col_out = col_in && lane >= KG && lane < 64 - KG;
+    const bool col_out = col_in && col >= KG && col < CW - KG;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
@@ -682,7 +753,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
             b = S::ld(pin, np + k);
             d = S::ld(pin, 2 * np + k);
             if (build) {
-                const int lr = wave * R + r;
+                const int lr = v * R + r;
                 const bool hr = gx < fr.W - 1, hd = gy < fr.H - 1;
                 int32_t npos = 0, nneg = 0;
                 int64_t tl = P.t_last[k];
@@ -692,12 +763,12 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
                     npos = P.npos[k];
                     nneg = P.nneg[k];
                 }
-                if (mode & kEvents) {
-                    npos += tb.pos[lr * 64 + lane];
-                    nneg += tb.neg[lr * 64 + lane];
-                    tl = max(tl, (int64_t)tb.tmax[lr * 65 + lane]);
-                    tr = max(tr, (int64_t)tb.tmax[lr * 65 + lane + 1]);
-                    td = max(td, (int64_t)tb.tmax[(lr + 1) * 65 + lane]);
+                if (events) {
+                    npos += tb.pos[lr * CW + col];
+                    nneg += tb.neg[lr * CW + col];
+                    tl = max(tl, (int64_t)tb.tmax[lr * (CW + 1) + col]);
+                    tr = max(tr, (int64_t)tb.tmax[lr * (CW + 1) + col + 1]);
+                    td = max(td, (int64_t)tb.tmax[(lr + 1) * (CW + 1) + col]);
                 }
                 f = data_image(uu, npos, nneg, bc.dpos, bc.dneg);
                 if (mode & kTimeMem) {
@@ -714,7 +785,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
                         S::st(txs, k, tx);
                         S::st(tys, k, ty);
                     }
-                    if (mode & kEvents) P.t_last[k] = tl;
+                    if (events) P.t_last[k] = tl;
                 }
             } else {
                 f = P.f[k];
@@ -726,19 +797,20 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         p1[r] = a;
         p2[r] = b;
         p3[r] = d;
-        // pixels outside the image get all-zero M, so their q is 0
-        c[r] = make_coef(tx, ty, f, kc.taulam, in && gx < fr.W - 1, in && gy < fr.H - 1);
+        // pixels outside the image get all-zero coefficients, so their q is 0
+        c[r] = make_coef(tx, ty, f, kc.taulam, kc.sigma, in && gx < fr.W - 1,
+                         in && gy < fr.H - 1);
     }
 
-    // Rows that cross wavefronts go through LDS.  xq[w + 1] holds wavefront
-    // w's last q_y row and xu[w] its first extrapolated row; xq[0] and
-    // xu[NW] stay zero (nothing above the first / below the last wavefront),
-    // so every wavefront reads its neighbour row unconditionally.
-    __shared__ float xq[NW + 1][64];
-    __shared__ float xu[NW + 1][64];
-    if constexpr (NW > 1) {
-        if (wave == 0) xq[0][lane] = 0.0f;
-        if (wave == NW - 1) xu[NW][lane] = 0.0f;
+    // Rows that cross lane rows go through LDS.  xq[v + 1] holds lane row
+    // v's last q_y row and xu[v] its first extrapolated row; xq[0] and
+    // xu[NV] stay zero (nothing above the first / below the last lane row),
+    // so every lane row reads its neighbour row unconditionally.
+    __shared__ float xq[NV + 1][CW];
+    __shared__ float xu[NV + 1][CW];
+    if constexpr (NV > 1) {
+        if (v == 0) xq[0][col] = 0.0f;
+        if (v == NV - 1) xu[NV][col] = 0.0f;
     }
 
     // With few rows per lane the loop runs two iterations per trip, so that
@@ -749,9 +821,9 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     constexpr bool kSkip = R <= 2 && NW > 1;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     auto step = [&](int it1) {
-        if (!kSkip || tile_rows_active<R, NW>(wv, it1))
-            tile_iteration<R, NW>(u, p1, p2, p3, c, kc.tau, kc.sigma, kc.umin, kc.umax, lane,
-                                  wave, xq, xu);
+        if (!kSkip || tile_rows_active<R * (64 / CW), NW>(wv, it1))
+            tile_iteration<R, NV, CW>(u, p1, p2, p3, c, kc.ts, kc.umin, kc.umax, col, v, xq,
+                                      xu);
         else
             tile_skip<NW>();
     };
@@ -768,7 +840,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int row = wave * R + r;
+        const int row = v * R + r;
         const int gy = gy0 + r;
         if (col_out && row >= KG && row < RH - KG && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
@@ -784,14 +856,14 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     }
 }
 
-template <int R, int NW, class S>
+template <int R, int NW, int CW, class S>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
                                                       BuildConsts bc, EventSegs segs, int cur,
                                                       int K, int mode, int tiles_x, int ntiles) {
     extern __shared__ unsigned char dyn_lds[];
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    pd_tile<R, NW, S>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
+    pd_tile<R, NW, CW, S>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
 }
 
 // One launch over the tiles of many streams (a work list of (stream, tile)
@@ -809,8 +881,8 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __
     const StreamDesc& d = descs[w.x];
     const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
     const int mode = launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0);
-    pd_tile<R, NW, S>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode, txi, tyi,
-                      w.y == 0, dyn_lds);
+    pd_tile<R, NW, 64, S>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode, txi,
+                          tyi, w.y == 0, dyn_lds);
 }
 
 // After a one-launch batched solve: commit and reset counts of every stream.
@@ -930,17 +1002,18 @@ __global__ __launch_bounds__(256) void k_gap_final(Planes P, size_t nblocks, int
     }
 }
 
-template <int R, int NW, class S>
+template <int R, int NW, int CW, class S>
 hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
                         const EventSegs& segs, int cur, int K, int mode, hipStream_t s,
                         LaunchEv ev) {
-    const int OW = 64 - 2 * K, OH = NW * R - 2 * K;
+    const int OW = CW - 2 * K, OH = NW * (64 / CW) * R - 2 * K;
     if (K < 1 || OW <= 0 || OH <= 0) return hipErrorInvalidValue;
     const int tiles_x = (fr.W + OW - 1) / OW;
     const int tiles_y = (fr.H + OH - 1) / OH;
     const int ntiles = tiles_x * tiles_y;
-    return launch(k_pd_fused<R, NW, S>, dim3(ntiles), dim3(64 * NW), fused_lds_bytes(R, NW, mode), s,
-                  ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
+    return launch(k_pd_fused<R, NW, CW, S>, dim3(ntiles), dim3(64 * NW),
+                  fused_lds_bytes(R, NW, CW, mode), s, ev.start, ev.stop, P, fr, kc, bc, segs, cur,
+                  K, mode, tiles_x, ntiles);
 }
 
 template <int R, int NW, class S>
@@ -948,22 +1021,22 @@ hipError_t batch_launch(const StreamDesc* descs, const int2* work, int nwork, in
                         int launch_idx, bool bins, hipStream_t s, LaunchEv ev) {
     if (K < 1 || K > KG || 64 - 2 * KG <= 0 || NW * R - 2 * KG <= 0) return hipErrorInvalidValue;
     return launch(k_pd_fused_batch<R, NW, S>, dim3(nwork), dim3(64 * NW),
-                  fused_lds_bytes(R, NW, bins ? kEvents : 0), s, ev.start, ev.stop, descs, work,
-                  nwork, K, KG, launch_idx);
+                  fused_lds_bytes(R, NW, 64, bins ? kEvents : 0), s, ev.start, ev.stop, descs,
+                  work, nwork, K, KG, launch_idx);
 }
 
 }  // namespace
 
 size_t gap_blocks(size_t np) { return (np + kGapBlock - 1) / kGapBlock; }
 
-size_t fused_lds_bytes(int rows, int waves, int mode) {
+size_t fused_lds_bytes(int rows, int waves, int cols, int mode) {
     if (!(mode & kEvents)) return 0;
-    const size_t RH = (size_t)rows * waves;
-    return 2 * RH * 64 * sizeof(int32_t) + (RH + 1) * 65 * sizeof(long long);
+    const size_t RH = (size_t)rows * waves * (64 / cols), CW = cols;
+    return 2 * RH * CW * sizeof(int32_t) + (RH + 1) * (CW + 1) * sizeof(long long);
 }
 
-int fused_tiles(Frame fr, int rows, int waves, int iters) {
-    const int OW = 64 - 2 * iters, OH = rows * waves - 2 * iters;
+int fused_tiles(Frame fr, int rows, int waves, int cols, int iters) {
+    const int OW = cols - 2 * iters, OH = rows * waves * (64 / cols) - 2 * iters;
     if (OW <= 0 || OH <= 0) return -1;
     return ((fr.W + OW - 1) / OW) * ((fr.H + OH - 1) / OH);
 }
@@ -1049,8 +1122,18 @@ hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hi
     return e;
 }
 
-bool fused_shape_supported(int rows, int waves, int storage) {
+bool fused_shape_supported(int rows, int waves, int cols, int storage) {
     const int key = rows * 100 + waves;
+    if (cols == 32) {
+        if (storage != kStoreF32) return key == 208;
+        switch (key) {
+            case 108: case 116: case 204: case 208: case 216: case 308: case 404: case 408:
+                return true;
+            default:
+                return false;
+        }
+    }
+    if (cols != 64) return false;
     if (storage != kStoreF32)
         return key == 216 || key == 416 || key == 804 || key == 808 || key == 408;
     switch (key) {
@@ -1064,48 +1147,61 @@ bool fused_shape_supported(int rows, int waves, int storage) {
     }
 }
 
-#define REC_FUSED_CASE(R, NW) \
-    case R * 100 + NW: return fused_launch<R, NW, StoreF32>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
-#define REC_FUSED_CASE16(R, NW)                                                                   \
-    case R * 100 + NW:                                                                           \
-        return storage == kStoreF16                                                              \
-                   ? fused_launch<R, NW, StoreF16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev)  \
-                   : fused_launch<R, NW, StoreBF16>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+#define REC_FUSED_CASE(R, NW, CW)                                                               \
+    case (CW == 32 ? 10000 : 0) + R * 100 + NW:                                                \
+        return fused_launch<R, NW, CW, StoreF32>(P, fr, kc, bc, segs, cur, iters, mode, s, ev);
+#define REC_FUSED_CASE16(R, NW, CW)                                                             \
+    case (CW == 32 ? 10000 : 0) + R * 100 + NW:                                                \
+        return storage == kStoreF16                                                             \
+                   ? fused_launch<R, NW, CW, StoreF16>(P, fr, kc, bc, segs, cur, iters, mode, s, \
+                                                       ev)                                      \
+                   : fused_launch<R, NW, CW, StoreBF16>(P, fr, kc, bc, segs, cur, iters, mode,  \
+                                                        s, ev);
 
 hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc,
                            const EventSegs& segs, int cur, int iters, int mode, int rows,
-                           int waves, int storage, hipStream_t s, LaunchEv ev) {
-    if (!fused_shape_supported(rows, waves, storage)) return hipErrorInvalidValue;
+                           int waves, int cols, int storage, hipStream_t s, LaunchEv ev) {
+    if (!fused_shape_supported(rows, waves, cols, storage)) return hipErrorInvalidValue;
+    const int key = (cols == 32 ? 10000 : 0) + rows * 100 + waves;
     if (storage != kStoreF32) {
-        switch (rows * 100 + waves) {
-            REC_FUSED_CASE16(2, 16)
-            REC_FUSED_CASE16(4, 16)
-            REC_FUSED_CASE16(4, 8)
-            REC_FUSED_CASE16(8, 4)
-            REC_FUSED_CASE16(8, 8)
+        switch (key) {
+            REC_FUSED_CASE16(2, 16, 64)
+            REC_FUSED_CASE16(4, 16, 64)
+            REC_FUSED_CASE16(4, 8, 64)
+            REC_FUSED_CASE16(8, 4, 64)
+            REC_FUSED_CASE16(8, 8, 64)
+            REC_FUSED_CASE16(2, 8, 32)
             default: return hipErrorInvalidValue;
         }
     }
-    switch (rows * 100 + waves) {
-        REC_FUSED_CASE(2, 2)
-        REC_FUSED_CASE(2, 4)
-        REC_FUSED_CASE(2, 8)
-        REC_FUSED_CASE(2, 16)
-        REC_FUSED_CASE(3, 16)
-        REC_FUSED_CASE(4, 1)
-        REC_FUSED_CASE(4, 2)
-        REC_FUSED_CASE(4, 4)
-        REC_FUSED_CASE(4, 8)
-        REC_FUSED_CASE(4, 16)
-        REC_FUSED_CASE(5, 8)
-        REC_FUSED_CASE(6, 8)
-        REC_FUSED_CASE(8, 1)
-        REC_FUSED_CASE(8, 2)
-        REC_FUSED_CASE(8, 4)
-        REC_FUSED_CASE(8, 8)
-        REC_FUSED_CASE(16, 1)
-        REC_FUSED_CASE(16, 2)
-        REC_FUSED_CASE(16, 4)
+    switch (key) {
+        REC_FUSED_CASE(2, 2, 64)
+        REC_FUSED_CASE(2, 4, 64)
+        REC_FUSED_CASE(2, 8, 64)
+        REC_FUSED_CASE(2, 16, 64)
+        REC_FUSED_CASE(3, 16, 64)
+        REC_FUSED_CASE(4, 1, 64)
+        REC_FUSED_CASE(4, 2, 64)
+        REC_FUSED_CASE(4, 4, 64)
+        REC_FUSED_CASE(4, 8, 64)
+        REC_FUSED_CASE(4, 16, 64)
+        REC_FUSED_CASE(5, 8, 64)
+        REC_FUSED_CASE(6, 8, 64)
+        REC_FUSED_CASE(8, 1, 64)
+        REC_FUSED_CASE(8, 2, 64)
+        REC_FUSED_CASE(8, 4, 64)
+        REC_FUSED_CASE(8, 8, 64)
+        REC_FUSED_CASE(16, 1, 64)
+        REC_FUSED_CASE(16, 2, 64)
+        REC_FUSED_CASE(16, 4, 64)
+        REC_FUSED_CASE(1, 8, 32)
+        REC_FUSED_CASE(1, 16, 32)
+        REC_FUSED_CASE(2, 4, 32)
+        REC_FUSED_CASE(2, 8, 32)
+        REC_FUSED_CASE(2, 16, 32)
+        REC_FUSED_CASE(3, 8, 32)
+        REC_FUSED_CASE(4, 4, 32)
+        REC_FUSED_CASE(4, 8, 32)
         default: return hipErrorInvalidValue;
     }
 }
@@ -1123,7 +1219,7 @@ hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
                            int li, bool bins, int rows, int waves, int storage, hipStream_t s,
                            LaunchEv ev) {
-    if (!fused_shape_supported(rows, waves, storage) || nwork <= 0) return hipErrorInvalidValue;
+    if (!batch_shape_supported(rows, waves, storage) || nwork <= 0) return hipErrorInvalidValue;
     if (storage != kStoreF32) {
         switch (rows * 100 + waves) {
             REC_BATCH_CASE16(2, 16)

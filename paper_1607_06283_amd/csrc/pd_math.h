@@ -11,7 +11,11 @@
 //   G           1 + tx^2 + ty^2 = det g;  s = sqrt(G)
 //   M           3x2 matrix of eqn. (3), L_g u = M (L_x u, L_y u):
 //               M = (1/G) [[1+ty^2, -tx ty], [-tx ty, 1+tx^2], [tx, ty]]
-//   q           M^T p; the adjoint is L_g^* p = -div q
+//   C           sigma M: the stored coefficients carry the dual step size,
+//               so the dual ascent p + sigma M grad is two fused multiply-adds
+//               per component
+//   q           C^T p = sigma M^T p; the adjoint is L_g^* p = -div(M^T p), so
+//               the primal step u - tau L_g^* p is u + (tau / sigma) div q
 //   beta        tau * lambda * s            (KL prox, eqn. update_rules)
 //   c4          4 beta f
 //
@@ -31,8 +35,8 @@
 namespace rec {
 
 struct Coef {
-    float a11, a21, a31;   // first column of M (multiplies L_x), 0 if masked
-    float b12, b22, b32;   // second column of M (multiplies L_y), 0 if masked
+    float a11, a21, a31;   // first column of sigma M (multiplies L_x), 0 if masked
+    float b12, b22, b32;   // second column of sigma M (multiplies L_y), 0 if masked
     float s;               // sqrt(G): dual ball radius
     float beta, c4;        // KL prox constants
 };
@@ -51,16 +55,17 @@ __device__ __forceinline__ float data_image(float u_prev, int npos, int nneg, do
 }
 
 // Metric-dependent constants of one pixel (computed once per block of
-// iterations; they depend on the block's tau and f only).  has_x: the pixel
-// has a right neighbour inside the image (so L_x is a real difference);
-// has_y: it has a lower neighbour.
-__device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float taulam, bool has_x,
-                                          bool has_y) {
+// iterations; they depend on the block's tau and f only).  sigma: the dual
+// step size folded into the coefficients.  has_x: the pixel has a right
+// neighbour inside the image (so L_x is a real difference); has_y: it has a
+// lower neighbour.
+__device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float taulam, float sigma,
+                                          bool has_x, bool has_y) {
     Coef c;
     const float ax = __builtin_fmaf(tx, tx, 1.0f);  // 1 + tx^2
     const float ay = __builtin_fmaf(ty, ty, 1.0f);  // 1 + ty^2
     const float G = __builtin_fmaf(tx, tx, ay);     // 1 + tx^2 + ty^2
-    const float iG = rcp(G);
+    const float iG = sigma * rcp(G);
     const float m12 = -(tx * ty) * iG;
     const float m11 = ay * iG, m22 = ax * iG;
     const float m31 = tx * iG, m32 = ty * iG;
@@ -76,7 +81,8 @@ __device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float tau
     return c;
 }
 
-// q = M^T p at one pixel (zero components where the column is masked).
+// q = C^T p = sigma M^T p at one pixel (zero components where the column is
+// masked).
 __device__ __forceinline__ float q_x(const Coef& c, float p1, float p2, float p3) {
     return __builtin_fmaf(c.a31, p3, __builtin_fmaf(c.a21, p2, c.a11 * p1));
 }
@@ -85,28 +91,31 @@ __device__ __forceinline__ float q_y(const Coef& c, float p1, float p2, float p3
 }
 
 // Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel, with
+// ubar = u + ts div q, ts = tau / sigma, and
 // div q = (q_x - q_x(left)) + (q_y - q_y(up)) (backward differences; the
 // neighbour values are 0 outside the image).  The KL prox uses the
 // cancellation-free form of the closed-form root: a = ubar - beta,
-// r = sqrt(a^2 + 4 beta f):  a >= 0: (a + r) / 2,  a < 0: 2 beta f / (r - a);
-// then clamp to [umin, umax].
+// r = sqrt(a^2 + 4 beta f), d = r + |a|:  a >= 0: d / 2,  a < 0: 2 beta f / d
+// (d is r + a in the first case and r - a in the second, so neither branch
+// subtracts nearly equal numbers); then clamp to [umin, umax].
 // prox_root returns the unclamped root and r (the reverse sweep of the
 // unrolled loop needs both); primal clamps it.
 __device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
-                                           const Coef& c, float tau, float& r) {
+                                           const Coef& c, float ts, float& r) {
     const float div = (qx - qx_left) + (qy - qy_up);
-    const float ubar = __builtin_fmaf(tau, div, u);
+    const float ubar = __builtin_fmaf(ts, div, u);
     const float a = ubar - c.beta;
     r = sqrt_(__builtin_fmaf(a, a, c.c4));
-    const float pos = 0.5f * (a + r);
-    const float neg = (0.5f * c.c4) * rcp(r - a);
+    const float d = r + __builtin_fabsf(a);
+    const float pos = 0.5f * d;
+    const float neg = (0.5f * c.c4) * rcp(d);
     return a >= 0.0f ? pos : neg;
 }
 
 __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
-                                        const Coef& c, float tau, float umin, float umax) {
+                                        const Coef& c, float ts, float umin, float umax) {
     float r;
-    const float un = prox_root(u, qx, qy, qx_left, qy_up, c, tau, r);
+    const float un = prox_root(u, qx, qy, qx_left, qy_up, c, ts, r);
     return __builtin_amdgcn_fmed3f(un, umin, umax);  // clamp (umin <= umax, un not NaN)
 }
 
@@ -115,19 +124,23 @@ __device__ __forceinline__ float extrapolate(float un, float u) {
     return __builtin_fmaf(2.0f, un, -u);
 }
 
-// Dual step p_{k+1} = prox_{sigma R^*}(p_k + sigma M (gx, gy)) at one pixel,
-// with (gx, gy) the forward differences of the extrapolated primal (any
-// finite value where the column of M is masked); the prox is the projection
+// Dual ascent pbar = p + sigma M (gx, gy) = p + C (gx, gy) at one pixel, with
+// (gx, gy) the forward differences of the extrapolated primal (any finite
+// value where the column of C is masked).
+__device__ __forceinline__ void dual_ascent(const Coef& c, float gx, float gy, float p1, float p2,
+                                            float p3, float& b1, float& b2, float& b3) {
+    b1 = __builtin_fmaf(c.a11, gx, __builtin_fmaf(c.b12, gy, p1));
+    b2 = __builtin_fmaf(c.a21, gx, __builtin_fmaf(c.b22, gy, p2));
+    b3 = __builtin_fmaf(c.a31, gx, __builtin_fmaf(c.b32, gy, p3));
+}
+
+// Dual step p_{k+1} = prox_{sigma R^*}(pbar) at one pixel: the projection
 // onto the ball of radius s, p / max(1, |p| / s), computed as
 // p * min(1, s / |p|).
 __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
-                                     const Coef& c, float sigma) {
-    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
-    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
-    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
-    const float b1 = __builtin_fmaf(sigma, v1, p1);
-    const float b2 = __builtin_fmaf(sigma, v2, p2);
-    const float b3 = __builtin_fmaf(sigma, v3, p3);
+                                     const Coef& c) {
+    float b1, b2, b3;
+    dual_ascent(c, gx, gy, p1, p2, p3, b1, b2, b3);
     const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
     const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
     p1 = b1 * sc;

@@ -90,7 +90,7 @@ struct rec_ctx {
     hipStream_t stream;
     int device;
     int cur;                 // which ping-pong buffers hold the current (u, p)
-    int rows, waves;         // fused tile shape
+    int rows, waves, cols;   // fused tile shape
     int kmax;                // iterations per fused launch (at most)
     // host staging for host-pointer pushes
     char* pinned;
@@ -200,33 +200,62 @@ int flush_deferred(rec_ctx* c) {
     return REC_OK;
 }
 
-// Fused tile shape (rows per lane, wavefronts per workgroup) and iterations
-// per launch.  Measured on MI355X: small frames are limited by launch
-// latency, so they take thin tiles (many workgroups) and long launches;
-// large frames are limited by HBM and VALU, so they take taller tiles and
-// short launches (less halo recomputation).
-void choose_shape(const rec_params* prm, int64_t np, int* rows, int* waves, int* kiters) {
-    int r = prm->tile_rows, w = prm->tile_waves, k;
-    if (np <= 250000) {
-        if (!r) { r = 2; w = 16; }
-        k = 13;
-    } else {
-        // 6 iterations per launch on 6 rows x 8 wavefronts (FP32; 16-bit
-        // storage has no 6-row variant and takes 4 rows): 1280x720 268 G
-        // pixel-iterations/s, 5120x5760 396 G; 4 x 8 tiles 239-252 and
-        // 387-391 G, 8 x 4 tiles 209 and 329 G, 4 x 16 tiles 219-255 and
-        // 277-303 G
-        if (!r) {
-            r = prm->storage == rec::kStoreF32 ? 6 : 4;
-            w = 8;
+// Fused tile shape (rows per lane, wavefronts per workgroup, columns) and
+// iterations per launch.  Small and mid-size frames are limited by the
+// latency of each iteration on a compute unit and by the fixed cost of each
+// launch, large frames by VALU issue and HBM.  Measured on MI355X, 50
+// iterations per block, pixel-iterations/s (shape = rows x waves x columns,
+// K = iterations per launch):
+//   64x64 and 128x128: 1x16x32 K 10: 5.4 and 21.4 G (2x16x64 K 13: 4.5, 17.9)
+//   240x180:           1x16x32 K 9: 49 G (2x16x64 K 13: 45 G)
+//   320x240, 346x260:  2x8x32 K 8: 69, 69 G (best of 18 shapes 74, 74 G;
+//                      2x16x64 K 13: 54, 51 G)
+//   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
+//   800x600:           2x8x32 K 8: 153 G (best 154 G)
+//   1280x720, 5120x5760: 6x8x64 K 6 (FP32): 279-292 G, 399-411 G; with
+//                      16-bit storage 4x8x64 K 6
+// `narrow` allows 32-column tiles (the batched launch has 64 only; it
+// takes 2x16 K 13 up to 250k pixels and the large-frame shape beyond).
+void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int* waves,
+                  int* cols, int* kiters) {
+    int r = prm->tile_rows, w = prm->tile_waves, cw = prm->tile_cols ? prm->tile_cols : 64, k;
+    const bool f32 = prm->storage == rec::kStoreF32;
+    int ar, aw, acw;  // automatic shape
+    if (!narrow) {
+        if (np <= 250000) {
+            ar = 2, aw = 16, acw = 64, k = 13;
+        } else {
+            ar = f32 ? 6 : 4, aw = 8, acw = 64, k = 6;
         }
-        k = 6;
+    } else if (np <= 24000) {
+        ar = 1, aw = 16, acw = 32, k = 10;
+    } else if (np <= 60000) {
+        ar = 1, aw = 16, acw = 32, k = 9;
+    } else if (np <= 120000) {
+        ar = 2, aw = 8, acw = 32, k = 8;
+    } else if (np <= 400000) {
+        ar = 4, aw = 16, acw = 64, k = 13;
+    } else if (np <= 600000) {
+        ar = 2, aw = 8, acw = 32, k = 8;
+    } else {
+        ar = f32 ? 6 : 4, aw = 8, acw = 64, k = 6;
+    }
+    if (!rec::fused_shape_supported(ar, aw, acw, prm->storage)) {
+        // 16-bit storage has 2x8 as its only 32-column tile
+        ar = 2, aw = 8, acw = 32;
+    }
+    if (!r) {
+        r = ar;
+        w = aw;
+        cw = acw;
     }
     if (prm->fuse_iters > 0) k = prm->fuse_iters;
-    const int kmax = (r * w - 1) / 2 < 31 ? (r * w - 1) / 2 : 31;
+    const int rh = r * w * (64 / cw);
+    const int kmax = (rh - 1) / 2 < (cw - 1) / 2 ? (rh - 1) / 2 : (cw - 1) / 2;
     if (k > kmax) k = kmax;
     *rows = r;
     *waves = w;
+    *cols = cw;
     *kiters = k;
 }
 
@@ -281,10 +310,14 @@ int rec_check_params(const rec_params* prm) {
     if (prm->tvl1_iters < 0 || prm->tvl1_iters > 10000) return REC_EINVAL;
     if (prm->tvl1_iters > 0 && !finite_pos(prm->tvl1_lambda)) return REC_EINVAL;
     if ((prm->tile_rows == 0) != (prm->tile_waves == 0)) return REC_EINVAL;
-    if (prm->tile_rows &&
-        !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves, prm->storage))
+    if (prm->tile_cols != 0 && (prm->tile_rows == 0 || (prm->tile_cols != 64 &&
+                                                        prm->tile_cols != 32)))
         return REC_EINVAL;
-    for (int i = 0; i < 4; ++i)
+    if (prm->tile_rows &&
+        !rec::fused_shape_supported(prm->tile_rows, prm->tile_waves,
+                                    prm->tile_cols ? prm->tile_cols : 64, prm->storage))
+        return REC_EINVAL;
+    for (int i = 0; i < 3; ++i)
         if (prm->reserved[i] != 0) return REC_EINVAL;
     return REC_OK;
 }
@@ -329,14 +362,15 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     c->prm = *prm;
     carve(prm, (char*)dev_workspace, &c->P);
     c->fr = {prm->width, prm->height};
-    c->kc.tau = (float)prm->tau;
+    c->kc.ts = (float)(prm->tau / prm->sigma);
     c->kc.sigma = (float)prm->sigma;
     c->kc.taulam = (float)(prm->tau * prm->lambda);
     c->kc.umin = (float)prm->u_min;
     c->kc.umax = (float)prm->u_max;
     c->stream = (hipStream_t)hip_stream;
     c->cur = 0;
-    choose_shape(prm, (int64_t)prm->width * prm->height, &c->rows, &c->waves, &c->kmax);
+    choose_shape(prm, (int64_t)prm->width * prm->height, true, &c->rows, &c->waves, &c->cols,
+                 &c->kmax);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return REC_EDEVICE;
@@ -453,7 +487,7 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
     bool fold = false;
     if (fused && !denoise && !c->deferred.empty()) {
         const int first_k = iters < c->kmax ? iters : c->kmax;
-        const int64_t tiles = rec::fused_tiles(c->fr, c->rows, c->waves, first_k);
+        const int64_t tiles = rec::fused_tiles(c->fr, c->rows, c->waves, c->cols, first_k);
         fold = c->deferred_events <= kFoldMaxEvents && tiles > 0 &&
                c->deferred_events * tiles <= kFoldMaxWork;
     }
@@ -516,7 +550,8 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
                     mode = rec::kCommit | (counts ? rec::kZero : 0);
                 rc = timed(c, 2, np * m, [&](rec::LaunchEv ev) {
                     return rec::launch_pd_fused(c->P, c->fr, c->kc, bc, segs, c->cur, m, mode,
-                                                c->rows, c->waves, c->prm.storage, c->stream, ev);
+                                                c->rows, c->waves, c->cols, c->prm.storage,
+                                                c->stream, ev);
                 });
                 if (rc) return rc;
                 c->cur ^= 1;
@@ -740,7 +775,7 @@ std::vector<Shape> batch_candidates(int storage) {
 
 int64_t batch_tiles(rec_ctx* const* ctxs, int n, Shape sh) {
     int64_t t = 0;
-    for (int i = 0; i < n; ++i) t += rec::fused_tiles(ctxs[i]->fr, sh.rows, sh.waves, sh.k);
+    for (int i = 0; i < n; ++i) t += rec::fused_tiles(ctxs[i]->fr, sh.rows, sh.waves, 64, sh.k);
     return t;
 }
 
@@ -772,7 +807,8 @@ size_t batch_desc_bytes(int n) { return align_up((size_t)n * sizeof(rec::StreamD
 int upload_work(rec_batch* b) {
     std::vector<int2> w;
     for (size_t s = 0; s < b->ctx.size(); ++s) {
-        const int t = rec::fused_tiles(b->ctx[s]->fr, b->shape.rows, b->shape.waves, b->shape.k);
+        const int t =
+            rec::fused_tiles(b->ctx[s]->fr, b->shape.rows, b->shape.waves, 64, b->shape.k);
         if (t <= 0) return REC_EINVAL;
         for (int q = 0; q < t; ++q) w.push_back(make_int2((int)s, q));
     }
@@ -906,11 +942,11 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
     }
     // default geometry: the automatic choice for the batch's total pixel
     // count (the launches cover every stream's tiles at once)
-    int r, w, k;
+    int r, w, cw, k;
     int64_t total = 0;
     for (int i = 0; i < n; ++i) total += (int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
-    choose_shape(&ctxs[0]->prm, total, &r, &w, &k);
-    if (!rec::batch_shape_supported(r, w, ctxs[0]->prm.storage)) {
+    choose_shape(&ctxs[0]->prm, total, false, &r, &w, &cw, &k);
+    if (cw != 64 || !rec::batch_shape_supported(r, w, ctxs[0]->prm.storage)) {
         r = 4;
         w = 8;
         if (k > 15) k = 15;
@@ -953,7 +989,8 @@ int rec_batch_solve(rec_batch* b, int32_t iters) {
     int rc;
     // pushes the first launch cannot fold are scattered first
     for (rec_ctx* c : b->ctx) {
-        const int64_t tiles = rec::fused_tiles(c->fr, b->shape.rows, b->shape.waves, b->shape.k);
+        const int64_t tiles =
+            rec::fused_tiles(c->fr, b->shape.rows, b->shape.waves, 64, b->shape.k);
         if (c->deferred_events > kFoldMaxEvents || c->deferred_events * tiles > kFoldMaxWork) {
             rc = flush_deferred(c);
             if (rc) return rc;

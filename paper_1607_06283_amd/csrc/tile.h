@@ -1,11 +1,13 @@
 // Register-tile building blocks shared by the fused loops: the forward
 // primal-dual iteration of a tile and the lane / XCD helpers.
 //
-// Tile layout: a workgroup of NW wavefronts covers 64 columns x (NW * R)
-// rows; lane = column, each lane holds R consecutive rows in registers and
-// wavefront w holds rows [w R, w R + R).  Horizontal neighbours come from
-// adjacent lanes (DPP), vertical ones from the lane's own registers or,
-// across wavefronts, through LDS.
+// Tile layout: a workgroup's lanes form NV rows of CW lanes ("lane rows";
+// CW = 64: one per wavefront, CW = 32: two per wavefront) and cover CW
+// columns x (NV * R) rows; lane = column within its lane row, each lane
+// holds R consecutive rows in registers and lane row v holds rows
+// [v R, v R + R).  Horizontal neighbours come from adjacent lanes (DPP
+// whole-wavefront shifts), vertical ones from the lane's own registers or,
+// across lane rows, through LDS.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,7 +26,10 @@ __device__ __forceinline__ int xcd_tile(int b, int ntiles) {
 }
 
 // Whole-wavefront lane shifts by one lane (DPP wave_shr:1 / wave_shl:1);
-// the lane without a source receives 0.
+// the lane without a source receives 0.  With two lane rows per wavefront
+// the first column of the second lane row receives the last column of the
+// first (and vice versa): both are halo columns of the tile, whose values
+// are not exact anyway, and every such value is finite.
 __device__ __forceinline__ float lane_from_left(float v) {   // value of lane - 1
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
@@ -40,6 +45,7 @@ __device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 
 // It may skip the iteration's arithmetic but must still take part in its
 // two barriers (tile_skip); the LDS rows it leaves stale are read only by
 // rows that are themselves outside the exact region.
+// (R: rows per wavefront, NW: wavefronts of the tile.)
 template <int R, int NW>
 __device__ __forceinline__ bool tile_rows_active(int wave, int it) {
     constexpr int RH = NW * R;
@@ -55,16 +61,17 @@ __device__ __forceinline__ void tile_skip() {
 }
 
 // One primal-dual iteration of a tile held in registers (u, p, metric
-// constants c per row).  Rows that cross wavefronts go through LDS:
-// xq[w + 1] receives wavefront w's last q_y row and xu[w] its first
-// extrapolated row (NW + 1 rows of 64 floats each); xq[0] and xu[NW] must
-// hold zeros.  Pixels outside the image carry all-zero M, so every
-// neighbour term they contribute is 0.
-template <int R, int NW>
+// constants c per row, ts = tau / sigma) with NV lane rows of CW lanes;
+// `col` is the lane's column and `v` its lane row.  Rows that cross lane
+// rows go through LDS: xq[v + 1] receives lane row v's last q_y row and
+// xu[v] its first extrapolated row (NV + 1 rows of CW floats each); xq[0]
+// and xu[NV] must hold zeros.  Pixels outside the image carry all-zero
+// coefficients, so every neighbour term they contribute is 0.
+template <int R, int NV, int CW = 64>
 __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
-                                               float (&p3)[R], const Coef (&c)[R], float tau,
-                                               float sigma, float umin, float umax, int lane,
-                                               int wave, float (*xq)[64], float (*xu)[64]) {
+                                               float (&p3)[R], const Coef (&c)[R], float ts,
+                                               float umin, float umax, int col, int v,
+                                               float (*xq)[CW], float (*xu)[CW]) {
     float qx[R], qy[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -72,30 +79,30 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
         qy[r] = q_y(c[r], p1[r], p2[r], p3[r]);
     }
     float qy_top = 0.0f;
-    if constexpr (NW > 1) {
-        xq[wave + 1][lane] = qy[R - 1];
+    if constexpr (NV > 1) {
+        xq[v + 1][col] = qy[R - 1];
         __syncthreads();
-        qy_top = xq[wave][lane];
+        qy_top = xq[v][col];
     }
     float un[R], ut[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const float qxl = lane_from_left(qx[r]);
         const float qyu = r > 0 ? qy[r - 1] : qy_top;
-        un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], tau, umin, umax);
+        un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], ts, umin, umax);
         ut[r] = extrapolate(un[r], u[r]);
     }
     float ut_bot = 0.0f;
-    if constexpr (NW > 1) {
-        xu[wave][lane] = ut[0];
+    if constexpr (NV > 1) {
+        xu[v][col] = ut[0];
         __syncthreads();
-        ut_bot = xu[wave + 1][lane];
+        ut_bot = xu[v + 1][col];
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const float utr = lane_from_right(ut[r]);
         const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
-        dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r], sigma);
+        dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r]);
         u[r] = un[r];
     }
 }

@@ -48,7 +48,8 @@ class rec_params(ctypes.Structure):
         ("storage", ctypes.c_int32),
         ("tvl1_iters", ctypes.c_int32),
         ("tvl1_lambda", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("tile_cols", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 

@@ -28,10 +28,11 @@ def test_exports_match_header():
 
 
 def test_struct_sizes_match_header_layout():
-    # rec_params: 2 int32, 9 double, 8 int32, 1 double, 4 int32 reserved
+    # rec_params: 2 int32, 9 double, 8 int32, 1 double, tile_cols, 3 int32 reserved
     import ctypes
     assert ctypes.sizeof(rec.rec_params) == 136
     assert rec.rec_params.tvl1_lambda.offset == 112
+    assert rec.rec_params.tile_cols.offset == 120
     assert ctypes.sizeof(rec.rec_stats) == 40
     assert ctypes.sizeof(rec.rec_profile_t) == 72
 
@@ -77,6 +78,29 @@ def test_reduced_storage_needs_fused_loop():
         p.tile_rows, p.tile_waves = 4, 16
         assert rec.rec_check_params(p) == rec.REC_OK
         p.tile_rows, p.tile_waves = 0, 0
+
+
+def test_tile_cols_params():
+    p = rec.rec_default_params(64, 48)
+    assert p.tile_cols == 0
+    p.tile_cols = 32                      # only together with tile_rows / tile_waves
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
+    p.tile_rows, p.tile_waves = 2, 8
+    assert rec.rec_check_params(p) == rec.REC_OK
+    for cols in (16, 48, 128, -32):
+        p.tile_cols = cols
+        assert rec.rec_check_params(p) == rec.REC_EINVAL
+    p.tile_cols = 32
+    p.tile_rows, p.tile_waves = 6, 8      # no 32-column variant of this tile
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
+    p.tile_rows, p.tile_waves = 1, 16
+    assert rec.rec_check_params(p) == rec.REC_OK
+    p.storage = rec.REC_STORE_BF16        # 16-bit storage: 2x8 only
+    assert rec.rec_check_params(p) == rec.REC_EINVAL
+    p.tile_rows, p.tile_waves = 2, 8
+    assert rec.rec_check_params(p) == rec.REC_OK
+    p.tile_cols = 64
+    assert rec.rec_check_params(p) == rec.REC_EINVAL   # 2x8 of 64 columns: FP32 only
 
 
 def test_denoising_params():

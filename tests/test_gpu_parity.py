@@ -163,7 +163,16 @@ def test_fused_equals_plain_bitwise(W, H):
             dict(fuse_iters=12, tile_rows=2, tile_waves=16, gap_every=5),
             dict(fuse_iters=6, tile_rows=6, tile_waves=8), dict(fuse_iters=7, tile_rows=5, tile_waves=8),
             dict(fuse_iters=9, tile_rows=3, tile_waves=16), dict(fuse_iters=6, tile_rows=4, tile_waves=8),
-            dict(fuse_iters=0, gap_every=7)]
+            dict(fuse_iters=0, gap_every=7),
+            # 32-column tiles (two lane rows per wavefront)
+            dict(fuse_iters=8, tile_rows=2, tile_waves=8, tile_cols=32),
+            dict(fuse_iters=15, tile_rows=1, tile_waves=16, tile_cols=32),
+            dict(fuse_iters=5, tile_rows=4, tile_waves=4, tile_cols=32),
+            dict(fuse_iters=3, tile_rows=1, tile_waves=8, tile_cols=32),
+            dict(fuse_iters=11, tile_rows=3, tile_waves=8, tile_cols=32),
+            dict(fuse_iters=13, tile_rows=2, tile_waves=16, tile_cols=32, gap_every=6),
+            dict(fuse_iters=6, tile_rows=2, tile_waves=4, tile_cols=32),
+            dict(fuse_iters=9, tile_rows=4, tile_waves=8, tile_cols=32)]
     for cfg in cfgs:
         r = rec.Reconstructor(W, H, **cfg)
         for a in range(0, n, n // 4):
@@ -533,8 +542,10 @@ def test_reduced_storage_tile_independent(storage):
     W, H = 150, 97
     t, x, y, p = _random_stream(W, H, 4000, seed=77)
     outs = []
-    for rows, waves in [(2, 16), (4, 16), (4, 8), (8, 4), (8, 8)]:
-        r = rec.Reconstructor(W, H, storage=storage, fuse_iters=6, tile_rows=rows, tile_waves=waves)
+    for rows, waves, cols in [(2, 16, 64), (4, 16, 64), (4, 8, 64), (8, 4, 64), (8, 8, 64),
+                              (2, 8, 32)]:
+        r = rec.Reconstructor(W, H, storage=storage, fuse_iters=6, tile_rows=rows, tile_waves=waves,
+                              tile_cols=cols)
         for a in range(0, 4000, 1000):
             r.push(*device_events(evgen.Events(t[a:a + 1000], x[a:a + 1000], y[a:a + 1000],
                                                p[a:a + 1000], np.zeros(1000, np.uint8))),
