@@ -37,6 +37,11 @@ __device__ __forceinline__ float lane_from_right(float v) {  // value of lane + 
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
 
+// Makes the value available at this point of the program: an empty asm
+// statement that reads it, so the compiler cannot sink its computation past
+// a following barrier.
+__device__ __forceinline__ void settle(float x) { asm volatile("" ::"v"(x)); }
+
 // Whether wavefront `wave` must compute iteration `it` (1-based) of a
 // launch.  After `it` iterations of a tile started from exact values
 // everywhere, rows [it, RH - it) are exact (each iteration reads one row
@@ -67,6 +72,9 @@ __device__ __forceinline__ void tile_skip() {
 // xu[v] its first extrapolated row (NV + 1 rows of CW floats each); xq[0]
 // and xu[NV] must hold zeros.  Pixels outside the image carry all-zero
 // coefficients, so every neighbour term they contribute is 0.
+// The rows whose neighbours are in the lane's own registers are updated
+// before each barrier, so that only one row's update waits for the
+// exchange (the result does not depend on this order).
 template <int R, int NV, int CW = 64>
 __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
                                                float (&p3)[R], const Coef (&c)[R], float ts,
@@ -78,33 +86,38 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
         qx[r] = q_x(c[r], p1[r], p2[r], p3[r]);
         qy[r] = q_y(c[r], p1[r], p2[r], p3[r]);
     }
+    if constexpr (NV > 1) xq[v + 1][col] = qy[R - 1];
+    float un[R], ut[R];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        un[r] = primal(u[r], qx[r], qy[r], lane_from_left(qx[r]), qy[r - 1], c[r], ts, umin, umax);
+        ut[r] = extrapolate(un[r], u[r]);
+        settle(ut[r]);
+    }
     float qy_top = 0.0f;
     if constexpr (NV > 1) {
-        xq[v + 1][col] = qy[R - 1];
         __syncthreads();
         qy_top = xq[v][col];
     }
-    float un[R], ut[R];
+    un[0] = primal(u[0], qx[0], qy[0], lane_from_left(qx[0]), qy_top, c[0], ts, umin, umax);
+    ut[0] = extrapolate(un[0], u[0]);
+    if constexpr (NV > 1) xu[v][col] = ut[0];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const float qxl = lane_from_left(qx[r]);
-        const float qyu = r > 0 ? qy[r - 1] : qy_top;
-        un[r] = primal(u[r], qx[r], qy[r], qxl, qyu, c[r], ts, umin, umax);
-        ut[r] = extrapolate(un[r], u[r]);
+    for (int r = 0; r < R - 1; ++r) {
+        dual(p1[r], p2[r], p3[r], lane_from_right(ut[r]) - ut[r], ut[r + 1] - ut[r], c[r]);
+        u[r] = un[r];
+        settle(p1[r]);
+        settle(p2[r]);
+        settle(p3[r]);
     }
     float ut_bot = 0.0f;
     if constexpr (NV > 1) {
-        xu[v][col] = ut[0];
         __syncthreads();
         ut_bot = xu[v + 1][col];
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const float utr = lane_from_right(ut[r]);
-        const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
-        dual(p1[r], p2[r], p3[r], utr - ut[r], utd - ut[r], c[r]);
-        u[r] = un[r];
-    }
+    dual(p1[R - 1], p2[R - 1], p3[R - 1], lane_from_right(ut[R - 1]) - ut[R - 1],
+         ut_bot - ut[R - 1], c[R - 1]);
+    u[R - 1] = un[R - 1];
 }
 
 }  // namespace rec
