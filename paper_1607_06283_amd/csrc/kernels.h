@@ -92,6 +92,8 @@ constexpr int kEvents = 4;  // with kBuild: validate and bin the folded events i
 constexpr int kCommit = 8;  // commit the pending stream state of the previous launch
 constexpr int kCounts = 16; // with kBuild: add the scattered event counts
 constexpr int kTimeMem = 32; // with kBuild: tx, ty were written by the timestamp denoising
+constexpr int kRotIn = 64;   // p is loaded in the standard basis: rotate it into the frame
+constexpr int kRotOut = 128; // rotate p back to the standard basis before storing it
 
 constexpr int kGapBlock = 256;
 constexpr int kGapHistCap = 4096;
@@ -137,14 +139,21 @@ hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double l
                        int storage, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
                          LaunchEv ev = {});
+// The two-kernel loop iterates on frame coordinates of p: launch_rotate
+// brings p into the frame (to_frame) before the first iteration of a solve
+// and back after the last.
+hipError_t launch_rotate(const Planes& P, Frame fr, int cur, bool to_frame, hipStream_t s,
+                         LaunchEv ev = {});
 hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts k, int cur, hipStream_t s,
                            LaunchEv ev = {});
 hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts k, BuildConsts bc,
                            const EventSegs& segs, int cur, int iters, int mode, int rows,
                            int waves, int cols, int storage, hipStream_t s, LaunchEv ev = {});
 bool fused_shape_supported(int rows, int waves, int cols, int storage);
+// rotated: p holds frame coordinates (between the launches of a solve).
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, int storage, hipStream_t s, LaunchEv ev = {});
+                      int cur, bool rotated, int slot, int storage, hipStream_t s,
+                      LaunchEv ev = {});
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
                              hipStream_t s);
 hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s);
@@ -153,8 +162,8 @@ hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipS
 // K iterations in this launch, KG the halo of the tile geometry (K <= KG),
 // li the launch's index within the solve, bins: some stream folds events.
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
-                           int li, bool bins, int rows, int waves, int storage, hipStream_t s,
-                           LaunchEv ev = {});
+                           int li, bool last, bool bins, int rows, int waves, int storage,
+                           hipStream_t s, LaunchEv ev = {});
 bool batch_shape_supported(int rows, int waves, int storage);
 hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max_np,
                                hipStream_t s);

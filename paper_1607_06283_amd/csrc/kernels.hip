@@ -464,8 +464,16 @@ __global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double 
 
 // ---------------------------------------------------------------- plain loop
 
-// Primal half-step for every pixel: needs q = C^T p here, at the left and
-// at the upper neighbour (0 where the neighbour is outside the image).
+// Coefficients of pixel k for the iteration on frame coordinates.
+__device__ __forceinline__ CoefT pixel_coef(const Planes& P, Frame fr, const IterConsts& kc,
+                                            size_t k, int i, int j) {
+    const Basis b = make_basis(P.tx[k], P.ty[k]);
+    return make_coef_t(b, P.f[k], kc.taulam, kc.sigma, j < fr.W - 1, i < fr.H - 1);
+}
+
+// Primal half-step for every pixel: needs q here, at the left and at the
+// upper neighbour (0 where the neighbour is outside the image); p holds
+// frame coordinates.
 __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts kc, int cur) {
     const int j = blockIdx.x * 64 + (threadIdx.x & 63);
     const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
@@ -473,22 +481,17 @@ __global__ __launch_bounds__(256) void k_primal(Planes P, Frame fr, IterConsts k
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)i * fr.W + j;
     const float* p = P.p[cur];
-    const Coef c =
-        make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, kc.sigma, j < fr.W - 1, i < fr.H - 1);
+    const CoefT c = pixel_coef(P, fr, kc, k, i, j);
     const float qx = q_x(c, p[k], p[np + k], p[2 * np + k]);
     const float qy = q_y(c, p[k], p[np + k], p[2 * np + k]);
     float qxl = 0.0f, qyu = 0.0f;
     if (j > 0) {
         const size_t kl = k - 1;
-        const Coef cl =
-            make_coef(P.tx[kl], P.ty[kl], P.f[kl], kc.taulam, kc.sigma, true, i < fr.H - 1);
-        qxl = q_x(cl, p[kl], p[np + kl], p[2 * np + kl]);
+        qxl = q_x(pixel_coef(P, fr, kc, kl, i, j - 1), p[kl], p[np + kl], p[2 * np + kl]);
     }
     if (i > 0) {
         const size_t ku = k - fr.W;
-        const Coef cu =
-            make_coef(P.tx[ku], P.ty[ku], P.f[ku], kc.taulam, kc.sigma, j < fr.W - 1, true);
-        qyu = q_y(cu, p[ku], p[np + ku], p[2 * np + ku]);
+        qyu = q_y(pixel_coef(P, fr, kc, ku, i - 1, j), p[ku], p[np + ku], p[2 * np + ku]);
     }
     P.u[cur ^ 1][k] = primal(P.u[cur][k], qx, qy, qxl, qyu, c, kc.ts, kc.umin, kc.umax);
 }
@@ -506,8 +509,7 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
     float gx = 0.0f, gy = 0.0f;
     if (j < fr.W - 1) gx = extrapolate(un[k + 1], uo[k + 1]) - ut;
     if (i < fr.H - 1) gy = extrapolate(un[k + fr.W], uo[k + fr.W]) - ut;
-    const Coef c =
-        make_coef(P.tx[k], P.ty[k], P.f[k], kc.taulam, kc.sigma, j < fr.W - 1, i < fr.H - 1);
+    const CoefT c = pixel_coef(P, fr, kc, k, i, j);
     const float* p = P.p[cur];
     float p1 = p[k], p2 = p[np + k], p3 = p[2 * np + k];
     dual(p1, p2, p3, gx, gy, c);
@@ -515,6 +517,24 @@ __global__ __launch_bounds__(256) void k_dual(Planes P, Frame fr, IterConsts kc,
     po[k] = p1;
     po[np + k] = p2;
     po[2 * np + k] = p3;
+}
+
+// p of every pixel into its frame (to = 1) or back to the standard basis
+// (to = 0), in place (two-kernel loop; FP32 storage).
+__global__ __launch_bounds__(256) void k_rotate(Planes P, Frame fr, int cur, int to) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    float* p = P.p[cur];
+    const Basis b = make_basis(P.tx[k], P.ty[k]);
+    float p1 = p[k], p2 = p[np + k], p3 = p[2 * np + k];
+    if (to)
+        to_frame(b, p1, p2, p3);
+    else
+        from_frame(b, p1, p2, p3);
+    p[k] = p1;
+    p[np + k] = p2;
+    p[2 * np + k] = p3;
 }
 
 // ---------------------------------------------------------------- fused loop
@@ -689,6 +709,11 @@ __device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int R
 //   (dynamic LDS); with kCounts the scattered counts are added.
 // mode & kZero: resets the scattered counts of the interior at the end.
 // mode & kCommit: block 0 commits the pending stream state.
+// mode & kRotIn: p is loaded in the standard basis and rotated into each
+//   pixel's tangent frame (the solve's first launch); otherwise p holds
+//   frame coordinates already.
+// mode & kRotOut: p is rotated back to the standard basis before it is
+//   stored (the solve's last launch).
 //
 // The tile geometry uses a halo of KG >= K pixels (the batched launch keeps
 // one geometry for all launches of a solve); tile (txi, tyi) covers the
@@ -738,7 +763,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     }
 
     float u[R], p1[R], p2[R], p3[R];
-    Coef c[R];
+    CoefT c[R];
     const bool col_in = gx >= 0 && gx < fr.W;
     const bool col_out = col_in && col >= KG && col < CW - KG;
 #pragma unroll
@@ -793,13 +818,14 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
                 ty = S::ld(tys, k);
             }
         }
+        // pixels outside the image get all-zero coefficients, so their q is 0
+        const Basis bs = make_basis(tx, ty);
+        c[r] = make_coef_t(bs, f, kc.taulam, kc.sigma, in && gx < fr.W - 1, in && gy < fr.H - 1);
+        if (mode & kRotIn) to_frame(bs, a, b, d);
         u[r] = uu;
         p1[r] = a;
         p2[r] = b;
         p3[r] = d;
-        // pixels outside the image get all-zero coefficients, so their q is 0
-        c[r] = make_coef(tx, ty, f, kc.taulam, kc.sigma, in && gx < fr.W - 1,
-                         in && gy < fr.H - 1);
     }
 
     // Rows that cross lane rows go through LDS.  xq[v + 1] holds lane row
@@ -845,6 +871,11 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         if (col_out && row >= KG && row < RH - KG && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
             uout[k] = u[r];
+            if (mode & kRotOut) {
+                // tx, ty as stored (this launch wrote them if it built them)
+                const Basis bs = make_basis(S::ld(txs, k), S::ld(tys, k));
+                from_frame(bs, p1[r], p2[r], p3[r]);
+            }
             S::st(pout, k, p1[r]);
             S::st(pout, np + k, p2[r]);
             S::st(pout, 2 * np + k, p3[r]);
@@ -870,17 +901,17 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
 // pairs); every stream runs the same iterations with its own planes,
 // constants and folded events.  launch = index of this launch in the solve
 // (selects the stream's first-launch and second-launch modes and the
-// ping-pong parity).
+// ping-pong parity); last: the solve's last launch.
 template <int R, int NW, class S>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __restrict__ descs,
                                                             const int2* __restrict__ work,
                                                             int nwork, int K, int KG,
-                                                            int launch) {
+                                                            int launch, int last) {
     extern __shared__ unsigned char dyn_lds[];
     const int2 w = work[xcd_tile(blockIdx.x, nwork)];
     const StreamDesc& d = descs[w.x];
     const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
-    const int mode = launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0);
+    const int mode = (launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0)) | (last ? kRotOut : 0);
     pd_tile<R, NW, 64, S>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode, txi,
                           tyi, w.y == 0, dyn_lds);
 }
@@ -914,7 +945,8 @@ __device__ __forceinline__ double warp_sum(double v) {
 //   energy = s |A| + b (u - f log u)
 template <class S>
 __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double lambda,
-                                                   double umin, double umax, int cur) {
+                                                   double umin, double umax, int cur,
+                                                   int rotated) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     double g = 0.0, e = 0.0;
@@ -924,10 +956,21 @@ __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double la
         const typename S::T* p = (const typename S::T*)P.p[cur];
         const typename S::T* txs = (const typename S::T*)P.tx;
         const typename S::T* tys = (const typename S::T*)P.ty;
+        // p of pixel kk in the standard basis (mid-solve the planes hold
+        // frame coordinates: rotated back with the FP32 arithmetic of the
+        // solve's last launch)
+        auto ld_p = [&](size_t kk, double& a, double& b, double& d) {
+            float p1 = S::ld(p, kk), p2 = S::ld(p, np + kk), p3 = S::ld(p, 2 * np + kk);
+            if (rotated) from_frame(make_basis(S::ld(txs, kk), S::ld(tys, kk)), p1, p2, p3);
+            a = p1;
+            b = p2;
+            d = p3;
+        };
         auto qxy = [&](size_t kk, double& qx, double& qy) {
             const double tx = S::ld(txs, kk), ty = S::ld(tys, kk);
             const double G = 1.0 + tx * tx + ty * ty;
-            const double a = S::ld(p, kk), b = S::ld(p, np + kk), d = S::ld(p, 2 * np + kk);
+            double a, b, d;
+            ld_p(kk, a, b, d);
             qx = ((1.0 + ty * ty) * a - tx * ty * b + tx * d) / G;
             qy = (-tx * ty * a + (1.0 + tx * tx) * b + ty * d) / G;
         };
@@ -941,8 +984,9 @@ __global__ __launch_bounds__(kGapBlock) void k_gap(Planes P, Frame fr, double la
         const double A2 = ((1.0 + tx * tx) * uy - tx * ty * ux) / G;
         const double A3 = (tx * ux + ty * uy) / G;
         const double nA = sqrt(A1 * A1 + A2 * A2 + A3 * A3);
-        const double t1 =
-            s * nA - (A1 * S::ld(p, k) + A2 * S::ld(p, np + k) + A3 * S::ld(p, 2 * np + k));
+        double pk1, pk2, pk3;
+        ld_p(k, pk1, pk2, pk3);
+        const double t1 = s * nA - (A1 * pk1 + A2 * pk2 + A3 * pk3);
         double qx, qy, qxl = 0.0, qyu = 0.0, dummy;
         qxy(k, qx, qy);
         if (j > 0) qxy(k - 1, qxl, dummy);
@@ -1018,11 +1062,11 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
 
 template <int R, int NW, class S>
 hipError_t batch_launch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
-                        int launch_idx, bool bins, hipStream_t s, LaunchEv ev) {
+                        int launch_idx, bool last, bool bins, hipStream_t s, LaunchEv ev) {
     if (K < 1 || K > KG || 64 - 2 * KG <= 0 || NW * R - 2 * KG <= 0) return hipErrorInvalidValue;
     return launch(k_pd_fused_batch<R, NW, S>, dim3(nwork), dim3(64 * NW),
                   fused_lds_bytes(R, NW, 64, bins ? kEvents : 0), s, ev.start, ev.stop, descs,
-                  work, nwork, K, KG, launch_idx);
+                  work, nwork, K, KG, launch_idx, last ? 1 : 0);
 }
 
 }  // namespace
@@ -1112,6 +1156,13 @@ hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_
     const size_t n = zero_counts ? np : 1;
     return launch(k_finish, dim3(blocks_for(n, 256)), dim3(256), 0, s, ev.start, ev.stop, P, np,
                   zero_counts ? 1 : 0);
+}
+
+hipError_t launch_rotate(const Planes& P, Frame fr, int cur, bool to_frame, hipStream_t s,
+                         LaunchEv ev) {
+    const size_t np = (size_t)fr.W * fr.H;
+    return launch(k_rotate, dim3(blocks_for(np, 256)), dim3(256), 0, s, ev.start, ev.stop, P, fr,
+                  cur, to_frame ? 1 : 0);
 }
 
 hipError_t launch_pd_plain(const Planes& P, Frame fr, IterConsts kc, int cur, hipStream_t s,
@@ -1208,17 +1259,20 @@ hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts
 #undef REC_FUSED_CASE
 #undef REC_FUSED_CASE16
 
-#define REC_BATCH_CASE(R, NW) \
-    case R * 100 + NW: return batch_launch<R, NW, StoreF32>(descs, work, nwork, K, KG, li, bins, s, ev);
+#define REC_BATCH_CASE(R, NW)                                                                   \
+    case R * 100 + NW:                                                                          \
+        return batch_launch<R, NW, StoreF32>(descs, work, nwork, K, KG, li, last, bins, s, ev);
 #define REC_BATCH_CASE16(R, NW)                                                                  \
     case R * 100 + NW:                                                                          \
         return storage == kStoreF16                                                             \
-                   ? batch_launch<R, NW, StoreF16>(descs, work, nwork, K, KG, li, bins, s, ev)   \
-                   : batch_launch<R, NW, StoreBF16>(descs, work, nwork, K, KG, li, bins, s, ev);
+                   ? batch_launch<R, NW, StoreF16>(descs, work, nwork, K, KG, li, last, bins, s, \
+                                                   ev)                                          \
+                   : batch_launch<R, NW, StoreBF16>(descs, work, nwork, K, KG, li, last, bins,  \
+                                                    s, ev);
 
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
-                           int li, bool bins, int rows, int waves, int storage, hipStream_t s,
-                           LaunchEv ev) {
+                           int li, bool last, bool bins, int rows, int waves, int storage,
+                           hipStream_t s, LaunchEv ev) {
     if (!batch_shape_supported(rows, waves, storage) || nwork <= 0) return hipErrorInvalidValue;
     if (storage != kStoreF32) {
         switch (rows * 100 + waves) {
@@ -1256,16 +1310,20 @@ hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max
 }
 
 hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, double umax,
-                      int cur, int slot, int storage, hipStream_t s, LaunchEv ev) {
+                      int cur, bool rotated, int slot, int storage, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     const size_t nb = gap_blocks(np);
     const dim3 g((unsigned)nb), b(kGapBlock);
+    const int rot = rotated ? 1 : 0;
     hipError_t e =
         storage == kStoreF16
-            ? launch(k_gap<StoreF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur)
+            ? launch(k_gap<StoreF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax,
+                     cur, rot)
         : storage == kStoreBF16
-            ? launch(k_gap<StoreBF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur)
-            : launch(k_gap<StoreF32>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax, cur);
+            ? launch(k_gap<StoreBF16>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax,
+                     cur, rot)
+            : launch(k_gap<StoreF32>, g, b, 0, s, ev.start, nullptr, P, fr, lambda, umin, umax,
+                     cur, rot);
     if (e == hipSuccess)
         e = launch(k_gap_final, dim3(1), dim3(256), 0, s, nullptr, ev.stop, P, nb, slot);
     return e;

@@ -101,15 +101,19 @@ __device__ __forceinline__ float q_y(const Coef& c, float p1, float p2, float p3
 // prox_root returns the unclamped root and r (the reverse sweep of the
 // unrolled loop needs both); primal clamps it.
 __device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
-                                           const Coef& c, float ts, float& r) {
+                                           float beta, float c4, float ts, float& r) {
     const float div = (qx - qx_left) + (qy - qy_up);
     const float ubar = __builtin_fmaf(ts, div, u);
-    const float a = ubar - c.beta;
-    r = sqrt_(__builtin_fmaf(a, a, c.c4));
+    const float a = ubar - beta;
+    r = sqrt_(__builtin_fmaf(a, a, c4));
     const float d = r + __builtin_fabsf(a);
     const float pos = 0.5f * d;
-    const float neg = (0.5f * c.c4) * rcp(d);
+    const float neg = (0.5f * c4) * rcp(d);
     return a >= 0.0f ? pos : neg;
+}
+__device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
+                                           const Coef& c, float ts, float& r) {
+    return prox_root(u, qx, qy, qx_left, qy_up, c.beta, c.c4, ts, r);
 }
 
 __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
@@ -146,6 +150,113 @@ __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, 
     p1 = b1 * sc;
     p2 = b2 * sc;
     p3 = b3 * sc;
+}
+
+// ------------------------------------------------------------------------
+// The same iteration with the dual variable in a per-pixel orthonormal frame.
+//
+// The columns of M span the tangent plane of the surface (x, y, tau(x, y)):
+// with a = sqrt(1 + ty^2) and s = sqrt(G),
+//   e1 = (1 + ty^2, -tx ty, tx) / (a s),  e2 = (0, 1, ty) / a,
+//   n  = (-tx, -ty, 1) / s              (unit normal)
+// form an orthonormal basis U = [e1 e2 n] and M = [e1 e2] T with the upper
+// triangular T = [[e1x, e1y], [0, e2y]] (e1x = a / s, e1y = -tx ty / (a s),
+// e2y = 1 / a).  Writing p = U p' (p' = U^T p):
+//   M^T p = T^T (p'1, p'2),   U^T (p + sigma M g) = p' + sigma (T g, 0),
+// and the projection onto the ball of radius s is the same in p' (U is
+// orthogonal).  So the iteration runs on p' with the three coefficients of
+// sigma T (a masked column of M masks the same column of T): q costs three
+// operations instead of six and the dual ascent three instead of six.  The
+// solve rotates p into the frame once at its start and back at its end (the
+// frame depends on the block's time surface only).
+struct Basis {
+    float e1x, e1y, e1z;  // e1
+    float e2y, e2z;       // e2 (e2x = 0)
+    float nx, ny, nz;     // n
+    float s;              // sqrt(G)
+};
+
+__device__ __forceinline__ Basis make_basis(float tx, float ty) {
+    Basis b;
+    const float a2 = __builtin_fmaf(ty, ty, 1.0f);  // 1 + ty^2
+    const float G = __builtin_fmaf(tx, tx, a2);     // 1 + tx^2 + ty^2
+    const float ia = rsq(a2), is = rsq(G);
+    const float ias = ia * is;
+    b.e1x = a2 * ias;
+    b.e1y = -(tx * ty) * ias;
+    b.e1z = tx * ias;
+    b.e2y = ia;
+    b.e2z = ty * ia;
+    b.nx = -tx * is;
+    b.ny = -ty * is;
+    b.nz = is;
+    b.s = G * is;
+    return b;
+}
+
+struct CoefT {
+    float k11;      // sigma T11, 0 if the first column is masked
+    float k12, k22; // sigma T12, sigma T22, 0 if the second column is masked
+    float s;        // ball radius sqrt(G)
+    float beta, c4; // KL prox constants
+};
+
+__device__ __forceinline__ CoefT make_coef_t(const Basis& b, float f, float taulam, float sigma,
+                                             bool has_x, bool has_y) {
+    CoefT c;
+    c.k11 = has_x ? sigma * b.e1x : 0.0f;
+    c.k12 = has_y ? sigma * b.e1y : 0.0f;
+    c.k22 = has_y ? sigma * b.e2y : 0.0f;
+    c.s = b.s;
+    c.beta = taulam * b.s;
+    c.c4 = (4.0f * c.beta) * f;
+    return c;
+}
+
+// p' = U^T p and p = U p'.
+__device__ __forceinline__ void to_frame(const Basis& b, float& p1, float& p2, float& p3) {
+    const float r1 = __builtin_fmaf(b.e1z, p3, __builtin_fmaf(b.e1y, p2, b.e1x * p1));
+    const float r2 = __builtin_fmaf(b.e2z, p3, b.e2y * p2);
+    const float r3 = __builtin_fmaf(b.nz, p3, __builtin_fmaf(b.ny, p2, b.nx * p1));
+    p1 = r1;
+    p2 = r2;
+    p3 = r3;
+}
+__device__ __forceinline__ void from_frame(const Basis& b, float& p1, float& p2, float& p3) {
+    const float x = __builtin_fmaf(b.nx, p3, b.e1x * p1);
+    const float y = __builtin_fmaf(b.ny, p3, __builtin_fmaf(b.e2y, p2, b.e1y * p1));
+    const float z = __builtin_fmaf(b.nz, p3, __builtin_fmaf(b.e2z, p2, b.e1z * p1));
+    p1 = x;
+    p2 = y;
+    p3 = z;
+}
+
+// q = sigma M^T p from the frame coordinates p' (p'3 does not enter).
+__device__ __forceinline__ float q_x(const CoefT& c, float p1, float, float) {
+    return c.k11 * p1;
+}
+__device__ __forceinline__ float q_y(const CoefT& c, float p1, float p2, float) {
+    return __builtin_fmaf(c.k22, p2, c.k12 * p1);
+}
+
+__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
+                                        const CoefT& c, float ts, float umin, float umax) {
+    float r;
+    const float un = prox_root(u, qx, qy, qx_left, qy_up, c.beta, c.c4, ts, r);
+    return __builtin_amdgcn_fmed3f(un, umin, umax);
+}
+
+// Dual step in the frame: pbar' = p' + (sigma T g, 0), then the projection
+// onto the ball of radius s.
+__device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
+                                     const CoefT& c) {
+    const float b1 = __builtin_fmaf(c.k11, gx, __builtin_fmaf(c.k12, gy, p1));
+    const float b2 = __builtin_fmaf(c.k22, gy, p2);
+    const float n2 = __builtin_fmaf(p3, p3, __builtin_fmaf(b2, b2, b1 * b1));
+    const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
+    p1 = b1 * sc;
+    p2 = b2 * sc;
+    p3 = p3 * sc;
 }
 
 }  // namespace rec

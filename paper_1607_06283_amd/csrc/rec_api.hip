@@ -531,12 +531,25 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
         int seg = iters - it;
         if (ge > 0 && seg > ge - it % ge) seg = ge - it % ge;
         if (!fused) {
+            // the iterations run on p in each pixel's tangent frame
+            if (it == 0) {
+                rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
+                    return rec::launch_rotate(c->P, c->fr, c->cur, true, c->stream, ev);
+                });
+                if (rc) return rc;
+            }
             for (int q = 0; q < seg; ++q) {
                 rc = timed(c, 2, np, [&](rec::LaunchEv ev) {
                     return rec::launch_pd_plain(c->P, c->fr, c->kc, c->cur, c->stream, ev);
                 });
                 if (rc) return rc;
                 c->cur ^= 1;
+            }
+            if (it + seg == iters) {
+                rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
+                    return rec::launch_rotate(c->P, c->fr, c->cur, false, c->stream, ev);
+                });
+                if (rc) return rc;
             }
         } else {
             const int nl = (seg + c->kmax - 1) / c->kmax;
@@ -545,9 +558,10 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
                 int mode = 0;
                 if (launch == 0)
                     mode = rec::kBuild | (fold ? rec::kEvents : 0) | (counts ? rec::kCounts : 0) |
-                           (denoise ? rec::kTimeMem : 0);
+                           (denoise ? rec::kTimeMem : 0) | rec::kRotIn;
                 else if (launch == 1)
                     mode = rec::kCommit | (counts ? rec::kZero : 0);
+                if (it + seg == iters && q == nl - 1) mode |= rec::kRotOut;
                 rc = timed(c, 2, np * m, [&](rec::LaunchEv ev) {
                     return rec::launch_pd_fused(c->P, c->fr, c->kc, bc, segs, c->cur, m, mode,
                                                 c->rows, c->waves, c->cols, c->prm.storage,
@@ -571,7 +585,7 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
             const int slot = samples < rec::kGapHistCap ? samples : rec::kGapHistCap - 1;
             rc = timed(c, 3, np, [&](rec::LaunchEv ev) {
                 return rec::launch_gap(c->P, c->fr, c->prm.lambda, c->prm.u_min, c->prm.u_max,
-                                       c->cur, slot, c->prm.storage, c->stream, ev);
+                                       c->cur, it < iters, slot, c->prm.storage, c->stream, ev);
             });
             if (rc) return rc;
             ++samples;
@@ -843,7 +857,8 @@ void fill_desc(rec_batch* b, rec::StreamDesc* d, bool* any_fold) {
             e.segs.count = (int32_t)c->deferred.size();
             *any_fold = true;
         }
-        e.mode0 = rec::kBuild | (fold ? rec::kEvents : 0) | (c->counts_dirty ? rec::kCounts : 0);
+        e.mode0 = rec::kBuild | (fold ? rec::kEvents : 0) | (c->counts_dirty ? rec::kCounts : 0) |
+                  rec::kRotIn;
         e.mode1 = rec::kCommit | (c->counts_dirty ? rec::kZero : 0);
     }
 }
@@ -872,8 +887,9 @@ int time_shape(rec_batch* b, int reps, double* us) {
         if (q == 2) ev.start = e0;
         if (q == reps + 1) ev.stop = e1;
         // launch index 2: mode 0 for every stream, parity of launch 0
-        e = rec::launch_pd_batch(b->d_desc[0], b->d_work, b->nwork, b->shape.k, b->shape.k, 2, false,
-                                 b->shape.rows, b->shape.waves, b->storage, b->stream, ev);
+        e = rec::launch_pd_batch(b->d_desc[0], b->d_work, b->nwork, b->shape.k, b->shape.k, 2,
+                                 false, false, b->shape.rows, b->shape.waves, b->storage,
+                                 b->stream, ev);
     }
     float ms = 0.0f;
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
@@ -1016,8 +1032,9 @@ int rec_batch_solve(rec_batch* b, int32_t iters) {
         if (c0->prof_on)
             for (rec_ctx* c : b->ctx) work += (int64_t)c->fr.W * c->fr.H * m;
         rc = timed(c0, 2, work, [&](rec::LaunchEv ev) {
-            return rec::launch_pd_batch(b->d_desc[q], b->d_work, b->nwork, m, K, li, fold && li == 0,
-                                        b->shape.rows, b->shape.waves, b->storage, b->stream, ev);
+            return rec::launch_pd_batch(b->d_desc[q], b->d_work, b->nwork, m, K, li, li == nl - 1,
+                                        fold && li == 0, b->shape.rows, b->shape.waves,
+                                        b->storage, b->stream, ev);
         });
         if (rc) return rc;
     }
