@@ -762,7 +762,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         }
     }
 
-    float u[R], p1[R], p2[R], p3[R];
+    float u[R], p1[R], p2[R], p3[R], txr[R], tyr[R];
     CoefT c[R];
     const bool col_in = gx >= 0 && gx < fr.W;
     const bool col_out = col_in && col >= KG && col < CW - KG;
@@ -819,13 +819,20 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
             }
         }
         // pixels outside the image get all-zero coefficients, so their q is 0
-        const Basis bs = make_basis(tx, ty);
-        c[r] = make_coef_t(bs, f, kc.taulam, kc.sigma, in && gx < fr.W - 1, in && gy < fr.H - 1);
-        if (mode & kRotIn) to_frame(bs, a, b, d);
+        c[r] = make_coef_t(make_basis(tx, ty), f, kc.taulam, kc.sigma, in && gx < fr.W - 1,
+                           in && gy < fr.H - 1);
+        txr[r] = tx;
+        tyr[r] = ty;
         u[r] = uu;
         p1[r] = a;
         p2[r] = b;
         p3[r] = d;
+    }
+    // (a separate pass: a branch inside the loop above would keep the
+    // compiler from issuing all rows' loads ahead of the arithmetic)
+    if (mode & kRotIn) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) to_frame(make_basis(txr[r], tyr[r]), p1[r], p2[r], p3[r]);
     }
 
     // Rows that cross lane rows go through LDS.  xq[v + 1] holds lane row
@@ -864,6 +871,21 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
 
     float* __restrict__ uout = P.u[cur ^ 1];
     typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];
+    if (mode & kRotOut) {
+        // tx, ty as stored (this launch wrote them if it built them)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            txr[r] = tyr[r] = 0.0f;
+            if (col_in && gy >= 0 && gy < fr.H) {
+                const size_t k = (size_t)gy * fr.W + gx;
+                txr[r] = S::ld(txs, k);
+                tyr[r] = S::ld(tys, k);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) from_frame(make_basis(txr[r], tyr[r]), p1[r], p2[r], p3[r]);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int row = v * R + r;
@@ -871,11 +893,6 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         if (col_out && row >= KG && row < RH - KG && gy >= 0 && gy < fr.H) {
             const size_t k = (size_t)gy * fr.W + gx;
             uout[k] = u[r];
-            if (mode & kRotOut) {
-                // tx, ty as stored (this launch wrote them if it built them)
-                const Basis bs = make_basis(S::ld(txs, k), S::ld(tys, k));
-                from_frame(bs, p1[r], p2[r], p3[r]);
-            }
             S::st(pout, k, p1[r]);
             S::st(pout, np + k, p2[r]);
             S::st(pout, 2 * np + k, p3[r]);
