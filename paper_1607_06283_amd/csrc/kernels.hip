@@ -719,7 +719,9 @@ __device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int R
 // one geometry for all launches of a solve); tile (txi, tyi) covers the
 // region whose interior starts at (txi, tyi) * (CW - 2 KG, NV R - 2 KG).
 // `lead`: this tile does the per-stream duties (commit, pending state).
-template <int R, int NW, int CW, class S>
+// B = (mode & kBuild): the first launch of a solve is a kernel of its own,
+// so that the others carry no branch of the build path.
+template <int R, int NW, int CW, class S, bool B>
 __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterConsts& kc,
                                         const BuildConsts& bc, const EventSegs& segs, int cur,
                                         int K, int KG, int mode, int txi, int tyi, bool lead,
@@ -742,7 +744,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
 
     if ((mode & kCommit) && lead && threadIdx.x == 0) commit_pending(P.st);
 
-    const bool build = (mode & kBuild) != 0;
+    constexpr bool build = B;  // mode & kBuild (separate instantiations)
     const bool events = build && (mode & kEvents) != 0;
     TileBins tb;
     tb.ss = nullptr;
@@ -904,14 +906,14 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     }
 }
 
-template <int R, int NW, int CW, class S>
+template <int R, int NW, int CW, class S, bool B>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
                                                       BuildConsts bc, EventSegs segs, int cur,
                                                       int K, int mode, int tiles_x, int ntiles) {
     extern __shared__ unsigned char dyn_lds[];
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    pd_tile<R, NW, CW, S>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
+    pd_tile<R, NW, CW, S, B>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
 }
 
 // One launch over the tiles of many streams (a work list of (stream, tile)
@@ -919,7 +921,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
 // constants and folded events.  launch = index of this launch in the solve
 // (selects the stream's first-launch and second-launch modes and the
 // ping-pong parity); last: the solve's last launch.
-template <int R, int NW, class S>
+template <int R, int NW, class S, bool B>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __restrict__ descs,
                                                             const int2* __restrict__ work,
                                                             int nwork, int K, int KG,
@@ -929,8 +931,8 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __
     const StreamDesc& d = descs[w.x];
     const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
     const int mode = (launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0)) | (last ? kRotOut : 0);
-    pd_tile<R, NW, 64, S>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode, txi,
-                          tyi, w.y == 0, dyn_lds);
+    pd_tile<R, NW, 64, S, B>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode,
+                             txi, tyi, w.y == 0, dyn_lds);
 }
 
 // After a one-launch batched solve: commit and reset counts of every stream.
@@ -1072,18 +1074,25 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
     const int tiles_x = (fr.W + OW - 1) / OW;
     const int tiles_y = (fr.H + OH - 1) / OH;
     const int ntiles = tiles_x * tiles_y;
-    return launch(k_pd_fused<R, NW, CW, S>, dim3(ntiles), dim3(64 * NW),
-                  fused_lds_bytes(R, NW, CW, mode), s, ev.start, ev.stop, P, fr, kc, bc, segs, cur,
-                  K, mode, tiles_x, ntiles);
+    const size_t lds = fused_lds_bytes(R, NW, CW, mode);
+    if (mode & kBuild)
+        return launch(k_pd_fused<R, NW, CW, S, true>, dim3(ntiles), dim3(64 * NW), lds, s,
+                      ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
+    return launch(k_pd_fused<R, NW, CW, S, false>, dim3(ntiles), dim3(64 * NW), lds, s, ev.start,
+                  ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
 }
 
 template <int R, int NW, class S>
 hipError_t batch_launch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
                         int launch_idx, bool last, bool bins, hipStream_t s, LaunchEv ev) {
     if (K < 1 || K > KG || 64 - 2 * KG <= 0 || NW * R - 2 * KG <= 0) return hipErrorInvalidValue;
-    return launch(k_pd_fused_batch<R, NW, S>, dim3(nwork), dim3(64 * NW),
-                  fused_lds_bytes(R, NW, 64, bins ? kEvents : 0), s, ev.start, ev.stop, descs,
-                  work, nwork, K, KG, launch_idx, last ? 1 : 0);
+    // every stream's first-launch mode builds (launch 0 only)
+    const size_t lds = fused_lds_bytes(R, NW, 64, bins ? kEvents : 0);
+    if (launch_idx == 0)
+        return launch(k_pd_fused_batch<R, NW, S, true>, dim3(nwork), dim3(64 * NW), lds, s,
+                      ev.start, ev.stop, descs, work, nwork, K, KG, launch_idx, last ? 1 : 0);
+    return launch(k_pd_fused_batch<R, NW, S, false>, dim3(nwork), dim3(64 * NW), lds, s, ev.start,
+                  ev.stop, descs, work, nwork, K, KG, launch_idx, last ? 1 : 0);
 }
 
 }  // namespace
