@@ -270,9 +270,9 @@ int rec_batch_destroy(rec_batch* b);
  *   p_k+1 = proj_{|.| <= sqrt(G)}(p_k + sigma L_g (2 u_k+1 - u_k))
  *
  * from (u0, p0), with L_g, G from the time differences (tx, ty) (eqn. 3).
- * w = 1 is the paper's model; with w = 1 and p0 = 0 the result agrees with
- * rec_solve on the same block to FP32 rounding (rec_solve carries p in each
- * pixel's tangent frame, this solve in the standard basis).  rec_diff_forward returns (u_K, p_K) and keeps
+ * w = 1 is the paper's model; with w = 1 and p0 = 0 the result has the same
+ * bits as rec_solve on the same block (both carry p in each pixel's tangent
+ * frame between the first and the last iteration).  rec_diff_forward returns (u_K, p_K) and keeps
  * checkpoints of (u, p) every ckpt_every iterations in the workspace;
  * rec_diff_backward, given dJ/du_K (and optionally dJ/dp_K), recomputes each
  * segment from its checkpoint and runs the adjoint iterations backwards,

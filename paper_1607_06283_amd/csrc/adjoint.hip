@@ -25,6 +25,14 @@
 // recomputed, bit for bit, by the same forward kernels before the segment's
 // reverse steps run.
 //
+// With iters > 0 every stored state (checkpoints, recorded states) holds p
+// in each pixel's tangent frame (p' = U^T p, U = [e1 e2 n] of the time
+// surface; see pd_math.h), as the stream solve does between its launches:
+// the forward rotates p0 in and p_K out, the reverse rotates dJ/dp_K in and
+// dJ/dp0 out, and the adjoint q of p lives in the same coordinates (U is
+// orthogonal, so the adjoint of the rotation is its transpose).  The
+// forward then produces the same bits as the stream solve of the block.
+//
 // Two forms, same bits:
 //  - fused (default): register tiles as in the forward solve.  The forward
 //    runs a segment's iterations per launch; the recomputation of a segment
@@ -63,7 +71,14 @@ struct Steps {
     double tau_d;  // tau in FP64 (for tau * lambda, as the forward solve forms it)
     float ts;      // tau / sigma (the primal step on the sigma-scaled coefficients)
     float sigma, umin, umax;
+    int rot;       // iters > 0: states carry p in the tangent frame
 };
+
+// Coefficients of a pixel for the iteration on frame coordinates.
+__device__ __forceinline__ CoefT coef(float tx, float ty, float f, float taulam, float sigma,
+                                      bool has_x, bool has_y) {
+    return make_coef_t(make_basis(tx, ty), f, taulam, sigma, has_x, has_y);
+}
 
 __device__ __forceinline__ bool pixel(const Dims& d, int& i, int& j, size_t& o, size_t& b) {
     j = blockIdx.x * kTileX + (threadIdx.x & (kTileX - 1));
@@ -89,14 +104,14 @@ __device__ __forceinline__ float qx_left(const Dims& d, int i, int j, size_t o, 
                                          float sigma) {
     if (j == 0) return 0.0f;
     const size_t l = o - 1;
-    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, sigma, true, i < d.H - 1);
+    const CoefT c = coef(tx[l], ty[l], 0.0f, 0.0f, sigma, true, i < d.H - 1);
     return q_x(c, v1[l], v1[np + l], v1[2 * np + l]);
 }
 __device__ __forceinline__ float qy_up(const Dims& d, int i, int j, size_t o, const float* tx,
                                        const float* ty, const float* v1, size_t np, float sigma) {
     if (i == 0) return 0.0f;
     const size_t l = o - d.W;
-    const Coef c = make_coef(tx[l], ty[l], 0.0f, 0.0f, sigma, j < d.W - 1, true);
+    const CoefT c = coef(tx[l], ty[l], 0.0f, 0.0f, sigma, j < d.W - 1, true);
     return q_y(c, v1[l], v1[np + l], v1[2 * np + l]);
 }
 
@@ -108,12 +123,15 @@ __device__ __forceinline__ size_t field(const Dims& d, size_t b, size_t o) {
 
 // ------------------------------------------------------------------ forward
 
-// f = u0 exp(dpos n+ - dneg n-); state 0 = (u0, p0 or 0).
+// f = u0 exp(dpos n+ - dneg n-); state 0 = (u0, p0 or 0), p0 rotated into
+// the frame when rot.
 __global__ __launch_bounds__(kThreads) void k_diff_init(Dims d, const float* __restrict__ u0,
                                                         const float* __restrict__ p0,
                                                         const int32_t* __restrict__ npos,
                                                         const int32_t* __restrict__ nneg,
                                                         const double* __restrict__ theta,
+                                                        const float* __restrict__ tx,
+                                                        const float* __restrict__ ty, int rot,
                                                         float* __restrict__ f, State s0) {
     int i, j;
     size_t o, b;
@@ -122,7 +140,16 @@ __global__ __launch_bounds__(kThreads) void k_diff_init(Dims d, const float* __r
     f[o] = data_image(u, npos[o], nneg[o], theta[1], theta[2]);
     s0.u[o] = u;
     const size_t q = field(d, b, o);
-    for (int m = 0; m < 3; ++m) s0.p[q + m * d.np] = p0 ? p0[q + m * d.np] : 0.0f;
+    float p1 = 0.0f, p2 = 0.0f, p3 = 0.0f;
+    if (p0) {
+        p1 = p0[q];
+        p2 = p0[q + d.np];
+        p3 = p0[q + 2 * d.np];
+        if (rot) to_frame(make_basis(tx[o], ty[o]), p1, p2, p3);
+    }
+    s0.p[q] = p1;
+    s0.p[q + d.np] = p2;
+    s0.p[q + 2 * d.np] = p3;
 }
 
 // Primal half-step from state a into b.u.
@@ -138,8 +165,8 @@ __global__ __launch_bounds__(kThreads) void k_diff_primal(Dims d, State a, State
     if (!pixel(d, i, j, o, b)) return;
     const size_t q = field(d, b, o);
     const float* p = a.p + (q - o);  // image b's field, indexed by o
-    const Coef c = make_coef(tx[o], ty[o], f[o], taulam_w(theta, st.tau_d, w, o), st.sigma,
-                             j < d.W - 1, i < d.H - 1);
+    const CoefT c = coef(tx[o], ty[o], f[o], taulam_w(theta, st.tau_d, w, o), st.sigma,
+                         j < d.W - 1, i < d.H - 1);
     const float qx = q_x(c, p[o], p[d.np + o], p[2 * d.np + o]);
     const float qy = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
     const float qxl = qx_left(d, i, j, o, tx, ty, p, d.np, st.sigma);
@@ -158,7 +185,7 @@ __global__ __launch_bounds__(kThreads) void k_diff_dual(Dims d, State a, State b
     float gx = 0.0f, gy = 0.0f;
     if (j < d.W - 1) gx = extrapolate(b_.u[o + 1], a.u[o + 1]) - ut;
     if (i < d.H - 1) gy = extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut;
-    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
+    const CoefT c = coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
     const size_t q = field(d, b, o);
     float p1 = a.p[q], p2 = a.p[q + d.np], p3 = a.p[q + 2 * d.np];
     dual(p1, p2, p3, gx, gy, c);
@@ -167,7 +194,11 @@ __global__ __launch_bounds__(kThreads) void k_diff_dual(Dims d, State a, State b
     b_.p[q + 2 * d.np] = p3;
 }
 
-__global__ __launch_bounds__(kThreads) void k_diff_out(Dims d, State s, float* __restrict__ u,
+// (u_K, p_K), p rotated back to the standard basis when rot.
+__global__ __launch_bounds__(kThreads) void k_diff_out(Dims d, State s,
+                                                       const float* __restrict__ tx,
+                                                       const float* __restrict__ ty, int rot,
+                                                       float* __restrict__ u,
                                                        float* __restrict__ p) {
     int i, j;
     size_t o, b;
@@ -175,7 +206,11 @@ __global__ __launch_bounds__(kThreads) void k_diff_out(Dims d, State s, float* _
     u[o] = s.u[o];
     if (p) {
         const size_t q = field(d, b, o);
-        for (int m = 0; m < 3; ++m) p[q + m * d.np] = s.p[q + m * d.np];
+        float p1 = s.p[q], p2 = s.p[q + d.np], p3 = s.p[q + 2 * d.np];
+        if (rot) from_frame(make_basis(tx[o], ty[o]), p1, p2, p3);
+        p[q] = p1;
+        p[q + d.np] = p2;
+        p[q + 2 * d.np] = p3;
     }
 }
 
@@ -190,27 +225,28 @@ struct Adj {
     float* gf;     // [B][np] sum of f_hat over the steps
 };
 
-// hat p of the state after the latest reverse step, at one pixel:
-// q - tau L_g ub_hat = q - ts C grad ub_hat, ts = tau / sigma (first = no
-// step yet: g_p, or 0).
+// hat p of the state after the latest reverse step, at one pixel, in frame
+// coordinates when st.rot: q - tau L_g ub_hat = q - ts sigma M grad ub_hat,
+// ts = tau / sigma (first = no step yet: g_p rotated into the frame, or 0).
 __device__ __forceinline__ void adj_p(const Dims& d, int i, int j, size_t o, size_t q,
-                                      const Coef& c, const Adj& A, const float* g_p, bool first,
-                                      float ts, float& h1, float& h2, float& h3) {
+                                      const CoefT& c, const float* tx, const float* ty,
+                                      const Adj& A, const float* g_p, bool first,
+                                      const Steps& st, float& h1, float& h2, float& h3) {
     if (first) {
         h1 = g_p ? g_p[q] : 0.0f;
         h2 = g_p ? g_p[q + d.np] : 0.0f;
         h3 = g_p ? g_p[q + 2 * d.np] : 0.0f;
+        if (g_p && st.rot) to_frame(make_basis(tx[o], ty[o]), h1, h2, h3);
         return;
     }
     const float ubc = A.ub[o];
     const float gx = j < d.W - 1 ? A.ub[o + 1] - ubc : 0.0f;
     const float gy = i < d.H - 1 ? A.ub[o + d.W] - ubc : 0.0f;
-    const float v1 = __builtin_fmaf(c.b12, gy, c.a11 * gx);
-    const float v2 = __builtin_fmaf(c.b22, gy, c.a21 * gx);
-    const float v3 = __builtin_fmaf(c.b32, gy, c.a31 * gx);
-    h1 = __builtin_fmaf(-ts, v1, A.q[q]);
-    h2 = __builtin_fmaf(-ts, v2, A.q[q + d.np]);
-    h3 = __builtin_fmaf(-ts, v3, A.q[q + 2 * d.np]);
+    float v1, v2;
+    ascent_dir(c, gx, gy, v1, v2);
+    h1 = __builtin_fmaf(-st.ts, v1, A.q[q]);
+    h2 = __builtin_fmaf(-st.ts, v2, A.q[q + d.np]);
+    h3 = A.q[q + 2 * d.np];
 }
 
 // Reverse of the dual half-step of the iteration a -> b: q = J_proj^T h_p.
@@ -223,9 +259,9 @@ __global__ __launch_bounds__(kThreads) void k_adj_dual(Dims d, State a, State b_
     size_t o, b;
     if (!pixel(d, i, j, o, b)) return;
     const size_t q = field(d, b, o);
-    const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
+    const CoefT c = coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
     float h1, h2, h3;
-    adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.ts, h1, h2, h3);
+    adj_p(d, i, j, o, q, c, tx, ty, A, g_p, first != 0, st, h1, h2, h3);
     // pbar of the forward step, recomputed
     const float ut = extrapolate(b_.u[o], a.u[o]);
     const float gx = j < d.W - 1 ? extrapolate(b_.u[o + 1], a.u[o + 1]) - ut : 0.0f;
@@ -262,9 +298,9 @@ __global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
     const float* qf = A.q + (q - o);
     const float* p = a.p + (q - o);
     const float fo = f[o];
-    const Coef c = make_coef(tx[o], ty[o], fo, taulam_w(theta, st.tau_d, w, o), st.sigma,
-                             j < d.W - 1, i < d.H - 1);
-    // ut_hat = sigma L_g^* q = -div(C^T q)
+    const CoefT c = coef(tx[o], ty[o], fo, taulam_w(theta, st.tau_d, w, o), st.sigma,
+                         j < d.W - 1, i < d.H - 1);
+    // ut_hat = sigma L_g^* q = -div(sigma M^T q)
     const float qx = q_x(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
     const float qy = q_y(c, qf[o], qf[d.np + o], qf[2 * d.np + o]);
     const float divq = (qx - qx_left(d, i, j, o, tx, ty, qf, d.np, st.sigma)) +
@@ -277,7 +313,8 @@ __global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
     const float py = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
     float r;
     const float un = prox_root(a.u[o], px, py, qx_left(d, i, j, o, tx, ty, p, d.np, st.sigma),
-                               qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma), c, st.ts, r);
+                               qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma), c.beta, c.c4, st.ts,
+                               r);
     const bool active = un >= st.umin && un <= st.umax;
     const float hr = active ? H * rcp(r) : 0.0f;
     const float ub_hat = un * hr;
@@ -310,10 +347,11 @@ __global__ __launch_bounds__(kThreads) void k_adj_final(
     double s_lam = 0.0, s_dp = 0.0, s_dn = 0.0;
     if (pixel(d, i, j, o, b)) {
         const size_t q = field(d, b, o);
-        const Coef c = make_coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
+        const CoefT c = coef(tx[o], ty[o], 0.0f, 0.0f, st.sigma, j < d.W - 1, i < d.H - 1);
         if (gp0) {
             float h1, h2, h3;
-            adj_p(d, i, j, o, q, c, A, g_p, first != 0, st.ts, h1, h2, h3);
+            adj_p(d, i, j, o, q, c, tx, ty, A, g_p, first != 0, st, h1, h2, h3);
+            if (st.rot) from_frame(make_basis(tx[o], ty[o]), h1, h2, h3);
             gp0[q] = h1;
             gp0[q + d.np] = h2;
             gp0[q + 2 * d.np] = h3;
@@ -442,7 +480,7 @@ __device__ __forceinline__ void store_state(const Dims& d, const TileGrid& g, co
 template <int R>
 __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, const float* f,
                                            const float* tx, const float* ty, const float* w,
-                                           float tl, float sigma, Coef (&c)[R], float (&fr)[R]) {
+                                           float tl, float sigma, CoefT (&c)[R], float (&fr)[R]) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = t.gy0 + r;
@@ -456,7 +494,7 @@ __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, cons
             if (w) tlw = tl * w[k];
         }
         fr[r] = ff;
-        c[r] = make_coef(x, y, ff, tlw, sigma, in && t.gx < d.W - 1, in && gy < d.H - 1);
+        c[r] = coef(x, y, ff, tlw, sigma, in && t.gx < d.W - 1, in && gy < d.H - 1);
     }
 }
 
@@ -473,7 +511,7 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
     const TilePos t = tile_pos<R, NW>(d, g);
     const int K = g.kg;
     float u[R], p1[R], p2[R], p3[R], fr[R];
-    Coef c[R];
+    CoefT c[R];
     tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), st.sigma, c,
                  fr);
 #pragma unroll
@@ -535,7 +573,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
     const int K = g.kg;
     const int lane = t.lane, wave = t.wave;
     float fr[R];
-    Coef c[R];
+    CoefT c[R];
     tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), st.sigma, c,
                  fr);
     float u1[R], Q1[R], Q2[R], Q3[R], UB[R], UH[R], GB[R], GF[R];
@@ -555,6 +593,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
                     Q1[r] = g_p[t.fld + k];
                     Q2[r] = g_p[t.fld + d.np + k];
                     Q3[r] = g_p[t.fld + 2 * d.np + k];
+                    if (st.rot)
+                        to_frame(make_basis(tx[t.img + k], ty[t.img + k]), Q1[r], Q2[r], Q3[r]);
                 }
                 if (g_u) UH[r] = g_u[t.img + k];
             } else {
@@ -610,13 +650,15 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const Coef& cc = c[r];
+            const CoefT& cc = c[r];
             const float ubr = lane_from_right(UB[r]);
             const float ubd = r < R - 1 ? UB[r + 1] : ub_bot;
             const float gx = ubr - UB[r], gy = ubd - UB[r];
-            float h1 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b12, gy, cc.a11 * gx), Q1[r]);
-            float h2 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b22, gy, cc.a21 * gx), Q2[r]);
-            float h3 = __builtin_fmaf(-st.ts, __builtin_fmaf(cc.b32, gy, cc.a31 * gx), Q3[r]);
+            float v1, v2;
+            ascent_dir(cc, gx, gy, v1, v2);
+            float h1 = __builtin_fmaf(-st.ts, v1, Q1[r]);
+            float h2 = __builtin_fmaf(-st.ts, v2, Q2[r]);
+            float h3 = Q3[r];
             const float utr = lane_from_right(ut[r]);
             const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
             float b1, b2, b3;
@@ -662,7 +704,8 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
             const float pxl = lane_from_left(qxp[r]);
             const float pyu = r > 0 ? qyp[r - 1] : qyp_top;
             float rr;
-            const float un = prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r], st.ts, rr);
+            const float un =
+                prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r].beta, c[r].c4, st.ts, rr);
             const bool active = un >= st.umin && un <= st.umax;
             const float hr = active ? H * rcp(rr) : 0.0f;
             const float ub = un * hr;
@@ -846,7 +889,7 @@ int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size
     if (bytes < x.cv.bytes) return REC_ENOMEM;
     x.dims = Dims{d->width, d->height, (size_t)d->width * d->height};
     x.st = Steps{d->tau, (float)(d->tau / d->sigma), (float)d->sigma, (float)d->u_min,
-                 (float)d->u_max};
+                 (float)d->u_max, d->iters > 0 ? 1 : 0};
     x.grid = grid_of(d);
     x.fs = fused_shape(d);
     return REC_OK;
@@ -925,7 +968,7 @@ int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u
     x.s = (hipStream_t)stream;
     (void)hipGetLastError();
     hipLaunchKernelGGL(k_diff_init, x.grid, dim3(kThreads), 0, x.s, x.dims, in->u0, in->p0,
-                       in->npos, in->nneg, in->theta, x.cv.f, x.cv.ck0);
+                       in->npos, in->nneg, in->theta, in->tx, in->ty, x.st.rot, x.cv.f, x.cv.ck0);
     const int C = segments(d), k = d->ckpt_every;
     const size_t sf = x.cv.state_floats;
     if (k == 1 && !d->unfused) {
@@ -949,7 +992,7 @@ int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u
         }
     }
     hipLaunchKernelGGL(k_diff_out, x.grid, dim3(kThreads), 0, x.s, x.dims,
-                       at(x.cv.ck0, x.cv.state_floats, C), u_out, p_out);
+                       at(x.cv.ck0, x.cv.state_floats, C), in->tx, in->ty, x.st.rot, u_out, p_out);
     return hipGetLastError() == hipSuccess ? REC_OK : REC_EDEVICE;
 }
 

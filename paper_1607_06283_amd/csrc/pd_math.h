@@ -246,17 +246,32 @@ __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_le
     return __builtin_amdgcn_fmed3f(un, umin, umax);
 }
 
-// Dual step in the frame: pbar' = p' + (sigma T g, 0), then the projection
-// onto the ball of radius s.
+// Dual ascent in the frame: pbar' = p' + (sigma T g, 0).
+__device__ __forceinline__ void dual_ascent(const CoefT& c, float gx, float gy, float p1, float p2,
+                                            float p3, float& b1, float& b2, float& b3) {
+    b1 = __builtin_fmaf(c.k11, gx, __builtin_fmaf(c.k12, gy, p1));
+    b2 = __builtin_fmaf(c.k22, gy, p2);
+    b3 = p3;
+}
+
+// sigma M (gx, gy) in frame coordinates (third component 0).
+__device__ __forceinline__ void ascent_dir(const CoefT& c, float gx, float gy, float& v1,
+                                           float& v2) {
+    v1 = __builtin_fmaf(c.k12, gy, c.k11 * gx);
+    v2 = c.k22 * gy;
+}
+
+// Dual step in the frame: the ascent, then the projection onto the ball of
+// radius s.
 __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
                                      const CoefT& c) {
-    const float b1 = __builtin_fmaf(c.k11, gx, __builtin_fmaf(c.k12, gy, p1));
-    const float b2 = __builtin_fmaf(c.k22, gy, p2);
-    const float n2 = __builtin_fmaf(p3, p3, __builtin_fmaf(b2, b2, b1 * b1));
+    float b1, b2, b3;
+    dual_ascent(c, gx, gy, p1, p2, p3, b1, b2, b3);
+    const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
     const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
     p1 = b1 * sc;
     p2 = b2 * sc;
-    p3 = p3 * sc;
+    p3 = b3 * sc;
 }
 
 }  // namespace rec
