@@ -751,8 +751,42 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     tb.pos = tb.neg = nullptr;
     tb.tmax = nullptr;
     tb.t_first = 0;
+    const bool col_in = gx >= 0 && gx < fr.W;
+    const bool col_out = col_in && col >= KG && col < CW - KG;
+    // First launch with few rows per lane: the pixel loads are issued
+    // between clearing the bins and scanning the events, so that their
+    // latency overlaps the event loads (with more rows the registers they
+    // hold would cost occupancy).
+    constexpr bool kEarly = B && R <= 2;
+    float eu[R], ea[R], eb[R], ed[R];
+    int64_t etl[R], etr[R], etd[R];
+    int32_t enp[R], enn[R];
+    if (events) bin_clear(RH, CW, dyn_lds, tb);
+    if constexpr (kEarly) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int gy = gy0 + r;
+            eu[r] = 1.0f;
+            ea[r] = eb[r] = ed[r] = 0.0f;
+            etl[r] = etr[r] = etd[r] = kNever;
+            enp[r] = enn[r] = 0;
+            if (col_in && gy >= 0 && gy < fr.H) {
+                const size_t k = (size_t)gy * fr.W + gx;
+                eu[r] = uin[k];
+                ea[r] = S::ld(pin, k);
+                eb[r] = S::ld(pin, np + k);
+                ed[r] = S::ld(pin, 2 * np + k);
+                etl[r] = P.t_last[k];
+                if (gx < fr.W - 1) etr[r] = P.t_last[k + 1];
+                if (gy < fr.H - 1) etd[r] = P.t_last[k + fr.W];
+                if (mode & kCounts) {
+                    enp[r] = P.npos[k];
+                    enn[r] = P.nneg[k];
+                }
+            }
+        }
+    }
     if (events) {
-        bin_clear(RH, CW, dyn_lds, tb);
         bin_scan(P, fr, segs, RH, CW, rx0, ry0, lead, tb);
     } else if (build) {
         tb.t_first = P.st->t_first;
@@ -766,8 +800,6 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
 
     float u[R], p1[R], p2[R], p3[R], txr[R], tyr[R];
     CoefT c[R];
-    const bool col_in = gx >= 0 && gx < fr.W;
-    const bool col_out = col_in && col >= KG && col < CW - KG;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
@@ -775,20 +807,36 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         float uu = 1.0f, a = 0.0f, b = 0.0f, d = 0.0f, f = 1.0f, tx = 0.0f, ty = 0.0f;
         if (in) {
             const size_t k = (size_t)gy * fr.W + gx;
-            uu = uin[k];
-            a = S::ld(pin, k);
-            b = S::ld(pin, np + k);
-            d = S::ld(pin, 2 * np + k);
+            if constexpr (kEarly) {
+                uu = eu[r];
+                a = ea[r];
+                b = eb[r];
+                d = ed[r];
+            } else {
+                uu = uin[k];
+                a = S::ld(pin, k);
+                b = S::ld(pin, np + k);
+                d = S::ld(pin, 2 * np + k);
+            }
             if (build) {
                 const int lr = v * R + r;
                 const bool hr = gx < fr.W - 1, hd = gy < fr.H - 1;
                 int32_t npos = 0, nneg = 0;
-                int64_t tl = P.t_last[k];
-                int64_t tr = hr ? P.t_last[k + 1] : kNever;
-                int64_t td = hd ? P.t_last[k + fr.W] : kNever;
-                if (mode & kCounts) {
-                    npos = P.npos[k];
-                    nneg = P.nneg[k];
+                int64_t tl, tr, td;
+                if constexpr (kEarly) {
+                    tl = etl[r];
+                    tr = etr[r];
+                    td = etd[r];
+                    npos = enp[r];
+                    nneg = enn[r];
+                } else {
+                    tl = P.t_last[k];
+                    tr = hr ? P.t_last[k + 1] : kNever;
+                    td = hd ? P.t_last[k + fr.W] : kNever;
+                    if (mode & kCounts) {
+                        npos = P.npos[k];
+                        nneg = P.nneg[k];
+                    }
                 }
                 if (events) {
                     npos += tb.pos[lr * CW + col];
