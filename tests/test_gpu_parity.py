@@ -185,6 +185,23 @@ def test_fused_equals_plain_bitwise(W, H):
         assert np.array_equal(pp, runs[0][1]), cfg
 
 
+@pytest.mark.parametrize("cfg", [dict(fuse_iters=-1), dict(fuse_iters=5, tile_rows=2, tile_waves=8,
+                                                              tile_cols=32)])
+def test_gap_samples_fused_equal_plain(c1, cfg):
+    """Gap samples taken between fused launches (p held in the tangent frame,
+    rotated back by the gap kernel) equal the two-kernel loop's bit for bit."""
+    hist = []
+    for kw in (dict(fuse_iters=0), cfg):
+        r = rec.Reconstructor(128, 128, gap_every=7, **kw)
+        for b in evgen.batches(c1.events, 500)[:3]:
+            r.push(b.t, b.x, b.y, b.p)
+            r.solve(30)
+        hist.append(r.gap_history())
+        r.close()
+    assert len(hist[0][0]) == 4
+    assert np.array_equal(hist[0][0], hist[1][0]) and np.array_equal(hist[0][1], hist[1][1])
+
+
 def test_repeat_run_deterministic(c1):
     outs = []
     for _ in range(2):
