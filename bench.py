@@ -39,9 +39,10 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 # copy: FETCH_SIZE read 131084 KiB and WRITE_SIZE 262144 KiB for 262144 KiB
 # moved each way, so fetched bytes = 2 x 1024 x FETCH_SIZE and written bytes
 # = 1024 x WRITE_SIZE.  Each entry holds for the kernel sources it was taken
-# with (hash of kernels.hip, pd_math.h, kernels.h, tile.h); after a change the bench
-# reports traffic null until the counters are taken again.
-TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h")
+# with (hash of kernels.hip, pd_math.h, kernels.h, tile.h, and rec_api.hip,
+# which picks the default tile); after a change the bench reports traffic
+# null until the counters are taken again.
+TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "rec_api.hip")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
     ("davis240", "f32"): ("807ce83846c1d83b", 2 * 1024 * 1073.2, 1024 * 820.7),

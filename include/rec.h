@@ -119,9 +119,9 @@ typedef struct {
                                   8x4 8x8) with 64 columns; set both or neither.  0, 0 =
                                   automatic by frame size (tile_cols 0 too): up to 60k
                                   pixels 1x16 of 32 columns, up to 120k 2x8 of 32 columns,
-                                  up to 400k 4x16, up to 600k 2x8 of 32 columns, larger 6x8
+                                  up to 400k 4x16, up to 600k 2x8 of 32 columns, larger 8x8
                                   (16-bit storage: 2x8 of 32 columns for the 32-column
-                                  cases, 4x8 for the largest frames) */
+                                  cases) */
     int32_t storage;         /* storage of the dual field p and of tx, ty: REC_STORE_F32
                                 (default), REC_STORE_BF16 or REC_STORE_F16; the arithmetic
                                 is FP32 in every case (16-bit forms need the fused loop) */

@@ -212,8 +212,10 @@ int flush_deferred(rec_ctx* c) {
 //                      2x16x64 K 13: 54, 51 G)
 //   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
 //   800x600:           2x8x32 K 8: 153 G (best 154 G)
-//   1280x720, 5120x5760: 6x8x64 K 6 (FP32): 279-292 G, 399-411 G; with
-//                      16-bit storage 4x8x64 K 6
+//   1280x720:          8x8x64 K 10: 308 G (6x8x64 K 6: 297 G, 8x8x64 K 8: 283 G)
+//   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G)
+//   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
+//                      (4x8x64 K 6: 284 G, 448 G)
 // `narrow` allows 32-column tiles (the batched launch has 64 only; it
 // takes 2x16 K 13 up to 250k pixels and the large-frame shape beyond).
 void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int* waves,
@@ -237,8 +239,10 @@ void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int
         ar = 4, aw = 16, acw = 64, k = 13;
     } else if (np <= 600000) {
         ar = 2, aw = 8, acw = 32, k = 8;
+    } else if (np <= 2000000) {
+        ar = 8, aw = 8, acw = 64, k = 10;
     } else {
-        ar = f32 ? 6 : 4, aw = 8, acw = 64, k = 6;
+        ar = 8, aw = 8, acw = 64, k = 8;
     }
     if (!rec::fused_shape_supported(ar, aw, acw, prm->storage)) {
         // 16-bit storage has 2x8 as its only 32-column tile
