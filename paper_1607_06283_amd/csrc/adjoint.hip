@@ -475,8 +475,8 @@ __device__ __forceinline__ void store_state(const Dims& d, const TileGrid& g, co
     }
 }
 
-// Metric constants of a tile's rows (pixels outside the image: zero M,
-// f = 1, as in the forward solve's tiles).
+// Metric constants of a tile's rows (pixels outside the image: zero
+// coefficients, f = 1, as in the forward solve's tiles).
 template <int R>
 __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, const float* f,
                                            const float* tx, const float* ty, const float* w,

@@ -6,9 +6,12 @@
 //   k_build         data image f, time differences tx/ty, reset counts
 //   k_finish        commit folded-event state / reset counts after a one-launch solve
 //   k_primal, k_dual    one primal-dual iteration as two plain kernels
+//   k_rotate        p into / out of each pixel's tangent frame (plain loop)
 //   k_pd_fused      several iterations per HBM round trip on a register tile;
-//                   its first launch of a solve can also bin the block's events
-//                   and build f, tx, ty
+//                   its first launch of a solve (an instantiation of its own)
+//                   can also bin the block's events and build f, tx, ty
+//   k_pd_fused_batch    the same over the tiles of many streams
+//   k_tvl1_*        timestamp denoising (FP64)
 //   k_gap, k_gap_final  primal-dual gap and energy (FP64 accumulation)
 //   k_time_plane, k_metric_plane   readback helpers
 #include <hip/hip_ext.h>

@@ -1,29 +1,40 @@
 // Per-pixel arithmetic of the primal-dual iteration on the event manifold.
 //
-// Every kernel that updates (u, p) -- the two-kernel loop and the fused
-// temporally-blocked loop -- calls these inline functions, so a pixel's
-// update is the same sequence of FP32 operations whichever kernel runs it
-// (the library is compiled with -ffp-contract=off and every fused
-// multiply-add below is explicit).
+// Every kernel that updates (u, p) -- the two-kernel loop, the fused
+// temporally-blocked loop and the differentiable solve -- calls these inline
+// functions, so a pixel's update is the same sequence of FP32 operations
+// whichever kernel runs it (the library is compiled with -ffp-contract=off
+// and every fused multiply-add below is explicit).
 //
 // Notation (Section 3.1-3.2 of the paper):
 //   tx, ty      forward differences of the time surface tau
 //   G           1 + tx^2 + ty^2 = det g;  s = sqrt(G)
 //   M           3x2 matrix of eqn. (3), L_g u = M (L_x u, L_y u):
 //               M = (1/G) [[1+ty^2, -tx ty], [-tx ty, 1+tx^2], [tx, ty]]
-//   C           sigma M: the stored coefficients carry the dual step size,
-//               so the dual ascent p + sigma M grad is two fused multiply-adds
-//               per component
-//   q           C^T p = sigma M^T p; the adjoint is L_g^* p = -div(M^T p), so
-//               the primal step u - tau L_g^* p is u + (tau / sigma) div q
 //   beta        tau * lambda * s            (KL prox, eqn. update_rules)
 //   c4          4 beta f
+//
+// The dual variable in a per-pixel orthonormal frame.  The columns of M span
+// the tangent plane of the surface (x, y, tau(x, y)): with a = sqrt(1 + ty^2),
+//   e1 = (1 + ty^2, -tx ty, tx) / (a s),  e2 = (0, 1, ty) / a,
+//   n  = (-tx, -ty, 1) / s              (unit normal)
+// form an orthonormal basis U = [e1 e2 n] and M = [e1 e2] T with the upper
+// triangular T = [[e1x, e1y], [0, e2y]] (e1x = a / s, e1y = -tx ty / (a s),
+// e2y = 1 / a).  Writing p = U p' (p' = U^T p):
+//   M^T p = T^T (p'1, p'2),   U^T (p + sigma M g) = p' + sigma (T g, 0),
+// and the projection onto the ball of radius s is the same in p' (U is
+// orthogonal).  So the iteration runs on p' with the three coefficients of
+// sigma T: q = sigma M^T p costs three operations, the dual ascent three.
+// The adjoint is L_g^* p = -div(M^T p), so the primal step u - tau L_g^* p
+// is u + (tau / sigma) div q.  A solve rotates p into the frame once at its
+// start and back at its end (the frame depends on the block's time surface
+// only).
 //
 // Boundary handling.  The forward differences vanish on the last column
 // (L_x) and the last row (L_y).  Since L_g u = M (L_x u, L_y u), a vanishing
 // L_x u is the same as a zero first column of M at that pixel, and the
 // adjoint's matching backward difference drops q_x there too; likewise for
-// the second column on the last row.  So the column of M that multiplies a
+// the second column on the last row.  So the column of T that multiplies a
 // difference leaving the image is stored as zero ("masked"), and pixels
 // outside the image carry zero coefficients.  The update formulas then need
 // no per-pixel boundary branches: the neighbour terms they read are exactly
@@ -33,13 +44,6 @@
 #include <hip/hip_runtime.h>
 
 namespace rec {
-
-struct Coef {
-    float a11, a21, a31;   // first column of sigma M (multiplies L_x), 0 if masked
-    float b12, b22, b32;   // second column of sigma M (multiplies L_y), 0 if masked
-    float s;               // sqrt(G): dual ball radius
-    float beta, c4;        // KL prox constants
-};
 
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -54,121 +58,7 @@ __device__ __forceinline__ float data_image(float u_prev, int npos, int nneg, do
     return (float)((double)u_prev * exp(e));
 }
 
-// Metric-dependent constants of one pixel (computed once per block of
-// iterations; they depend on the block's tau and f only).  sigma: the dual
-// step size folded into the coefficients.  has_x: the pixel has a right
-// neighbour inside the image (so L_x is a real difference); has_y: it has a
-// lower neighbour.
-__device__ __forceinline__ Coef make_coef(float tx, float ty, float f, float taulam, float sigma,
-                                          bool has_x, bool has_y) {
-    Coef c;
-    const float ax = __builtin_fmaf(tx, tx, 1.0f);  // 1 + tx^2
-    const float ay = __builtin_fmaf(ty, ty, 1.0f);  // 1 + ty^2
-    const float G = __builtin_fmaf(tx, tx, ay);     // 1 + tx^2 + ty^2
-    const float iG = sigma * rcp(G);
-    const float m12 = -(tx * ty) * iG;
-    const float m11 = ay * iG, m22 = ax * iG;
-    const float m31 = tx * iG, m32 = ty * iG;
-    c.a11 = has_x ? m11 : 0.0f;
-    c.a21 = has_x ? m12 : 0.0f;
-    c.a31 = has_x ? m31 : 0.0f;
-    c.b12 = has_y ? m12 : 0.0f;
-    c.b22 = has_y ? m22 : 0.0f;
-    c.b32 = has_y ? m32 : 0.0f;
-    c.s = sqrt_(G);
-    c.beta = taulam * c.s;
-    c.c4 = (4.0f * c.beta) * f;
-    return c;
-}
-
-// q = C^T p = sigma M^T p at one pixel (zero components where the column is
-// masked).
-__device__ __forceinline__ float q_x(const Coef& c, float p1, float p2, float p3) {
-    return __builtin_fmaf(c.a31, p3, __builtin_fmaf(c.a21, p2, c.a11 * p1));
-}
-__device__ __forceinline__ float q_y(const Coef& c, float p1, float p2, float p3) {
-    return __builtin_fmaf(c.b32, p3, __builtin_fmaf(c.b22, p2, c.b12 * p1));
-}
-
-// Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel, with
-// ubar = u + ts div q, ts = tau / sigma, and
-// div q = (q_x - q_x(left)) + (q_y - q_y(up)) (backward differences; the
-// neighbour values are 0 outside the image).  The KL prox uses the
-// cancellation-free form of the closed-form root: a = ubar - beta,
-// r = sqrt(a^2 + 4 beta f), d = r + |a|:  a >= 0: d / 2,  a < 0: 2 beta f / d
-// (d is r + a in the first case and r - a in the second, so neither branch
-// subtracts nearly equal numbers); then clamp to [umin, umax].
-// prox_root returns the unclamped root and r (the reverse sweep of the
-// unrolled loop needs both); primal clamps it.
-__device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
-                                           float beta, float c4, float ts, float& r) {
-    const float div = (qx - qx_left) + (qy - qy_up);
-    const float ubar = __builtin_fmaf(ts, div, u);
-    const float a = ubar - beta;
-    r = sqrt_(__builtin_fmaf(a, a, c4));
-    const float d = r + __builtin_fabsf(a);
-    const float pos = 0.5f * d;
-    const float neg = (0.5f * c4) * rcp(d);
-    return a >= 0.0f ? pos : neg;
-}
-__device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
-                                           const Coef& c, float ts, float& r) {
-    return prox_root(u, qx, qy, qx_left, qy_up, c.beta, c.c4, ts, r);
-}
-
-__device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
-                                        const Coef& c, float ts, float umin, float umax) {
-    float r;
-    const float un = prox_root(u, qx, qy, qx_left, qy_up, c, ts, r);
-    return __builtin_amdgcn_fmed3f(un, umin, umax);  // clamp (umin <= umax, un not NaN)
-}
-
-// Over-relaxed primal 2 u_{k+1} - u_k.
-__device__ __forceinline__ float extrapolate(float un, float u) {
-    return __builtin_fmaf(2.0f, un, -u);
-}
-
-// Dual ascent pbar = p + sigma M (gx, gy) = p + C (gx, gy) at one pixel, with
-// (gx, gy) the forward differences of the extrapolated primal (any finite
-// value where the column of C is masked).
-__device__ __forceinline__ void dual_ascent(const Coef& c, float gx, float gy, float p1, float p2,
-                                            float p3, float& b1, float& b2, float& b3) {
-    b1 = __builtin_fmaf(c.a11, gx, __builtin_fmaf(c.b12, gy, p1));
-    b2 = __builtin_fmaf(c.a21, gx, __builtin_fmaf(c.b22, gy, p2));
-    b3 = __builtin_fmaf(c.a31, gx, __builtin_fmaf(c.b32, gy, p3));
-}
-
-// Dual step p_{k+1} = prox_{sigma R^*}(pbar) at one pixel: the projection
-// onto the ball of radius s, p / max(1, |p| / s), computed as
-// p * min(1, s / |p|).
-__device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
-                                     const Coef& c) {
-    float b1, b2, b3;
-    dual_ascent(c, gx, gy, p1, p2, p3, b1, b2, b3);
-    const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
-    const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
-    p1 = b1 * sc;
-    p2 = b2 * sc;
-    p3 = b3 * sc;
-}
-
-// ------------------------------------------------------------------------
-// The same iteration with the dual variable in a per-pixel orthonormal frame.
-//
-// The columns of M span the tangent plane of the surface (x, y, tau(x, y)):
-// with a = sqrt(1 + ty^2) and s = sqrt(G),
-//   e1 = (1 + ty^2, -tx ty, tx) / (a s),  e2 = (0, 1, ty) / a,
-//   n  = (-tx, -ty, 1) / s              (unit normal)
-// form an orthonormal basis U = [e1 e2 n] and M = [e1 e2] T with the upper
-// triangular T = [[e1x, e1y], [0, e2y]] (e1x = a / s, e1y = -tx ty / (a s),
-// e2y = 1 / a).  Writing p = U p' (p' = U^T p):
-//   M^T p = T^T (p'1, p'2),   U^T (p + sigma M g) = p' + sigma (T g, 0),
-// and the projection onto the ball of radius s is the same in p' (U is
-// orthogonal).  So the iteration runs on p' with the three coefficients of
-// sigma T (a masked column of M masks the same column of T): q costs three
-// operations instead of six and the dual ascent three instead of six.  The
-// solve rotates p into the frame once at its start and back at its end (the
-// frame depends on the block's time surface only).
+// The frame of one pixel.
 struct Basis {
     float e1x, e1y, e1z;  // e1
     float e2y, e2z;       // e2 (e2x = 0)
@@ -194,6 +84,10 @@ __device__ __forceinline__ Basis make_basis(float tx, float ty) {
     return b;
 }
 
+// Metric-dependent constants of one pixel (computed once per launch; they
+// depend on the block's tau and f only).  sigma: the dual step size folded
+// into the coefficients.  has_x: the pixel has a right neighbour inside the
+// image (so L_x is a real difference); has_y: it has a lower neighbour.
 struct CoefT {
     float k11;      // sigma T11, 0 if the first column is masked
     float k12, k22; // sigma T12, sigma T22, 0 if the second column is masked
@@ -231,7 +125,8 @@ __device__ __forceinline__ void from_frame(const Basis& b, float& p1, float& p2,
     p3 = z;
 }
 
-// q = sigma M^T p from the frame coordinates p' (p'3 does not enter).
+// q = sigma M^T p from the frame coordinates p' (p'3 does not enter; zero
+// components where the column is masked).
 __device__ __forceinline__ float q_x(const CoefT& c, float p1, float, float) {
     return c.k11 * p1;
 }
@@ -239,14 +134,43 @@ __device__ __forceinline__ float q_y(const CoefT& c, float p1, float p2, float) 
     return __builtin_fmaf(c.k22, p2, c.k12 * p1);
 }
 
+// Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel, with
+// ubar = u + ts div q, ts = tau / sigma, and
+// div q = (q_x - q_x(left)) + (q_y - q_y(up)) (backward differences; the
+// neighbour values are 0 outside the image).  The KL prox uses the
+// cancellation-free form of the closed-form root: a = ubar - beta,
+// r = sqrt(a^2 + 4 beta f), d = r + |a|:  a >= 0: d / 2,  a < 0: 2 beta f / d
+// (d is r + a in the first case and r - a in the second, so neither branch
+// subtracts nearly equal numbers); then clamp to [umin, umax].
+// prox_root returns the unclamped root and r (the reverse sweep of the
+// unrolled loop needs both); primal clamps it.
+__device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
+                                           float beta, float c4, float ts, float& r) {
+    const float div = (qx - qx_left) + (qy - qy_up);
+    const float ubar = __builtin_fmaf(ts, div, u);
+    const float a = ubar - beta;
+    r = sqrt_(__builtin_fmaf(a, a, c4));
+    const float d = r + __builtin_fabsf(a);
+    const float pos = 0.5f * d;
+    const float neg = (0.5f * c4) * rcp(d);
+    return a >= 0.0f ? pos : neg;
+}
+
 __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
                                         const CoefT& c, float ts, float umin, float umax) {
     float r;
     const float un = prox_root(u, qx, qy, qx_left, qy_up, c.beta, c.c4, ts, r);
-    return __builtin_amdgcn_fmed3f(un, umin, umax);
+    return __builtin_amdgcn_fmed3f(un, umin, umax);  // clamp (umin <= umax, un not NaN)
 }
 
-// Dual ascent in the frame: pbar' = p' + (sigma T g, 0).
+// Over-relaxed primal 2 u_{k+1} - u_k.
+__device__ __forceinline__ float extrapolate(float un, float u) {
+    return __builtin_fmaf(2.0f, un, -u);
+}
+
+// Dual ascent in the frame: pbar' = p' + (sigma T g, 0), with (gx, gy) the
+// forward differences of the extrapolated primal (any finite value where
+// the column of T is masked).
 __device__ __forceinline__ void dual_ascent(const CoefT& c, float gx, float gy, float p1, float p2,
                                             float p3, float& b1, float& b2, float& b3) {
     b1 = __builtin_fmaf(c.k11, gx, __builtin_fmaf(c.k12, gy, p1));
@@ -261,8 +185,9 @@ __device__ __forceinline__ void ascent_dir(const CoefT& c, float gx, float gy, f
     v2 = c.k22 * gy;
 }
 
-// Dual step in the frame: the ascent, then the projection onto the ball of
-// radius s.
+// Dual step p_{k+1} = prox_{sigma R^*}(pbar) in the frame: the ascent, then
+// the projection onto the ball of radius s, p / max(1, |p| / s), computed as
+// p * min(1, s / |p|).
 __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, float gy,
                                      const CoefT& c) {
     float b1, b2, b3;

@@ -65,9 +65,9 @@ __device__ __forceinline__ void tile_skip() {
     }
 }
 
-// One primal-dual iteration of a tile held in registers (u, p, metric
-// constants c per row: Coef with p in the standard basis, CoefT with p in
-// the per-pixel tangent frame; ts = tau / sigma) with NV lane rows of CW lanes;
+// One primal-dual iteration of a tile held in registers (u, p in frame
+// coordinates, metric constants c per row; ts = tau / sigma) with NV lane
+// rows of CW lanes;
 // `col` is the lane's column and `v` its lane row.  Rows that cross lane
 // rows go through LDS: xq[v + 1] receives lane row v's last q_y row and
 // xu[v] its first extrapolated row (NV + 1 rows of CW floats each); xq[0]
@@ -76,9 +76,9 @@ __device__ __forceinline__ void tile_skip() {
 // The rows whose neighbours are in the lane's own registers are updated
 // before each barrier, so that only one row's update waits for the
 // exchange (the result does not depend on this order).
-template <int R, int NV, int CW = 64, class C = Coef>
+template <int R, int NV, int CW = 64>
 __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
-                                               float (&p3)[R], const C (&c)[R], float ts,
+                                               float (&p3)[R], const CoefT (&c)[R], float ts,
                                                float umin, float umax, int col, int v,
                                                float (*xq)[CW], float (*xu)[CW]) {
     float qx[R], qy[R];
