@@ -90,6 +90,29 @@ def test_time_planes_bit_exact(c1, ts):
         assert np.array_equal(r.image(rec.REC_TIME), o.get(oracle.TAU32))
 
 
+@pytest.mark.parametrize("iters", [1, 2, 9, 10, 19])
+def test_short_solves(c1, iters):
+    """Solves of a few iterations: a single launch that rotates p into each
+    pixel's frame and back (iters up to the iterations per launch) or a short
+    split, with device pushes folded into the first launch; against the
+    two-kernel loop bit for bit and against the oracle."""
+    r, o = make(128, 128)
+    rp = rec.Reconstructor(128, 128, fuse_iters=0)
+    for b in evgen.batches(c1.events, 500)[:4]:
+        r.push(*device_events(b), on_device=True)
+        rp.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(iters)
+        rp.solve(iters)
+        o.solve(iters)
+        u = r.image(rec.REC_U)
+        assert np.array_equal(u, rp.image(rec.REC_U))
+        assert np.array_equal(r.image(rec.REC_STATE_P), rp.image(rec.REC_STATE_P))
+        assert np.abs(u.astype(np.float64) - o.u).max() <= U_TOL
+    r.close()
+    rp.close()
+
+
 def test_large_push_path_bit_exact(c1):
     """Pushes above the single-workgroup size use the multi-kernel path."""
     r, o = make(128, 128)
