@@ -135,8 +135,12 @@ hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool
                         hipStream_t s, LaunchEv ev = {});
 // Timestamp denoising: `iters` TV-L1 iterations on the surface, then tx, ty
 // (in the given storage) from the denoised surface.
+// Timestamp denoising; with folded pushes (segs.count > 0, only up to
+// kTvl1FusedMax iterations) the launch bins the block's events itself.
+constexpr int kTvl1FusedMax = 14;
+int tvl1_tiles(Frame fr, int iters);  // tiles of the one-launch form, -1 beyond it
 hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
-                       int storage, hipStream_t s, LaunchEv ev = {});
+                       int storage, const EventSegs& segs, hipStream_t s, LaunchEv ev = {});
 hipError_t launch_finish(const Planes& P, Frame fr, bool zero_counts, hipStream_t s,
                          LaunchEv ev = {});
 // The two-kernel loop iterates on frame coordinates of p: launch_rotate

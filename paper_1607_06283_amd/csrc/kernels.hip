@@ -286,6 +286,161 @@ __global__ void k_widen(const void* src, float* out, size_t n) {
     if (k < n) out[k] = S::ld((const typename S::T*)src, k);
 }
 
+// ---------------------------------------------------------------- event binning
+
+// Folded events of the first launch, binned for one tile region (LDS).
+struct ScanState {
+    unsigned long long seg_bad[kMaxSegs];  // first event failing its own checks, per push
+    int seg_ok[kMaxSegs];                  // push accepted
+    int all_ok;                            // every push accepted
+    long long t_first;                     // stream's first timestamp after the pushes
+    long long t_ref;                       // latest accepted timestamp after the pushes
+};
+
+struct TileBins {
+    ScanState* ss;
+    int64_t t_ref;    // latest accepted timestamp after the pushes
+    int32_t* pos;     // RH x CW counts
+    int32_t* neg;
+    long long* tmax;  // (RH + 1) x (CW + 1) latest timestamps (one extra column and row)
+    int64_t t_first;  // stream's first timestamp after this block's events
+};
+
+// Binning of the folded pushes of a solve's first launch, for the tile
+// region [rx0, rx0 + CW] x [ry0, ry0 + RH], in two calls:
+//  bin_clear  lays out and zeroes the LDS bins;
+//  bin_scan   validates the pushes in order (each all-or-nothing, with the
+//             same error codes as a scattered push) and bins the accepted
+//             events.
+// The scan reads every event once: it bins each event while checking it and
+// only when a push turns out to be rejected (rare) clears the bins and bins
+// the accepted pushes again.  The caller issues its per-pixel loads between
+// the two calls, so their latency overlaps the event loads.  Every
+// workgroup takes the same decisions; the lead workgroup records the
+// outcome as pending state.
+__device__ void bin_clear(int RH, int CW, unsigned char* lds, TileBins& tb) {
+    __shared__ ScanState ss;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid < kMaxSegs) ss.seg_bad[tid] = (unsigned long long)kNoBad;
+    tb.ss = &ss;
+    tb.pos = (int32_t*)lds;
+    tb.neg = tb.pos + RH * CW;
+    tb.tmax = (long long*)(tb.neg + RH * CW);
+    for (int q = tid; q < RH * CW; q += nt) {
+        tb.pos[q] = 0;
+        tb.neg[q] = 0;
+    }
+    for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void bin_one(const EventSegs& segs, int s, int64_t i, int RH, int CW,
+                                        int rx0, int ry0, TileBins& tb) {
+    const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
+    if (lc < 0 || lc > CW || lr < 0 || lr > RH) return;
+    atomicMax(&tb.tmax[lr * (CW + 1) + lc], (long long)segs.t[s][i]);
+    if (lc < CW && lr < RH)
+        atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * CW + lc] : &tb.neg[lr * CW + lc], 1);
+}
+
+__device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int RH, int CW,
+                         int rx0, int ry0, bool lead, TileBins& tb) {
+    ScanState& ss = *tb.ss;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    DevState* st = P.st;
+    // what the in-order decisions below need for the first push (nearly
+    // always the only one), loaded by thread 0 ahead of the event pass so
+    // that the loads overlap it
+    int32_t started = 0;
+    int64_t st_ref = 0, st_first = 0, st_events = 0, t0 = 0, tn = 0;
+    uint16_t x0 = 0, y0 = 0;
+    int8_t p0 = 0;
+    if (tid == 0) {
+        started = st->started;
+        st_ref = st->t_ref;
+        st_first = st->t_first;
+        st_events = st->batch_events;
+        if (segs.count > 0) {
+            t0 = segs.t[0][0];
+            tn = segs.t[0][segs.n[0] - 1];
+            x0 = segs.x[0][0];
+            y0 = segs.y[0][0];
+            p0 = segs.p[0][0];
+        }
+    }
+    // per-event checks (each push's first event is checked against the
+    // running reference time in sequence below), binning as we go
+    for (int s = 0; s < segs.count; ++s) {
+        const int64_t* t = segs.t[s];
+        for (int64_t i = tid; i < segs.n[s]; i += nt) {
+            const int64_t prev = i ? t[i - 1] : INT64_MIN;
+            if (event_error(t[i], prev, segs.x[s][i], segs.y[s][i], segs.p[s][i], fr.W, fr.H))
+                atomicMin(&ss.seg_bad[s], (unsigned long long)i);
+            else
+                bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
+        }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int64_t ref = started ? st_ref : INT64_MIN;
+        int64_t first = kNever, last = 0, accepted = 0;
+        int32_t err = 0;
+        int ok_all = 1;
+        for (int s = 0; s < segs.count; ++s) {
+            const int64_t* t = segs.t[s];
+            const int64_t ts0 = s == 0 ? t0 : t[0];
+            const int64_t fb = (int64_t)ss.seg_bad[s];
+            int32_t code = 0;
+            if (fb == 0)
+                code = s == 0 ? event_error(t0, INT64_MIN, x0, y0, p0, fr.W, fr.H)
+                              : event_error(t[0], INT64_MIN, segs.x[s][0], segs.y[s][0],
+                                            segs.p[s][0], fr.W, fr.H);
+            else if (ts0 < ref)
+                code = kErrOrder;
+            else if (fb != kNoBad)
+                code = event_error(segs.t[s][fb], segs.t[s][fb - 1], segs.x[s][fb],
+                                   segs.y[s][fb], segs.p[s][fb], fr.W, fr.H);
+            ss.seg_ok[s] = code == 0;
+            if (code == 0) {
+                if (first == kNever) first = ts0;
+                ref = s == 0 ? tn : t[segs.n[s] - 1];
+                last = ref;
+                accepted += segs.n[s];
+            } else {
+                ok_all = 0;
+                if (err == 0) err = code;
+            }
+        }
+        ss.all_ok = ok_all;
+        ss.t_first = started ? st_first : (first == kNever ? 0 : first);
+        ss.t_ref = accepted > 0 ? last : st_ref;
+        if (lead) {
+            st->pend_t_ref = last;
+            st->pend_t_first = first;
+            st->pend_accepted = accepted > 0;
+            st->pend_events = st_events + accepted;
+            st->pend_err = err;
+        }
+    }
+    __syncthreads();
+    if (!ss.all_ok) {
+        // a rejected push: bin the accepted pushes again from clear bins
+        for (int q = tid; q < RH * CW; q += nt) {
+            tb.pos[q] = 0;
+            tb.neg[q] = 0;
+        }
+        for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
+        __syncthreads();
+        for (int s = 0; s < segs.count; ++s) {
+            if (!ss.seg_ok[s]) continue;
+            for (int64_t i = tid; i < segs.n[s]; i += nt) bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
+        }
+        __syncthreads();
+    }
+    tb.t_first = ss.t_first;
+    tb.t_ref = ss.t_ref;
+}
+
 // ---------------------------------------------------------------- timestamp denoising
 
 // Section 4 denoises the timestamps with a few TV-L1 iterations before the
@@ -362,7 +517,10 @@ __global__ void k_tvl1_finish(Planes P, Frame fr, int cur) {
 // iters + 1 pixels runs every iteration in registers (neighbours through DPP
 // and LDS, as in the primal-dual tile) and writes tx, ty of its interior.
 // Each pixel's arithmetic and its order are those of the kernels above.
-constexpr int kTvl1FusedMax = 14;
+// With folded pushes (segs.count > 0) the tile first validates and bins the
+// block's events like the primal-dual build launch does (without recording
+// any state: that launch bins them again and commits), so the surface it
+// denoises already holds the block's latest timestamps.
 
 __device__ __forceinline__ double lane_from_left_d(double v) {
     return __hiloint2double(__float_as_int(lane_from_left(__int_as_float(__double2hiint(v)))),
@@ -375,18 +533,30 @@ __device__ __forceinline__ double lane_from_right_d(double v) {
 
 template <class S>
 __global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double ts, int iters,
-                                                     double lambda, int tiles_x, int ntiles) {
+                                                     double lambda, EventSegs segs, int tiles_x,
+                                                     int ntiles) {
+    extern __shared__ unsigned char dyn_lds[];
     constexpr int R = 2, NW = 16, RH = R * NW;
     const int KH = iters + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tile = xcd_tile(blockIdx.x, ntiles);
     const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
-    const int gx = txi * (64 - 2 * KH) - KH + lane;
-    const int gy0 = tyi * (RH - 2 * KH) - KH + wave * R;
+    const int rx0 = txi * (64 - 2 * KH) - KH, ry0 = tyi * (RH - 2 * KH) - KH;
+    const int gx = rx0 + lane;
+    const int gy0 = ry0 + wave * R;
     const bool col_in = gx >= 0 && gx < fr.W;
     const bool hx = gx < fr.W - 1, lx = gx > 0;
     const DevState* st = P.st;
-    const int64_t t_ref = st->t_ref, t_first = st->t_first;
+    int64_t t_ref = st->t_ref, t_first = st->t_first;
+    const bool events = segs.count > 0;
+    TileBins tb;
+    tb.tmax = nullptr;
+    if (events) {
+        bin_clear(RH, 64, dyn_lds, tb);
+        bin_scan(P, fr, segs, RH, 64, rx0, ry0, false, tb);
+        t_ref = tb.t_ref;
+        t_first = tb.t_first;
+    }
     const double s = 0.35355339059327373;  // 1 / sqrt(8)
     const double tl = s * lambda;
     double v0[R], v[R], q1[R], q2[R];
@@ -394,8 +564,11 @@ __global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double 
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
         v0[r] = 0.0;
-        if (col_in && gy >= 0 && gy < fr.H)
-            v0[r] = (double)(t_ref - resolved_last(P.t_last[(size_t)gy * fr.W + gx], t_first)) / ts;
+        if (col_in && gy >= 0 && gy < fr.H) {
+            int64_t tl = P.t_last[(size_t)gy * fr.W + gx];
+            if (events) tl = max(tl, (int64_t)tb.tmax[(wave * R + r) * 65 + lane]);
+            v0[r] = (double)(t_ref - resolved_last(tl, t_first)) / ts;
+        }
         v[r] = v0[r];
         q1[r] = 0.0;
         q2[r] = 0.0;
@@ -541,155 +714,6 @@ __global__ __launch_bounds__(256) void k_rotate(Planes P, Frame fr, int cur, int
 }
 
 // ---------------------------------------------------------------- fused loop
-
-// Folded events of the first launch, binned for one tile region (LDS).
-struct ScanState {
-    unsigned long long seg_bad[kMaxSegs];  // first event failing its own checks, per push
-    int seg_ok[kMaxSegs];                  // push accepted
-    int all_ok;                            // every push accepted
-    long long t_first;
-};
-
-struct TileBins {
-    ScanState* ss;
-    int32_t* pos;     // RH x CW counts
-    int32_t* neg;
-    long long* tmax;  // (RH + 1) x (CW + 1) latest timestamps (one extra column and row)
-    int64_t t_first;  // stream's first timestamp after this block's events
-};
-
-// Binning of the folded pushes of a solve's first launch, for the tile
-// region [rx0, rx0 + CW] x [ry0, ry0 + RH], in two calls:
-//  bin_clear  lays out and zeroes the LDS bins;
-//  bin_scan   validates the pushes in order (each all-or-nothing, with the
-//             same error codes as a scattered push) and bins the accepted
-//             events.
-// The scan reads every event once: it bins each event while checking it and
-// only when a push turns out to be rejected (rare) clears the bins and bins
-// the accepted pushes again.  The caller issues its per-pixel loads between
-// the two calls, so their latency overlaps the event loads.  Every
-// workgroup takes the same decisions; the lead workgroup records the
-// outcome as pending state.
-__device__ void bin_clear(int RH, int CW, unsigned char* lds, TileBins& tb) {
-    __shared__ ScanState ss;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    if (tid < kMaxSegs) ss.seg_bad[tid] = (unsigned long long)kNoBad;
-    tb.ss = &ss;
-    tb.pos = (int32_t*)lds;
-    tb.neg = tb.pos + RH * CW;
-    tb.tmax = (long long*)(tb.neg + RH * CW);
-    for (int q = tid; q < RH * CW; q += nt) {
-        tb.pos[q] = 0;
-        tb.neg[q] = 0;
-    }
-    for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
-    __syncthreads();
-}
-
-__device__ __forceinline__ void bin_one(const EventSegs& segs, int s, int64_t i, int RH, int CW,
-                                        int rx0, int ry0, TileBins& tb) {
-    const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
-    if (lc < 0 || lc > CW || lr < 0 || lr > RH) return;
-    atomicMax(&tb.tmax[lr * (CW + 1) + lc], (long long)segs.t[s][i]);
-    if (lc < CW && lr < RH)
-        atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * CW + lc] : &tb.neg[lr * CW + lc], 1);
-}
-
-__device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int RH, int CW,
-                         int rx0, int ry0, bool lead, TileBins& tb) {
-    ScanState& ss = *tb.ss;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    DevState* st = P.st;
-    // what the in-order decisions below need for the first push (nearly
-    // always the only one), loaded by thread 0 ahead of the event pass so
-    // that the loads overlap it
-    int32_t started = 0;
-    int64_t st_ref = 0, st_first = 0, st_events = 0, t0 = 0, tn = 0;
-    uint16_t x0 = 0, y0 = 0;
-    int8_t p0 = 0;
-    if (tid == 0) {
-        started = st->started;
-        st_ref = st->t_ref;
-        st_first = st->t_first;
-        st_events = st->batch_events;
-        if (segs.count > 0) {
-            t0 = segs.t[0][0];
-            tn = segs.t[0][segs.n[0] - 1];
-            x0 = segs.x[0][0];
-            y0 = segs.y[0][0];
-            p0 = segs.p[0][0];
-        }
-    }
-    // per-event checks (each push's first event is checked against the
-    // running reference time in sequence below), binning as we go
-    for (int s = 0; s < segs.count; ++s) {
-        const int64_t* t = segs.t[s];
-        for (int64_t i = tid; i < segs.n[s]; i += nt) {
-            const int64_t prev = i ? t[i - 1] : INT64_MIN;
-            if (event_error(t[i], prev, segs.x[s][i], segs.y[s][i], segs.p[s][i], fr.W, fr.H))
-                atomicMin(&ss.seg_bad[s], (unsigned long long)i);
-            else
-                bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
-        }
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int64_t ref = started ? st_ref : INT64_MIN;
-        int64_t first = kNever, last = 0, accepted = 0;
-        int32_t err = 0;
-        int ok_all = 1;
-        for (int s = 0; s < segs.count; ++s) {
-            const int64_t* t = segs.t[s];
-            const int64_t ts0 = s == 0 ? t0 : t[0];
-            const int64_t fb = (int64_t)ss.seg_bad[s];
-            int32_t code = 0;
-            if (fb == 0)
-                code = s == 0 ? event_error(t0, INT64_MIN, x0, y0, p0, fr.W, fr.H)
-                              : event_error(t[0], INT64_MIN, segs.x[s][0], segs.y[s][0],
-                                            segs.p[s][0], fr.W, fr.H);
-            else if (ts0 < ref)
-                code = kErrOrder;
-            else if (fb != kNoBad)
-                code = event_error(segs.t[s][fb], segs.t[s][fb - 1], segs.x[s][fb],
-                                   segs.y[s][fb], segs.p[s][fb], fr.W, fr.H);
-            ss.seg_ok[s] = code == 0;
-            if (code == 0) {
-                if (first == kNever) first = ts0;
-                ref = s == 0 ? tn : t[segs.n[s] - 1];
-                last = ref;
-                accepted += segs.n[s];
-            } else {
-                ok_all = 0;
-                if (err == 0) err = code;
-            }
-        }
-        ss.all_ok = ok_all;
-        ss.t_first = started ? st_first : (first == kNever ? 0 : first);
-        if (lead) {
-            st->pend_t_ref = last;
-            st->pend_t_first = first;
-            st->pend_accepted = accepted > 0;
-            st->pend_events = st_events + accepted;
-            st->pend_err = err;
-        }
-    }
-    __syncthreads();
-    if (!ss.all_ok) {
-        // a rejected push: bin the accepted pushes again from clear bins
-        for (int q = tid; q < RH * CW; q += nt) {
-            tb.pos[q] = 0;
-            tb.neg[q] = 0;
-        }
-        for (int q = tid; q < (RH + 1) * (CW + 1); q += nt) tb.tmax[q] = kNever;
-        __syncthreads();
-        for (int s = 0; s < segs.count; ++s) {
-            if (!ss.seg_ok[s]) continue;
-            for (int64_t i = tid; i < segs.n[s]; i += nt) bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
-        }
-        __syncthreads();
-    }
-    tb.t_first = ss.t_first;
-}
 
 // K primal-dual iterations per launch on a register tile.  A workgroup of
 // NW wavefronts forms NV = NW * 64 / CW lane rows of CW lanes (CW = 64 or
@@ -1193,24 +1217,31 @@ hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool
                   cur, bc, time_mem ? 1 : 0);
 }
 
+int tvl1_tiles(Frame fr, int iters) {
+    if (iters > kTvl1FusedMax) return -1;
+    const int kh = iters + 1;
+    return ((fr.W + 64 - 2 * kh - 1) / (64 - 2 * kh)) * ((fr.H + 32 - 2 * kh - 1) / (32 - 2 * kh));
+}
+
 hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
-                       int storage, hipStream_t s, LaunchEv ev) {
+                       int storage, const EventSegs& segs, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     if (iters <= kTvl1FusedMax) {
         const int kh = iters + 1;
         const int tiles_x = (fr.W + 64 - 2 * kh - 1) / (64 - 2 * kh);
-        const int tiles_y = (fr.H + 32 - 2 * kh - 1) / (32 - 2 * kh);
-        const int nt = tiles_x * tiles_y;
+        const int nt = tvl1_tiles(fr, iters);
         const dim3 gt(nt), bt(1024);
+        const size_t lds = segs.count > 0 ? fused_lds_bytes(2, 16, 64, kEvents) : 0;
         if (storage == kStoreF16)
-            return launch(k_tvl1_fused<StoreF16>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts, iters,
-                          lambda, tiles_x, nt);
+            return launch(k_tvl1_fused<StoreF16>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts,
+                          iters, lambda, segs, tiles_x, nt);
         if (storage == kStoreBF16)
-            return launch(k_tvl1_fused<StoreBF16>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts,
-                          iters, lambda, tiles_x, nt);
-        return launch(k_tvl1_fused<StoreF32>, gt, bt, 0, s, ev.start, ev.stop, P, fr, ts, iters,
-                      lambda, tiles_x, nt);
+            return launch(k_tvl1_fused<StoreBF16>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts,
+                          iters, lambda, segs, tiles_x, nt);
+        return launch(k_tvl1_fused<StoreF32>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts, iters,
+                      lambda, segs, tiles_x, nt);
     }
+    if (segs.count > 0) return hipErrorInvalidValue;  // pushes must be scattered first
     const dim3 g(blocks_for(np, 256)), b(256);
     hipError_t e = launch(k_tvl1_init, g, b, 0, s, ev.start, nullptr, P, fr, ts);
     int cur = 0;

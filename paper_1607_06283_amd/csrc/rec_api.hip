@@ -7,6 +7,7 @@
 //     primal-dual launch of the next solve validates and bins them itself
 //     (up to kMaxSegs pushes and kFoldMaxEvents events; beyond that, and for
 //     host-pointer pushes, the events are scattered by their own kernels);
+//     with timestamp denoising the one-launch denoiser bins them too;
 //   - the solve's first fused launch builds f, tx, ty and iterates; the
 //     next launches iterate; the second one commits the stream state (or a
 //     small finishing kernel does, when the solve has one launch).
@@ -489,11 +490,15 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
     rec::EventSegs segs;
     memset(&segs, 0, sizeof(segs));
     bool fold = false;
-    if (fused && !denoise && !c->deferred.empty()) {
+    // with denoising the one-launch denoiser bins the pushes as well (it
+    // needs the block's timestamps before the metric is built)
+    const int64_t dn_tiles =
+        denoise ? rec::tvl1_tiles(c->fr, c->prm.tvl1_iters) : 0;
+    if (fused && dn_tiles >= 0 && !c->deferred.empty()) {
         const int first_k = iters < c->kmax ? iters : c->kmax;
         const int64_t tiles = rec::fused_tiles(c->fr, c->rows, c->waves, c->cols, first_k);
         fold = c->deferred_events <= kFoldMaxEvents && tiles > 0 &&
-               c->deferred_events * tiles <= kFoldMaxWork;
+               c->deferred_events * (tiles > dn_tiles ? tiles : dn_tiles) <= kFoldMaxWork;
     }
     if (fold) {
         for (size_t s = 0; s < c->deferred.size(); ++s) {
@@ -511,10 +516,11 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
         if (rc) return rc;
     }
     if (denoise) {
-        // the denoised surface needs every timestamp of the block first
+        // the denoised surface needs every timestamp of the block first:
+        // scattered above, or binned by the denoising launch itself
         rc = timed(c, 1, np, [&](rec::LaunchEv ev) {
             return rec::launch_tvl1(c->P, c->fr, c->prm.time_unit_us, c->prm.tvl1_iters,
-                                    c->prm.tvl1_lambda, c->prm.storage, c->stream, ev);
+                                    c->prm.tvl1_lambda, c->prm.storage, segs, c->stream, ev);
         });
         if (rc) return rc;
     }

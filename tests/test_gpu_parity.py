@@ -626,16 +626,21 @@ def test_denoised_time_differences_and_image(noisy, fuse):
         assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
 
 
+@pytest.mark.parametrize("on_device", [False, True])
 @pytest.mark.parametrize("iters", [1, 5, 14, 15, 20])
-def test_denoised_time_differences_exact(noisy, iters):
+def test_denoised_time_differences_exact(noisy, iters, on_device):
     """Up to 14 iterations the denoising runs as one tiled launch, beyond as
     one launch per half-step; both repeat the oracle's FP64 operations in
-    order, so the rounded time differences equal the oracle's bit for bit."""
+    order, so the rounded time differences equal the oracle's bit for bit.
+    Device pushes are binned by the one-launch denoiser itself."""
     r, o = make(96, 72, tvl1_iters=iters, tvl1_lambda=1.0)
     n = len(noisy)
     for a in range(0, n - n % 2, n // 2):
         b = noisy.slice(a, a + n // 2)
-        r.push(b.t, b.x, b.y, b.p)
+        if on_device:
+            r.push(*device_events(b), on_device=True)
+        else:
+            r.push(b.t, b.x, b.y, b.p)
         o.push_events(b)
         r.solve(3)
         o.solve(3)
