@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
     const float py = q_y(c, p[o], p[d.np + o], p[2 * d.np + o]);
     float r;
     const float un = prox_root(a.u[o], px, py, qx_left(d, i, j, o, tx, ty, p, d.np, st.sigma),
-                               qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma), c.beta, c.c4, st.ts,
+                               qy_up(d, i, j, o, tx, ty, p, d.np, st.sigma), c.hb, c.bf, st.ts,
                                r);
     const bool active = un >= st.umin && un <= st.umax;
     const float hr = active ? H * rcp(r) : 0.0f;
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_primal(Dims d, State a,
     A.ub[o] = ub_hat;
     A.uh[o] = ub_hat - ut_hat;
     A.gbeta[o] += (fo - un) * hr;
-    A.gf[o] += c.beta * hr;
+    A.gf[o] += prox_beta(c) * hr;
 }
 
 __global__ __launch_bounds__(kThreads) void k_adj_zero(Dims d, Adj A) {
@@ -532,7 +532,7 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
     if (t.wave == 0) xq[0][t.lane] = 0.0f;
     if (t.wave == NW - 1) xu[NW][t.lane] = 0.0f;
     for (int it = 0; it < K; ++it) {
-        tile_iteration<R, NW>(u, p1, p2, p3, c, st.ts, st.umin, st.umax, t.lane, t.wave, xq,
+        tile_iteration<R, NW>(u, u, p1, p2, p3, c, st.ts, st.umin, st.umax, t.lane, t.wave, xq,
                               xu);
         if (rec.u && it < K - 1)
             store_state<R, NW>(d, g, t, rec.u + it * rec.stride, rec.p + it * rec.stride, u, p1,
@@ -705,14 +705,14 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
             const float pyu = r > 0 ? qyp[r - 1] : qyp_top;
             float rr;
             const float un =
-                prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r].beta, c[r].c4, st.ts, rr);
+                prox_root(u0[r], qxp[r], qyp[r], pxl, pyu, c[r].hb, c[r].bf, st.ts, rr);
             const bool active = un >= st.umin && un <= st.umax;
             const float hr = active ? H * rcp(rr) : 0.0f;
             const float ub = un * hr;
             UB[r] = ub;
             UH[r] = ub - ut_hat;
             GB[r] += (fr[r] - un) * hr;
-            GF[r] += c[r].beta * hr;
+            GF[r] += prox_beta(c[r]) * hr;
             u1[r] = u0[r];
         }
     }

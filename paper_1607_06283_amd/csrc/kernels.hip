@@ -923,28 +923,37 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         if (v == NV - 1) xu[NV][col] = 0.0f;
     }
 
-    // With few rows per lane the loop runs two iterations per trip, so that
-    // the rotation of u between iterations needs no register copies (with 8
-    // or more rows the register pressure undoes the gain).  With 2 rows per
-    // lane (many wavefronts) a wavefront skips the iterations that cannot
-    // reach the exact interior (about a third of them at K = 13).
+    // With few rows per lane the loop runs two iterations per trip, with u
+    // alternating between two register sets, so that passing u from one
+    // iteration to the next needs no register copies (with 8 or more rows
+    // the register pressure undoes the gain).  With 2 rows per lane (many
+    // wavefronts) a wavefront skips the iterations that cannot reach the
+    // exact interior (about a third of them at K = 13).
     constexpr bool kSkip = R <= 2 && NW > 1;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
-    auto step = [&](int it1) {
-        if (!kSkip || tile_rows_active<R * (64 / CW), NW>(wv, it1))
-            tile_iteration<R, NV, CW>(u, p1, p2, p3, c, kc.ts, kc.umin, kc.umax, col, v, xq,
+    // med3 takes one scalar operand (umin): umax is held in a vector
+    // register once, instead of being copied into one every iteration.
+    float umax = kc.umax;
+    asm volatile("" : "+v"(umax));
+    auto step = [&](int it1, float (&ui)[R], float (&uo)[R]) {
+        if (!kSkip || tile_rows_active<R * (64 / CW), NW>(wv, it1)) {
+            tile_iteration<R, NV, CW>(ui, uo, p1, p2, p3, c, kc.ts, kc.umin, umax, col, v, xq,
                                       xu);
-        else
+        } else {
             tile_skip<NW>();
+#pragma unroll
+            for (int r = 0; r < R; ++r) uo[r] = ui[r];
+        }
     };
     int it = 0;
     if constexpr (R <= 6) {
+        float ub[R];
         for (; it + 1 < K; it += 2) {
-            step(it + 1);
-            step(it + 2);
+            step(it + 1, u, ub);
+            step(it + 2, ub, u);
         }
     }
-    for (; it < K; ++it) step(it + 1);
+    for (; it < K; ++it) step(it + 1, u, u);
 
     float* __restrict__ uout = P.u[cur ^ 1];
     typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];

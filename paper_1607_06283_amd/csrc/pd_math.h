@@ -12,7 +12,6 @@
 //   M           3x2 matrix of eqn. (3), L_g u = M (L_x u, L_y u):
 //               M = (1/G) [[1+ty^2, -tx ty], [-tx ty, 1+tx^2], [tx, ty]]
 //   beta        tau * lambda * s            (KL prox, eqn. update_rules)
-//   c4          4 beta f
 //
 // The dual variable in a per-pixel orthonormal frame.  The columns of M span
 // the tangent plane of the surface (x, y, tau(x, y)): with a = sqrt(1 + ty^2),
@@ -92,8 +91,11 @@ struct CoefT {
     float k11;      // sigma T11, 0 if the first column is masked
     float k12, k22; // sigma T12, sigma T22, 0 if the second column is masked
     float s;        // ball radius sqrt(G)
-    float beta, c4; // KL prox constants
+    float hb, bf;   // KL prox constants beta / 2 and beta f
 };
+
+// beta itself (exact: hb is beta / 2).
+__device__ __forceinline__ float prox_beta(const CoefT& c) { return 2.0f * c.hb; }
 
 __device__ __forceinline__ CoefT make_coef_t(const Basis& b, float f, float taulam, float sigma,
                                              bool has_x, bool has_y) {
@@ -102,8 +104,9 @@ __device__ __forceinline__ CoefT make_coef_t(const Basis& b, float f, float taul
     c.k12 = has_y ? sigma * b.e1y : 0.0f;
     c.k22 = has_y ? sigma * b.e2y : 0.0f;
     c.s = b.s;
-    c.beta = taulam * b.s;
-    c.c4 = (4.0f * c.beta) * f;
+    const float beta = taulam * b.s;
+    c.hb = 0.5f * beta;
+    c.bf = beta * f;
     return c;
 }
 
@@ -137,29 +140,31 @@ __device__ __forceinline__ float q_y(const CoefT& c, float p1, float p2, float) 
 // Primal step u_{k+1} = prox_{tau D}(u_k - tau L_g^* p_k) at one pixel, with
 // ubar = u + ts div q, ts = tau / sigma, and
 // div q = (q_x - q_x(left)) + (q_y - q_y(up)) (backward differences; the
-// neighbour values are 0 outside the image).  The KL prox uses the
-// cancellation-free form of the closed-form root: a = ubar - beta,
-// r = sqrt(a^2 + 4 beta f), d = r + |a|:  a >= 0: d / 2,  a < 0: 2 beta f / d
-// (d is r + a in the first case and r - a in the second, so neither branch
-// subtracts nearly equal numbers); then clamp to [umin, umax].
+// neighbour values are 0 outside the image).  The KL prox is the positive
+// root of u^2 - a u - beta f = 0, a = ubar - beta, in the cancellation-free
+// form: with r = sqrt(a^2 + 4 beta f) and d = r + |a|, the root is d / 2 for
+// a >= 0 and 2 beta f / d for a < 0 (d is r + a in the first case and r - a
+// in the second, so neither branch subtracts nearly equal numbers); then it
+// is clamped to [umin, umax].  Everything is evaluated at half scale,
+// h = a / 2 = (u + (ts div - beta)) / 2, r / 2 = sqrt(h^2 + beta f),
+// d / 2 = r / 2 + |h|: the root is d / 2 itself, or beta f / (d / 2), so no
+// halving is left in the loop.
 // prox_root returns the unclamped root and r (the reverse sweep of the
 // unrolled loop needs both); primal clamps it.
 __device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
-                                           float beta, float c4, float ts, float& r) {
+                                           float hb, float bf, float ts, float& r) {
     const float div = (qx - qx_left) + (qy - qy_up);
-    const float ubar = __builtin_fmaf(ts, div, u);
-    const float a = ubar - beta;
-    r = sqrt_(__builtin_fmaf(a, a, c4));
-    const float d = r + __builtin_fabsf(a);
-    const float pos = 0.5f * d;
-    const float neg = (0.5f * c4) * rcp(d);
-    return a >= 0.0f ? pos : neg;
+    const float h = __builtin_fmaf(0.5f, u, __builtin_fmaf(0.5f * ts, div, -hb));
+    const float rh = sqrt_(__builtin_fmaf(h, h, bf));
+    const float dh = rh + __builtin_fabsf(h);
+    r = 2.0f * rh;
+    return h >= 0.0f ? dh : bf * rcp(dh);
 }
 
 __device__ __forceinline__ float primal(float u, float qx, float qy, float qx_left, float qy_up,
                                         const CoefT& c, float ts, float umin, float umax) {
     float r;
-    const float un = prox_root(u, qx, qy, qx_left, qy_up, c.beta, c.c4, ts, r);
+    const float un = prox_root(u, qx, qy, qx_left, qy_up, c.hb, c.bf, ts, r);
     return __builtin_amdgcn_fmed3f(un, umin, umax);  // clamp (umin <= umax, un not NaN)
 }
 

@@ -67,7 +67,7 @@ __device__ __forceinline__ void tile_skip() {
 
 // One primal-dual iteration of a tile held in registers (u, p in frame
 // coordinates, metric constants c per row; ts = tau / sigma) with NV lane
-// rows of CW lanes;
+// rows of CW lanes; the new u goes to uo (which may be u itself);
 // `col` is the lane's column and `v` its lane row.  Rows that cross lane
 // rows go through LDS: xq[v + 1] receives lane row v's last q_y row and
 // xu[v] its first extrapolated row (NV + 1 rows of CW floats each); xq[0]
@@ -77,8 +77,9 @@ __device__ __forceinline__ void tile_skip() {
 // before each barrier, so that only one row's update waits for the
 // exchange (the result does not depend on this order).
 template <int R, int NV, int CW = 64>
-__device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], float (&p2)[R],
-                                               float (&p3)[R], const CoefT (&c)[R], float ts,
+__device__ __forceinline__ void tile_iteration(float (&u)[R], float (&uo)[R], float (&p1)[R],
+                                               float (&p2)[R], float (&p3)[R],
+                                               const CoefT (&c)[R], float ts,
                                                float umin, float umax, int col, int v,
                                                float (*xq)[CW], float (*xu)[CW]) {
     float qx[R], qy[R];
@@ -106,7 +107,7 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
 #pragma unroll
     for (int r = 0; r < R - 1; ++r) {
         dual(p1[r], p2[r], p3[r], lane_from_right(ut[r]) - ut[r], ut[r + 1] - ut[r], c[r]);
-        u[r] = un[r];
+        uo[r] = un[r];
         settle(p1[r]);
         settle(p2[r]);
         settle(p3[r]);
@@ -118,7 +119,7 @@ __device__ __forceinline__ void tile_iteration(float (&u)[R], float (&p1)[R], fl
     }
     dual(p1[R - 1], p2[R - 1], p3[R - 1], lane_from_right(ut[R - 1]) - ut[R - 1],
          ut_bot - ut[R - 1], c[R - 1]);
-    u[R - 1] = un[R - 1];
+    uo[R - 1] = un[R - 1];
 }
 
 }  // namespace rec
