@@ -935,19 +935,22 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     // register once, instead of being copied into one every iteration.
     float umax = kc.umax;
     asm volatile("" : "+v"(umax));
+    // A skipped wavefront leaves uo as it was: it stays skipped for the rest
+    // of the launch (the exact region only shrinks), its rows lie outside
+    // the stored interior, and its registers feed no other row, so the stale
+    // (finite) values are never used.
     auto step = [&](int it1, float (&ui)[R], float (&uo)[R]) {
-        if (!kSkip || tile_rows_active<R * (64 / CW), NW>(wv, it1)) {
+        if (!kSkip || tile_rows_active<R * (64 / CW), NW>(wv, it1))
             tile_iteration<R, NV, CW>(ui, uo, p1, p2, p3, c, kc.ts, kc.umin, umax, col, v, xq,
                                       xu);
-        } else {
+        else
             tile_skip<NW>();
-#pragma unroll
-            for (int r = 0; r < R; ++r) uo[r] = ui[r];
-        }
     };
     int it = 0;
     if constexpr (R <= 6) {
         float ub[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ub[r] = u[r];
         for (; it + 1 < K; it += 2) {
             step(it + 1, u, ub);
             step(it + 2, ub, u);
