@@ -513,9 +513,11 @@ __global__ void k_tvl1_finish(Planes P, Frame fr, int cur) {
 }
 
 // The same denoising in one launch for up to kTvl1FusedMax iterations: a
-// 64 x 32 register tile (2 rows per lane, 16 wavefronts) with a halo of
+// 64 x 16R register tile (R rows per lane, 16 wavefronts) with a halo of
 // iters + 1 pixels runs every iteration in registers (neighbours through DPP
 // and LDS, as in the primal-dual tile) and writes tx, ty of its interior.
+// R = 1 spreads a small frame over more compute units (the FP64 iteration
+// is bound by each unit's arithmetic), R = 2 wastes less on halos.
 // Each pixel's arithmetic and its order are those of the kernels above.
 // With folded pushes (segs.count > 0) the tile first validates and bins the
 // block's events like the primal-dual build launch does (without recording
@@ -531,12 +533,12 @@ __device__ __forceinline__ double lane_from_right_d(double v) {
                             __float_as_int(lane_from_right(__int_as_float(__double2loint(v)))));
 }
 
-template <class S>
+template <class S, int R>
 __global__ __launch_bounds__(1024) void k_tvl1_fused(Planes P, Frame fr, double ts, int iters,
                                                      double lambda, EventSegs segs, int tiles_x,
                                                      int ntiles) {
     extern __shared__ unsigned char dyn_lds[];
-    constexpr int R = 2, NW = 16, RH = R * NW;
+    constexpr int NW = 16, RH = R * NW;
     const int KH = iters + 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int tile = xcd_tile(blockIdx.x, ntiles);
@@ -1229,29 +1231,57 @@ hipError_t launch_build(const Planes& P, Frame fr, int cur, BuildConsts bc, bool
                   cur, bc, time_mem ? 1 : 0);
 }
 
+namespace {
+// Tiles of the one-launch denoiser with R rows per lane (64 x 16R pixels,
+// halo iters + 1), or -1 if the halo leaves no interior.
+int tvl1_tiles_r(Frame fr, int iters, int R) {
+    const int kh = iters + 1, ow = 64 - 2 * kh, oh = 16 * R - 2 * kh;
+    if (ow <= 0 || oh <= 0) return -1;
+    return ((fr.W + ow - 1) / ow) * ((fr.H + oh - 1) / oh);
+}
+
+// One row per lane when those tiles fit on the compute units at once (one
+// 1024-lane workgroup each; MI355X has 256), else two.
+constexpr int kTvl1OneRowTiles = 256;
+int tvl1_rows(Frame fr, int iters) {
+    const int n1 = tvl1_tiles_r(fr, iters, 1);
+    return n1 > 0 && n1 <= kTvl1OneRowTiles ? 1 : 2;
+}
+}  // namespace
+
 int tvl1_tiles(Frame fr, int iters) {
     if (iters > kTvl1FusedMax) return -1;
-    const int kh = iters + 1;
-    return ((fr.W + 64 - 2 * kh - 1) / (64 - 2 * kh)) * ((fr.H + 32 - 2 * kh - 1) / (32 - 2 * kh));
+    return tvl1_tiles_r(fr, iters, tvl1_rows(fr, iters));
 }
 
 hipError_t launch_tvl1(const Planes& P, Frame fr, double ts, int iters, double lambda,
                        int storage, const EventSegs& segs, hipStream_t s, LaunchEv ev) {
     const size_t np = (size_t)fr.W * fr.H;
     if (iters <= kTvl1FusedMax) {
-        const int kh = iters + 1;
+        const int kh = iters + 1, R = tvl1_rows(fr, iters);
         const int tiles_x = (fr.W + 64 - 2 * kh - 1) / (64 - 2 * kh);
         const int nt = tvl1_tiles(fr, iters);
+        if (nt <= 0) return hipErrorInvalidValue;
         const dim3 gt(nt), bt(1024);
-        const size_t lds = segs.count > 0 ? fused_lds_bytes(2, 16, 64, kEvents) : 0;
+        const size_t lds = segs.count > 0 ? fused_lds_bytes(R, 16, 64, kEvents) : 0;
+        if (R == 1) {
+            if (storage == kStoreF16)
+                return launch(k_tvl1_fused<StoreF16, 1>, gt, bt, lds, s, ev.start, ev.stop, P,
+                              fr, ts, iters, lambda, segs, tiles_x, nt);
+            if (storage == kStoreBF16)
+                return launch(k_tvl1_fused<StoreBF16, 1>, gt, bt, lds, s, ev.start, ev.stop, P,
+                              fr, ts, iters, lambda, segs, tiles_x, nt);
+            return launch(k_tvl1_fused<StoreF32, 1>, gt, bt, lds, s, ev.start, ev.stop, P, fr,
+                          ts, iters, lambda, segs, tiles_x, nt);
+        }
         if (storage == kStoreF16)
-            return launch(k_tvl1_fused<StoreF16>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts,
-                          iters, lambda, segs, tiles_x, nt);
+            return launch(k_tvl1_fused<StoreF16, 2>, gt, bt, lds, s, ev.start, ev.stop, P, fr,
+                          ts, iters, lambda, segs, tiles_x, nt);
         if (storage == kStoreBF16)
-            return launch(k_tvl1_fused<StoreBF16>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts,
-                          iters, lambda, segs, tiles_x, nt);
-        return launch(k_tvl1_fused<StoreF32>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts, iters,
-                      lambda, segs, tiles_x, nt);
+            return launch(k_tvl1_fused<StoreBF16, 2>, gt, bt, lds, s, ev.start, ev.stop, P, fr,
+                          ts, iters, lambda, segs, tiles_x, nt);
+        return launch(k_tvl1_fused<StoreF32, 2>, gt, bt, lds, s, ev.start, ev.stop, P, fr, ts,
+                      iters, lambda, segs, tiles_x, nt);
     }
     if (segs.count > 0) return hipErrorInvalidValue;  // pushes must be scattered first
     const dim3 g(blocks_for(np, 256)), b(256);

@@ -651,6 +651,28 @@ def test_denoised_time_differences_exact(noisy, iters, on_device):
     r.close()
 
 
+@pytest.mark.parametrize("W,H", [(320, 240), (40, 30)])
+def test_denoised_time_differences_exact_tile_heights(W, H):
+    """The one-launch denoiser takes one row per lane (64 x 16 tiles) when
+    those tiles fit on the compute units at once and two rows otherwise:
+    320 x 240 at 5 iterations needs 420 one-row tiles (so two rows run),
+    40 x 30 a handful.  Both equal the oracle bit for bit."""
+    spec = evgen.StreamSpec(W, H, 23, duration_us=20_000, speed_px_s=400.0, omega_rad_s=3.0,
+                            noise_frac=0.05)
+    ev = evgen.generate(spec).events
+    r, o = make(W, H, tvl1_iters=5, tvl1_lambda=1.0)
+    n = len(ev)
+    for a in range(0, n - n % 2, n // 2):
+        b = ev.slice(a, a + n // 2)
+        r.push(*device_events(b), on_device=True)
+        o.push_events(b)
+        r.solve(3)
+        o.solve(3)
+        for which, plane in ((rec.REC_TX, oracle.TX32), (rec.REC_TY, oracle.TY32)):
+            assert np.array_equal(r.image(which), o.get(plane))
+    r.close()
+
+
 def test_denoising_flattens_noise_spikes(noisy):
     """Uniform noise events put isolated, out-of-sequence timestamps into the
     surface; the denoised surface has far fewer large time differences."""
