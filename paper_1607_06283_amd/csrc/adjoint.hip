@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_dual(Dims d, State a, State b_
     const float gy = i < d.H - 1 ? extrapolate(b_.u[o + d.W], a.u[o + d.W]) - ut : 0.0f;
     float b1, b2, b3;
     dual_ascent(c, gx, gy, a.p[q], a.p[q + d.np], a.p[q + 2 * d.np], b1, b2, b3);
-    const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
+    const float n2 = norm2(b1, b2, b3);
     const float sc = c.s * rsq(n2);
     if (sc < 1.0f) {  // the forward projected this point (same test as its min)
         const float t = __builtin_fmaf(b3, h3, __builtin_fmaf(b2, h2, b1 * h1)) * rcp(n2);
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
             const float utd = r < R - 1 ? ut[r + 1] : ut_bot;
             float b1, b2, b3;
             dual_ascent(cc, utr - ut[r], utd - ut[r], pa[r], pb[r], pc[r], b1, b2, b3);
-            const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
+            const float n2 = norm2(b1, b2, b3);
             const float sc = cc.s * rsq(n2);
             if (sc < 1.0f) {
                 const float tt = __builtin_fmaf(b3, h3, __builtin_fmaf(b2, h2, b1 * h1)) * rcp(n2);

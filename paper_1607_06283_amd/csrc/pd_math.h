@@ -153,8 +153,10 @@ __device__ __forceinline__ float q_y(const CoefT& c, float p1, float p2, float) 
 // unrolled loop needs both); primal clamps it.
 __device__ __forceinline__ float prox_root(float u, float qx, float qy, float qx_left, float qy_up,
                                            float hb, float bf, float ts, float& r) {
-    const float div = (qx - qx_left) + (qy - qy_up);
-    const float h = __builtin_fmaf(0.5f, u, __builtin_fmaf(0.5f * ts, div, -hb));
+    // (operands ordered so that the values that arrive last -- the upper
+    // neighbour's q_y from another lane row, then div -- enter last)
+    const float div = ((qx - qx_left) + qy) - qy_up;
+    const float h = __builtin_fmaf(0.5f * ts, div, __builtin_fmaf(0.5f, u, -hb));
     const float rh = sqrt_(__builtin_fmaf(h, h, bf));
     const float dh = rh + __builtin_fabsf(h);
     r = 2.0f * rh;
@@ -178,9 +180,14 @@ __device__ __forceinline__ float extrapolate(float un, float u) {
 // the column of T is masked).
 __device__ __forceinline__ void dual_ascent(const CoefT& c, float gx, float gy, float p1, float p2,
                                             float p3, float& b1, float& b2, float& b3) {
-    b1 = __builtin_fmaf(c.k11, gx, __builtin_fmaf(c.k12, gy, p1));
+    b1 = __builtin_fmaf(c.k12, gy, __builtin_fmaf(c.k11, gx, p1));  // gy (lower row) last
     b2 = __builtin_fmaf(c.k22, gy, p2);
     b3 = p3;
+}
+
+// |b|^2 with the terms that do not wait for b1 formed first.
+__device__ __forceinline__ float norm2(float b1, float b2, float b3) {
+    return __builtin_fmaf(b1, b1, __builtin_fmaf(b2, b2, b3 * b3));
 }
 
 // sigma M (gx, gy) in frame coordinates (third component 0).
@@ -197,7 +204,7 @@ __device__ __forceinline__ void dual(float& p1, float& p2, float& p3, float gx, 
                                      const CoefT& c) {
     float b1, b2, b3;
     dual_ascent(c, gx, gy, p1, p2, p3, b1, b2, b3);
-    const float n2 = __builtin_fmaf(b3, b3, __builtin_fmaf(b2, b2, b1 * b1));
+    const float n2 = norm2(b1, b2, b3);
     const float sc = __builtin_fminf(1.0f, c.s * rsq(n2));
     p1 = b1 * sc;
     p2 = b2 * sc;
