@@ -187,6 +187,9 @@ def test_fused_equals_plain_bitwise(W, H):
             dict(fuse_iters=6, tile_rows=6, tile_waves=8), dict(fuse_iters=7, tile_rows=5, tile_waves=8),
             dict(fuse_iters=9, tile_rows=3, tile_waves=16), dict(fuse_iters=6, tile_rows=4, tile_waves=8),
             dict(fuse_iters=0, gap_every=7),
+            # the automatic shapes of larger frames (64 x 64 tiles)
+            dict(fuse_iters=10, tile_rows=8, tile_waves=8),
+            dict(fuse_iters=13, tile_rows=4, tile_waves=16),
             # 32-column tiles (two lane rows per wavefront)
             dict(fuse_iters=8, tile_rows=2, tile_waves=8, tile_cols=32),
             dict(fuse_iters=15, tile_rows=1, tile_waves=16, tile_cols=32),
