@@ -218,3 +218,14 @@ def test_diff_rejects_without_touching_device():
     g = rec.rec_diff_grads(None, None, None, None)
     assert rec.rec_diff_backward(d, inp, None, None, g, 0x10000, n - 1, None) == rec.REC_ENOMEM
     assert rec.rec_diff_backward(d, inp, None, None, g, None, n, None) == rec.REC_EINVAL
+
+
+def test_missing_library_fails_loudly(monkeypatch):
+    """Without the built library every entry raises: there is no CPU path to
+    fall back to."""
+    monkeypatch.setattr(rec, "_lib", None)
+    monkeypatch.setattr(rec, "LIB_PATH", "/nonexistent/librec.so")
+    with pytest.raises(RuntimeError, match="missing"):
+        rec.load()
+    with pytest.raises(RuntimeError, match="missing"):
+        rec.rec_default_params(64, 64)
