@@ -181,27 +181,11 @@ def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_B
     return dt, prof, u
 
 
-STREAM_SIZES = [(128, 128), (240, 180), (346, 260), (640, 480)]
-
-
 def streams64(steps, seed=400):
     """Per-camera (W, H, block size, events) for the 64-camera workload."""
     import evgen
 
-    cams = []
-    for i in range(64):
-        rng = np.random.default_rng(seed + i)
-        W, H = STREAM_SIZES[i // 16]
-        rate = float(np.exp(rng.uniform(np.log(1e5), np.log(5e6))))
-        bs = int(round(np.exp(rng.uniform(np.log(200), np.log(5000)))))
-        n = bs * steps
-        dt = rng.exponential(1e6 / rate, n)
-        t = evgen.T0_US + np.floor(np.cumsum(dt)).astype(np.int64)
-        x = rng.integers(0, W, n).astype(np.uint16)
-        y = rng.integers(0, H, n).astype(np.uint16)
-        p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
-        cams.append((W, H, bs, evgen.Events(t, x, y, p, np.zeros(n, np.uint8))))
-    return cams
+    return evgen.streams64(steps, seed)
 
 
 def run_streams64(steps, warmup, iters, batched, profile, tune=True):
@@ -254,10 +238,29 @@ def run_streams64(steps, warmup, iters, batched, profile, tune=True):
     return dt, prof, cfg, px, ev_per_step
 
 
-def cpu_baseline(ev, budget_s=10.0, W=W_, H=H_, batch=EVENTS_PER_BATCH, iters=ITERS):
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_threads() -> int:
+    """Threads the OpenMP oracle build runs with (OMP_NUM_THREADS, else all cores)."""
+    try:
+        return int(os.environ.get("OMP_NUM_THREADS", "")) or os.cpu_count() or 1
+    except ValueError:
+        return os.cpu_count() or 1
+
+
+def _oracle_rate(ev, budget_s, W, H, batch, iters, threads):
     import oracle
 
-    o = oracle.Oracle(oracle.Params(W, H))
+    o = oracle.Oracle(oracle.Params(W, H), threads=threads)
     n = 0
     t0 = time.perf_counter()
     while True:
@@ -268,11 +271,59 @@ def cpu_baseline(ev, budget_s=10.0, W=W_, H=H_, batch=EVENTS_PER_BATCH, iters=IT
         el = time.perf_counter() - t0
         if el >= budget_s or (n + 1) * batch > len(ev):
             break
+    o.close()
+    return n, el
+
+
+def cpu_baseline(ev, budget_s=8.0, W=W_, H=H_, batch=EVENTS_PER_BATCH, iters=ITERS):
+    """The FP64 C oracle on the first blocks of the same stream: its OpenMP
+    build on all host cores (the reported value) and the single-threaded
+    build beside it, each for about budget_s seconds."""
+    cores = oracle_threads()
+    n, el = _oracle_rate(ev, budget_s, W, H, batch, iters, threads=True)
+    n1, el1 = _oracle_rate(ev, budget_s, W, H, batch, iters, threads=False)
     rate = n * iters * W * H / el / 1e6
-    return {"value": round(rate, 3), "unit": "PD iter*Mpix/s", "cores": 1, "kind": "oracle",
+    rate1 = n1 * iters * W * H / el1 / 1e6
+    return {"value": round(rate, 3), "unit": "PD iter*Mpix/s", "cores": cores, "kind": "oracle",
             "sample": f"first {n} blocks of the same stream ({n * batch} events, "
-                      f"{n * iters} iterations of {W}x{H}) in {el:.1f} s, FP64 C, one thread",
-            "events_per_s": round(n * batch / el, 1)}
+                      f"{n * iters} iterations of {W}x{H}) in {el:.1f} s, FP64 C, OpenMP over "
+                      f"pixels on {cores} threads",
+            "events_per_s": round(n * batch / el, 1),
+            "host_cpu": host_cpu_model(), "host_logical_cpus": os.cpu_count(),
+            "single_thread": {"value": round(rate1, 3), "events_per_s": round(n1 * batch / el1, 1),
+                              "sample": f"first {n1} blocks in {el1:.1f} s"}}
+
+
+def oracle_c1_and_c5():
+    """The oracle (all host cores) on the 128x128 workload in full (20 blocks
+    of 500 events, 50 iterations) and on the forward of the differentiation
+    workload (16 x 346x260, 100 iterations from u0 = exp(L_gt(t0)))."""
+    import evgen
+    import oracle
+
+    out = {}
+    s, bs, nb, iters = evgen.dvs128(seed=1, n_batches=20)
+    o = oracle.Oracle(oracle.Params(128, 128), threads=True)
+    t0 = time.perf_counter()
+    for b in evgen.batches(s.events, bs)[:nb]:
+        o.push_events(b)
+        o.solve(iters)
+    el = time.perf_counter() - t0
+    o.close()
+    out["dvs128_full"] = {"s": round(el, 3), "PD iter*Mpix/s": round(nb * iters * 128 * 128 / el / 1e6, 2),
+                          "events_per_s": round(nb * bs / el, 1), "ms_per_image": round(el / nb * 1e3, 3)}
+    blocks = evgen.diff_blocks(500, 16, 346, 260, 2000)
+    t0 = time.perf_counter()
+    for spec, blk, L0, _ in blocks:
+        o = oracle.Oracle(oracle.Params(346, 260), u0=np.exp(L0).astype(np.float32).astype(np.float64),
+                          threads=True)
+        o.push_events(blk)
+        o.solve(100)
+        o.close()
+    el = time.perf_counter() - t0
+    out["diff16_forward"] = {"s": round(el, 3),
+                             "PD iter*Mpix/s": round(16 * 100 * 346 * 260 / el / 1e6, 2)}
+    return out
 
 
 def copy_probe(mib=256, reps=5):
@@ -305,13 +356,6 @@ def main_streams64(args):
     log("bench: 64 cameras, one solve per camera")
     dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
     value = steps * IT * px / dt / 1e6
-    achieved = BYTES_PER_PX_ITER * prof.pd_pixel_iters / (prof.ms[2] * 1e-3) / 1e9
-    avg_us = prof.ms[2] / prof.launches[2] * 1e3
-    traffic, tb = None, None
-    m = MEASURED_TRAFFIC.get(("streams64", "f32"))
-    if m and tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE and m[0] == kernel_source_hash():
-        tb = m[1] + m[2]
-        traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": round(dt / steps * 1e3, 4),
@@ -325,12 +369,8 @@ def main_streams64(args):
         "per_camera_solves": {"value": round(steps * IT * px / dt_solo / 1e6, 2),
                               "ms_per_step": round(dt_solo / steps * 1e3, 4)},
         "batched_speedup": round(dt_solo / dt, 3),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_pd_fused_batch",
-                     "avg_launch_us": round(avg_us, 3),
-                     "launches": int(prof.launches[2]), "bytes_per_px_iter": BYTES_PER_PX_ITER,
-                     "hbm_bytes_per_launch": None if tb is None else round(tb)},
+        "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused_batch", ("streams64", "f32"),
+                             tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE),
     }
     print(json.dumps(out), flush=True)
 
@@ -479,6 +519,9 @@ def main():
                     help="TV-L1 timestamp-denoising iterations before each block's metric")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="davis240: skip the 128x128, 64-camera and probe sections and the "
+                         "oracle's 128x128 / differentiation-forward timings")
     ap.add_argument("--no-tune", action="store_true",
                     help="streams64: keep the default tile geometry instead of autotuning")
     ap.add_argument("--copy-probe", action="store_true",
@@ -537,33 +580,141 @@ def main():
     if not args.no_profile:
         log("bench: per-kernel timing pass")
         _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True, **kw)
-        pd_ms = prof.ms[2]
-        pd_launches = int(prof.launches[2])
         bpi = BYTES_PER_PX_ITER if storage == 0 else BYTES_PER_PX_ITER_16
-        achieved = bpi * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
-        avg_us = pd_ms / pd_launches * 1e3
-        traffic, tb = None, None
-        m = MEASURED_TRAFFIC.get((args.workload, args.storage))
-        if m and args.fuse == -1 and not args.rows and not args.tvl1 and m[0] == kernel_source_hash():
-            tb = m[1] + m[2]
-            traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
-        out["roofline"] = {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "kernel": "k_pd_fused" if args.fuse else "k_primal+k_dual",
-            "avg_launch_us": round(avg_us, 3),
-            "launches": pd_launches,
-            "bytes_per_px_iter": bpi,
-            "algorithmic_bytes_per_launch": round(bpi * prof.pd_pixel_iters / pd_launches),
-            "hbm_bytes_per_launch": None if tb is None else round(tb),
-        }
+        eligible = args.fuse == -1 and not args.rows and not args.tvl1
+        out["roofline"] = roofline(prof, bpi, "k_pd_fused" if args.fuse else "k_primal+k_dual",
+                                   (args.workload, args.storage) if eligible else None)
         out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),
-                            "pd": round(pd_ms, 3)}
+                            "pd": round(prof.ms[2], 3)}
+    if args.workload == "davis240" and args.storage == "f32" and not (
+            args.rows or args.tvl1 or args.fuse != -1 or args.no_extras):
+        # the other configurations, each on its own clock, beside the headline
+        log("bench: 128x128 blocks of 500 events (latency and throughput)")
+        out["dvs128"] = bench_dvs128()
+        log("bench: 64 cameras, batched")
+        out["streams64"] = bench_streams64()
+        log("bench: 5120x5760 probe")
+        out["probe"] = bench_probe()
     # the oracle beside the GPU on the frames whose blocks it finishes in seconds
     if not args.no_cpu and args.workload in ("davis240", "hd720"):
-        log("bench: oracle baseline")
+        log("bench: oracle baseline (all host cores, then one thread)")
         out["cpu_baseline"] = cpu_baseline(ev, W=W, H=H, batch=B, iters=IT)
+        if args.workload == "davis240" and not args.no_extras:
+            out["cpu_baseline"].update(oracle_c1_and_c5())
     print(json.dumps(out), flush=True)
+
+
+def roofline(prof, bpi, kernel, traffic_key=None, shape_ok=True):
+    """Roofline object of the primal-dual launches timed in `prof`:
+    achieved = algorithmic bytes (bpi per pixel-iteration) / kernel time;
+    traffic = the HBM bytes per launch measured by the counters for this
+    workload and these sources (None when not measured or stale)."""
+    pd_ms = prof.ms[2]
+    launches = int(prof.launches[2])
+    achieved = bpi * prof.pd_pixel_iters / (pd_ms * 1e-3) / 1e9
+    avg_us = pd_ms / launches * 1e3
+    traffic, tb = None, None
+    m = MEASURED_TRAFFIC.get(traffic_key) if traffic_key else None
+    if m and shape_ok and m[0] == kernel_source_hash():
+        tb = m[1] + m[2]
+        traffic = round(tb / (avg_us * 1e-6) / 1e9, 1)
+    return {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "traffic_frac": None if traffic is None else round(traffic / HBM_PEAK_GBS, 4),
+        "kernel": kernel, "avg_launch_us": round(avg_us, 3), "launches": launches,
+        "bytes_per_px_iter": bpi,
+        "algorithmic_bytes_per_launch": round(bpi * prof.pd_pixel_iters / launches),
+        "hbm_bytes_per_launch": None if tb is None else round(tb),
+    }
+
+
+PAPER_REALTIME = ("1.7 ms per reconstructed 128x128 image from 500 events (about 580 images/s, "
+                  "0.29 M events/s) on an NVIDIA Titan X with a 3.4 GHz CPU (Section 4.1)")
+
+
+def bench_dvs128(n_blocks=200, warmup=20):
+    """The paper's setting: 128x128 sensor, blocks of 500 events, 50
+    iterations.  Throughput over n_blocks back-to-back blocks, and the
+    latency of one image (push, solve, wait for it) averaged over blocks."""
+    import torch
+    import evgen
+    from paper_1607_06283_amd import rec
+
+    s, bs, nb, iters = evgen.dvs128(seed=1, n_batches=n_blocks + warmup)
+    ev = s.events
+    dev = torch.device("cuda", 0)
+    t = torch.from_numpy(ev.t).to(dev)
+    x = torch.from_numpy(ev.x.view(np.int16)).to(dev)
+    y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
+    p = torch.from_numpy(ev.p).to(dev)
+    r = rec.Reconstructor(128, 128)
+
+    def step(i):
+        a = i * bs
+        rc = rec.rec_push_events(r.ctx, t.data_ptr() + 8 * a, x.data_ptr() + 2 * a,
+                                 y.data_ptr() + 2 * a, p.data_ptr() + a, bs, 1)
+        if rc:
+            raise rec.RecError(rc, "rec_push_events")
+        rc, _ = rec.rec_solve(r.ctx, iters, False)
+        if rc:
+            raise rec.RecError(rc, "rec_solve")
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + n_blocks):
+        step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat = []
+    for i in range(warmup, warmup + 50):
+        t1 = time.perf_counter()
+        step(i)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t1)
+    r.sync()
+    r.close()
+    return {"workload": "128x128 sensor, texture translating at 200 px/s, blocks of 500 events, "
+                        "50 FP32 iterations per block, device-resident events",
+            "blocks": n_blocks, "PD iter*Mpix/s": round(n_blocks * iters * 128 * 128 / dt / 1e6, 2),
+            "events_per_s": round(n_blocks * bs / dt, 1),
+            "images_per_s": round(n_blocks / dt, 1),
+            "ms_per_image_back_to_back": round(dt / n_blocks * 1e3, 4),
+            "ms_per_image_latency": round(float(np.mean(lat)) * 1e3, 4),
+            "paper_context": PAPER_REALTIME}
+
+
+def bench_streams64(steps=20, warmup=3):
+    """64 cameras batched (autotuned), against one solve per camera."""
+    IT = WORKLOADS["streams64"][3]
+    dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False)
+    _, prof, cfg_p, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True)
+    dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
+    return {"workload": WORKLOAD_TEXT["streams64"], "steps": steps, "warmup": warmup,
+            "PD iter*Mpix/s": round(steps * IT * px / dt / 1e6, 2),
+            "ms_per_step": round(dt / steps * 1e3, 4), "events_per_s": round(steps * evs / dt, 1),
+            "config": {"tile_rows": cfg[0], "tile_waves": cfg[1], "fuse_iters": cfg[2]},
+            "per_camera_solves": {"PD iter*Mpix/s": round(steps * IT * px / dt_solo / 1e6, 2),
+                                  "ms_per_step": round(dt_solo / steps * 1e3, 4)},
+            "batched_speedup": round(dt_solo / dt, 3),
+            "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused_batch", ("streams64", "f32"),
+                                 tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE)}
+
+
+def bench_probe(steps=10, warmup=2):
+    """5120x5760 frame, uniform random events, blocks of 20000, 50 iterations:
+    a state beyond the Infinity Cache, so the fused loop streams from HBM."""
+    W, H, B, IT = WORKLOADS["probe"]
+    ev = random_stream(W, H, (steps + warmup) * B)
+    kw = dict(shape=(W, H), batch=B, iters=IT)
+    dt, _, _ = run_gpu(ev, steps, warmup, -1, profile=False, **kw)
+    _, prof, _ = run_gpu(ev, steps, warmup, -1, profile=True, **kw)
+    return {"workload": WORKLOAD_TEXT["probe"], "steps": steps, "warmup": warmup,
+            "PD iter*Mpix/s": round(steps * IT * W * H / dt / 1e6, 2),
+            "ms_per_step": round(dt / steps * 1e3, 4),
+            "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused", ("probe", "f32"))}
 
 
 if __name__ == "__main__":

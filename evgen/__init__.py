@@ -318,3 +318,31 @@ def diff_blocks(seed0: int = 500, n: int = 16, width: int = 346, height: int = 2
         t_end = int(blk.t[-1]) - spec.t0_us
         out.append((spec, blk, frame(spec, 0), frame(spec, t_end)))
     return out
+
+
+STREAMS64_SIZES = [(128, 128), (240, 180), (346, 260), (640, 480)]
+
+
+def streams64(steps: int, seed: int = 400, sizes=None, per_size: int = 16):
+    """Many independent cameras of uneven size and event rate: `per_size`
+    cameras of each sensor size (default 16 each of 128x128, 240x180,
+    346x260, 640x480), camera i seeded with seed + i.  Per camera an event
+    rate log-uniform in [1e5, 5e6] /s and a block size log-uniform in
+    [200, 5000] events; uniform random pixels and polarities, exponential
+    inter-event times at that rate (floored to us), `steps` blocks.
+    Returns a list of (W, H, block_size, Events)."""
+    sizes = STREAMS64_SIZES if sizes is None else sizes
+    cams = []
+    for i in range(per_size * len(sizes)):
+        rng = np.random.default_rng(seed + i)
+        W, H = sizes[i // per_size]
+        rate = float(np.exp(rng.uniform(np.log(1e5), np.log(5e6))))
+        bs = int(round(np.exp(rng.uniform(np.log(200), np.log(5000)))))
+        n = bs * steps
+        dt = rng.exponential(1e6 / rate, n)
+        t = T0_US + np.floor(np.cumsum(dt)).astype(np.int64)
+        x = rng.integers(0, W, n).astype(np.uint16)
+        y = rng.integers(0, H, n).astype(np.uint16)
+        p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+        cams.append((W, H, bs, Events(t, x, y, p, np.zeros(n, np.uint8))))
+    return cams

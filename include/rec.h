@@ -20,9 +20,10 @@
  *   - Timestamps are int64 microseconds and must not decrease (ties allowed),
  *     also across pushes.  Relative times are formed from exact int64
  *     differences, divided in FP64, and only then rounded to FP32.
- *   - The primal image u, the data image f, the dual field p (3 planes) and
- *     the time differences are FP32 in device memory; the primal-dual gap is
- *     accumulated in FP64.
+ *   - The primal image u and the data image f are FP32 in device memory.
+ *     The dual field p (3 planes) and the time differences tx, ty are FP32,
+ *     or BF16 / FP16 with rec_params.storage; the arithmetic is FP32 in
+ *     every case, and the primal-dual gap is accumulated in FP64.
  *   - Every function returns an int status: REC_OK (0) or a negative REC_E*
  *     code.  No C++ exception crosses this interface.
  *
@@ -31,21 +32,27 @@
  *     keeps it alive until rec_destroy; the library never allocates device
  *     memory.  It allocates the host-side context and a pinned host staging
  *     buffer for host-pointer pushes, both released by rec_destroy.
- *   - Event arrays and output buffers belong to the caller; host arrays only
- *     need to stay valid for the duration of the call; device arrays until
- *     the push has executed, which is guaranteed once the next rec_solve has
- *     completed on the caller's stream or a synchronising call returned.
+ *   - Event arrays and output buffers belong to the caller.  Host arrays
+ *     only need to stay valid for the duration of the call.  A device-
+ *     pointer push records the pointers: the arrays must stay valid, and
+ *     unchanged, until the next rec_solve (or rec_batch_solve) has completed
+ *     on the context's stream, or until one of the synchronising calls
+ *     below has returned (each scatters the recorded pushes first).
  *
  * Streams and synchronisation
- *   - Builds, iterations, gap evaluations and readbacks are enqueued on the
- *     hipStream_t given to rec_init (NULL = the default stream).  Pushes run
- *     on an internal stream of the context, ordered by events after the
- *     previous block's build and before the next one, so a push overlaps the
- *     previous block's iterations.  Work the caller enqueues on its stream
- *     after rec_solve returns is ordered after that solve.
- *   - rec_push_events (device pointers) and rec_solve without stats do not
- *     synchronise.  rec_solve with stats, rec_get_image, rec_gap_history,
- *     rec_profile_read, rec_sync and rec_destroy do (both streams).
+ *   - All device work of a context -- pushes, builds, iterations, gap
+ *     evaluations and readbacks -- is enqueued in order on the one
+ *     hipStream_t given to rec_init (NULL = the default stream); the library
+ *     creates no stream of its own.  Work the caller enqueues on that stream
+ *     after a call returns is ordered after that call's work.
+ *   - Device-pointer pushes are not launched when made: the first fused
+ *     launch of the next rec_solve validates and bins them itself (or, for
+ *     more pushes or events than it takes, they are scattered by kernels of
+ *     their own at that point).  Host-pointer pushes are validated on the
+ *     host, copied through the pinned staging buffer and scattered at once.
+ *   - rec_push_events and rec_solve without stats do not synchronise.
+ *     rec_solve with stats, rec_get_image, rec_gap_history,
+ *     rec_profile_read, rec_sync and rec_destroy synchronise the stream.
  *   - Errors found on the device (device-pointer pushes) are reported by the
  *     next synchronising call; the rejected push changes no state.
  *
@@ -70,7 +77,8 @@ enum {
     REC_EORDER = -3,   /* timestamp lower than the previous one */
     REC_EDEVICE = -4,  /* a HIP runtime call failed */
     REC_ENUMERIC = -5, /* non-finite gap or energy */
-    REC_ESTATE = -6,   /* call not valid in the context's state */
+    REC_ESTATE = -6,   /* call not valid in the object's state: rec_destroy of a
+                          context that a live batch still holds */
     REC_ENOMEM = -7    /* workspace too small or host allocation failed */
 };
 
@@ -85,7 +93,8 @@ enum {
     REC_TY = 6,        /* float[H*W]  tau(x, y+1) - tau(x, y), 0 on the last row */
     REC_COUNT_POS = 7, /* int32[H*W]  positive events of the pending block */
     REC_COUNT_NEG = 8, /* int32[H*W]  negative events of the pending block */
-    REC_T_LAST = 9     /* int64[H*W]  latest timestamp (first stream timestamp if none) */
+    REC_T_LAST = 9     /* int64[H*W]  latest timestamp; a pixel that never fired reads
+                          as the stream's first timestamp (0 before any event) */
 };
 
 /* Storage of the dual field and the time differences (rec_params.storage). */
@@ -172,31 +181,64 @@ int rec_check_events(const int64_t* t_us, const uint16_t* x, const uint16_t* y,
                      const int8_t* polarity, int64_t n, int32_t width, int32_t height,
                      int64_t t_prev);
 
-/* Create a context on the current HIP device.  dev_workspace: device memory of
- * at least rec_workspace_bytes(prm) bytes, 256-byte aligned.  hip_stream: a
- * hipStream_t or NULL.  u0: optional host image (H*W floats, each in
- * (0, inf)) used as the initial u instead of prm->u_init.  On success *out
- * holds the context; the workspace is initialised asynchronously on the stream. */
+/* Create a context on the current HIP device: the reconstruction state of
+ * one event camera of width x height pixels (the image domain Omega of
+ * Section 3), with u initialised to prm->u_init or to the caller's first
+ * image u0 (Section 3 notes that the first image cannot be recovered from
+ * events; a known u0 is the case the paper integrates from), p = 0, no
+ * event seen.
+ *   dev_workspace  device memory of at least rec_workspace_bytes(prm)
+ *                  bytes, 256-byte aligned; owned by the caller.
+ *   ws_bytes       its size in bytes.
+ *   hip_stream     a hipStream_t or NULL (default stream).
+ *   u0             optional host image, H*W floats row-major, each finite
+ *                  and > 0; copied before the call returns.
+ *   out            receives the context.
+ * Errors: REC_EINVAL (bad parameters, NULL or misaligned workspace, a u0
+ * value <= 0 or non-finite), REC_ENOMEM (short workspace, host allocation),
+ * REC_EDEVICE (HIP call failed).  On error *out is NULL and nothing is
+ * left allocated.  The workspace is initialised asynchronously on the
+ * stream (with u0 the call synchronises once). */
 int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* hip_stream,
              const float* u0, rec_ctx** out);
 
-/* Add n events to the pending block (SoA arrays; host memory if on_device == 0,
- * device memory otherwise).  All-or-nothing.  Host pointers are validated on
- * the host before anything is enqueued (errors returned directly); device
- * pointers are validated on the device (errors reported by the next
- * synchronising call).  n == 0 is a no-op. */
+/* Add n events e^k = (x^k, y^k, theta^k, t^k) (Section 3: pixel, polarity
+ * +-1, timestamp) to the pending block.  SoA arrays of n elements each:
+ * t_us int64 microseconds, non-decreasing within the push and across
+ * pushes; x < width and y < height; polarity in {-1, +1}.  Host memory if
+ * on_device == 0, device memory otherwise (see Ownership).
+ * All-or-nothing: a rejected push changes no state.  Host pointers are
+ * validated on the host before anything is enqueued (REC_EINVAL bad
+ * polarity or NULL array, REC_ERANGE coordinate outside the image,
+ * REC_EORDER timestamp below the previous one; the first failing event
+ * decides); device pointers are validated on the device and the same codes
+ * are reported by the next synchronising call.  n == 0 is a no-op. */
 int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const uint16_t* y,
                     const int8_t* polarity, int64_t n, int on_device);
 
-/* Solve the pending block: build f, tau and the metric, then run `iters`
- * primal-dual iterations (prm->iters if iters <= 0) warm-started from the
- * previous (u, p).  With stats != NULL the call synchronises and fills it;
- * a non-finite gap or energy returns REC_ENUMERIC. */
+/* Solve the pending block.
+ *   1. f = u_prev * exp(Delta+ n+ - Delta- n-) per pixel, n+- the block's
+ *      event counts (eqn. intensity_update applied for every event);
+ *   2. tau = (t_ref - t_last) / T_s and its forward differences tx, ty,
+ *      which define the metric g = I + grad tau grad tau^T, G = det g and
+ *      the operator L_g (Section 3.1, eqns. 1-3);
+ *   3. `iters` Chambolle-Pock iterations for eqn. (5) with the closed-form
+ *      proximal maps of Section 3.2 (eqns. cont_iterates, update_rules),
+ *      warm-started from the previous block's (u, p); prm->iters if
+ *      iters <= 0.
+ * Without stats the call only enqueues work.  With stats != NULL it
+ * synchronises and fills *stats; REC_ENUMERIC if the last sampled gap or
+ * energy is not finite (gap sampling needs prm->gap_every > 0), and any
+ * deferred push error is returned.  REC_EDEVICE if a launch fails. */
 int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats);
 
-/* Copy a plane (see the REC_U.. list) into out: host memory if on_device == 0
- * (synchronises), device memory otherwise (enqueued, then synchronises so
- * pending device errors are reported). */
+/* Copy a plane of the state into out (the REC_U.. list gives type and
+ * size): the reconstructed image u : Omega -> [u_min, u_max] (Section 3,
+ * eqn. 5) and the inputs and intermediates of the last solve.  out is host
+ * memory if on_device == 0, device memory otherwise; the call synchronises
+ * in both cases and reports deferred push errors.  Recorded device-pointer
+ * pushes are scattered first, so count, time and latest-timestamp planes
+ * include them.  REC_EINVAL for an unknown plane or NULL out. */
 int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device);
 
 /* Gap and energy samples of the last rec_solve, in order; returns the number
@@ -213,7 +255,9 @@ int rec_profile(rec_ctx* c, int enable);
 /* Read the timing totals collected since profiling was turned on (synchronises). */
 int rec_profile_read(rec_ctx* c, rec_profile_t* out);
 
-/* Release the context (after synchronising its stream).  NULL is a no-op. */
+/* Release the context (after synchronising its stream).  NULL is a no-op.
+ * REC_ESTATE, and nothing is released, while a live batch (rec_batch_init
+ * without rec_batch_destroy yet) holds the context. */
 int rec_destroy(rec_ctx* c);
 
 /* Static description of a status code. */

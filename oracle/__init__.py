@@ -20,6 +20,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_LIB_MT_PATH = os.path.join(_HERE, "liboracle_mt.so")  # same source, OpenMP over pixels
 
 OK, EINVAL, ERANGE, EORDER = 0, -1, -2, -3
 U, F, TAU, TX, TY, P1, P2, P3, TAU32, TX32, TY32, NPOS, NNEG, TLAST = range(14)
@@ -66,68 +67,83 @@ class Params:
 
 
 def build(force: bool = True) -> str:
-    """Compile ``liboracle.so`` (gcc -O2, IEEE double, no contraction)."""
-    if force or not os.path.exists(_LIB_PATH):
-        tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call([
-            "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
-            "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile ``liboracle.so`` (gcc -O2, IEEE double, no contraction) and
+    the OpenMP build of the same file, ``liboracle_mt.so``."""
+    for path, extra in ((_LIB_PATH, ["-Wno-unknown-pragmas"]), (_LIB_MT_PATH, ["-fopenmp"])):
+        if force or not os.path.exists(path):
+            tmp = path + ".tmp"
+            subprocess.check_call([
+                "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math",
+                "-ffp-contract=off", "-Wall", *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
 _lib = None
+_lib_mt = None
 _vp = ctypes.c_void_p
 
 
-def _load():
-    global _lib
+def _load(threads: bool = False):
+    """The single-threaded library, or with threads=True the OpenMP build
+    (its thread count follows OMP_NUM_THREADS)."""
+    global _lib, _lib_mt
+    if threads:
+        if _lib_mt is None:
+            if not os.path.exists(_LIB_MT_PATH):
+                build(force=False)
+            _lib_mt = _declare(ctypes.CDLL(_LIB_MT_PATH))
+        return _lib_mt
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
-            build()
-        lib = ctypes.CDLL(_LIB_PATH)
-        lib.orc_create.restype = _vp
-        lib.orc_create.argtypes = [ctypes.POINTER(_P), _vp]
-        lib.orc_free.restype = None
-        lib.orc_free.argtypes = [_vp]
-        lib.orc_check_params.restype = ctypes.c_int
-        lib.orc_check_params.argtypes = [ctypes.POINTER(_P)]
-        lib.orc_push.restype = ctypes.c_int
-        lib.orc_push.argtypes = [_vp] * 5 + [ctypes.c_int64]
-        lib.orc_build.restype = None
-        lib.orc_build.argtypes = [_vp]
-        lib.orc_iterate.restype = None
-        lib.orc_iterate.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
-        lib.orc_solve.restype = None
-        lib.orc_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
-        lib.orc_gap_energy.restype = None
-        lib.orc_gap_energy.argtypes = [_vp, _vp, _vp]
-        lib.orc_get.restype = ctypes.c_int
-        lib.orc_get.argtypes = [_vp, ctypes.c_int, _vp]
-        lib.orc_t_ref.restype = ctypes.c_int64
-        lib.orc_t_ref.argtypes = [_vp]
-        lib.orc_set_state.restype = ctypes.c_int
-        lib.orc_set_state.argtypes = [_vp] * 5
-        lib.orc_set_data.restype = ctypes.c_int
-        lib.orc_set_data.argtypes = [_vp] * 4
-        lib.orc_grad.restype = None
-        lib.orc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
-        lib.orc_div.restype = None
-        lib.orc_div.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
-        lib.orc_apply_Lg.restype = None
-        lib.orc_apply_Lg.argtypes = [ctypes.c_int, ctypes.c_int] + [_vp] * 6
-        lib.orc_apply_LgT.restype = None
-        lib.orc_apply_LgT.argtypes = [ctypes.c_int, ctypes.c_int] + [_vp] * 6
-        lib.orc_prox_kl.restype = ctypes.c_double
-        lib.orc_prox_kl.argtypes = [ctypes.c_double] * 5
-        lib.orc_project.restype = None
-        lib.orc_project.argtypes = [_vp, _vp, _vp, ctypes.c_double]
-        lib.orc_set_weights.restype = ctypes.c_int
-        lib.orc_set_weights.argtypes = [_vp, _vp]
-        lib.orc_tvl1.restype = None
-        lib.orc_tvl1.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, _vp]
-        _lib = lib
+            build(force=False)
+        _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
+
+
+def _declare(lib):
+    """Argument and result types of the exported functions."""
+    lib.orc_create.restype = _vp
+    lib.orc_create.argtypes = [ctypes.POINTER(_P), _vp]
+    lib.orc_free.restype = None
+    lib.orc_free.argtypes = [_vp]
+    lib.orc_check_params.restype = ctypes.c_int
+    lib.orc_check_params.argtypes = [ctypes.POINTER(_P)]
+    lib.orc_push.restype = ctypes.c_int
+    lib.orc_push.argtypes = [_vp] * 5 + [ctypes.c_int64]
+    lib.orc_build.restype = None
+    lib.orc_build.argtypes = [_vp]
+    lib.orc_iterate.restype = None
+    lib.orc_iterate.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
+    lib.orc_solve.restype = None
+    lib.orc_solve.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp]
+    lib.orc_gap_energy.restype = None
+    lib.orc_gap_energy.argtypes = [_vp, _vp, _vp]
+    lib.orc_get.restype = ctypes.c_int
+    lib.orc_get.argtypes = [_vp, ctypes.c_int, _vp]
+    lib.orc_t_ref.restype = ctypes.c_int64
+    lib.orc_t_ref.argtypes = [_vp]
+    lib.orc_set_state.restype = ctypes.c_int
+    lib.orc_set_state.argtypes = [_vp] * 5
+    lib.orc_set_data.restype = ctypes.c_int
+    lib.orc_set_data.argtypes = [_vp] * 4
+    lib.orc_grad.restype = None
+    lib.orc_grad.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.orc_div.restype = None
+    lib.orc_div.argtypes = [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp]
+    lib.orc_apply_Lg.restype = None
+    lib.orc_apply_Lg.argtypes = [ctypes.c_int, ctypes.c_int] + [_vp] * 6
+    lib.orc_apply_LgT.restype = None
+    lib.orc_apply_LgT.argtypes = [ctypes.c_int, ctypes.c_int] + [_vp] * 6
+    lib.orc_prox_kl.restype = ctypes.c_double
+    lib.orc_prox_kl.argtypes = [ctypes.c_double] * 5
+    lib.orc_project.restype = None
+    lib.orc_project.argtypes = [_vp, _vp, _vp, ctypes.c_double]
+    lib.orc_set_weights.restype = ctypes.c_int
+    lib.orc_set_weights.argtypes = [_vp, _vp]
+    lib.orc_tvl1.restype = None
+    lib.orc_tvl1.argtypes = [ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double, _vp]
+    return lib
 
 
 def _f64(a) -> np.ndarray:
@@ -207,9 +223,9 @@ def check_params(p: Params) -> int:
 class Oracle:
     """One event stream reconstructed in FP64 (mirrors the library's calls)."""
 
-    def __init__(self, params: Params, u0: Optional[np.ndarray] = None):
+    def __init__(self, params: Params, u0: Optional[np.ndarray] = None, threads: bool = False):
         self.params = params
-        self._lib = _load()
+        self._lib = _load(threads)
         c = params._c()
         u0a = None if u0 is None else _f64(u0).reshape(params.height, params.width)
         self._h = self._lib.orc_create(ctypes.byref(c), _ptr(u0a))

@@ -55,6 +55,12 @@
  *   term2 = (u - v)(b + d) - b f log(u / v),
  *           v = clamp(b f / (b + d)) if b + d > 0 else u_max    (>= 0)
  * The gap is the sum of both terms over all pixels.
+ *
+ * Built twice from this one file: single-threaded, and with OpenMP (the
+ * pragmas below split the per-pixel loops of the operators and of the
+ * iteration over threads; every pixel's value is computed by the same
+ * operations either way, and the gap and energy sums stay serial, so both
+ * builds give the same bits).
  */
 #include <math.h>
 #include <stdint.h>
@@ -101,6 +107,7 @@ typedef struct {
 
 /* Forward differences with zero on the last column / row (Chambolle 2004). */
 void orc_grad(int W, int H, const double* v, double* gx, double* gy) {
+#pragma omp parallel for
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             size_t k = (size_t)i * W + j;
@@ -111,6 +118,7 @@ void orc_grad(int W, int H, const double* v, double* gx, double* gy) {
 
 /* div = -grad^T: backward differences with the matching boundary rows. */
 void orc_div(int W, int H, const double* qx, const double* qy, double* out) {
+#pragma omp parallel for
     for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             size_t k = (size_t)i * W + j;
@@ -131,6 +139,7 @@ void orc_apply_Lg(int W, int H, const double* tx, const double* ty, const double
     double* ux = (double*)malloc(sizeof(double) * np);
     double* uy = (double*)malloc(sizeof(double) * np);
     orc_grad(W, H, u, ux, uy);
+#pragma omp parallel for
     for (size_t k = 0; k < np; ++k) {
         double G = 1.0 + tx[k] * tx[k] + ty[k] * ty[k];
         a1[k] = ((1.0 + ty[k] * ty[k]) * ux[k] - tx[k] * ty[k] * uy[k]) / G;
@@ -148,6 +157,7 @@ void orc_apply_LgT(int W, int H, const double* tx, const double* ty, const doubl
     size_t np = (size_t)W * H;
     double* qx = (double*)calloc(np, sizeof(double));
     double* qy = (double*)calloc(np, sizeof(double));
+#pragma omp parallel for
     for (size_t k = 0; k < np; ++k) {
         double G = 1.0 + tx[k] * tx[k] + ty[k] * ty[k];
         /* columns of M: M[:,0] = (1+ty^2, -tx ty, tx)/G, M[:,1] = (-tx ty, 1+tx^2, ty)/G */
@@ -155,6 +165,7 @@ void orc_apply_LgT(int W, int H, const double* tx, const double* ty, const doubl
         qy[k] = (-tx[k] * ty[k] * p1[k] + (1.0 + tx[k] * tx[k]) * p2[k] + ty[k] * p3[k]) / G;
     }
     orc_div(W, H, qx, qy, out);
+#pragma omp parallel for
     for (size_t k = 0; k < np; ++k) out[k] = -out[k];
     free(qx);
     free(qy);
@@ -418,6 +429,7 @@ void orc_iterate(orc_state* S, int iters, int gap_every, double* gaps, double* e
     for (int it = 0; it < iters; ++it) {
         /* primal step */
         orc_apply_LgT(W, H, S->tx, S->ty, S->p1, S->p2, S->p3, ls);
+#pragma omp parallel for
         for (size_t k = 0; k < n; ++k) {
             double s = sqrt(1.0 + S->tx[k] * S->tx[k] + S->ty[k] * S->ty[k]);
             double beta = tau * lam * (S->w ? S->w[k] : 1.0) * s;
@@ -427,6 +439,7 @@ void orc_iterate(orc_state* S, int iters, int gap_every, double* gaps, double* e
         }
         /* dual step on the extrapolated primal */
         orc_apply_Lg(W, H, S->tx, S->ty, ut, a1, a2, a3);
+#pragma omp parallel for
         for (size_t k = 0; k < n; ++k) {
             double s = sqrt(1.0 + S->tx[k] * S->tx[k] + S->ty[k] * S->ty[k]);
             double q1 = S->p1[k] + sigma * a1[k];

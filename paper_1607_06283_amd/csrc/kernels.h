@@ -161,6 +161,7 @@ hipError_t launch_gap(const Planes& P, Frame fr, double lambda, double umin, dou
 hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, float* out,
                              hipStream_t s);
 hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s);
+hipError_t launch_tlast_plane(const Planes& P, Frame fr, int64_t* out, hipStream_t s);
 hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s);
 // Batched solve: one launch over the work list of (stream, tile) pairs.
 // K iterations in this launch, KG the halo of the tile geometry (K <= KG),

@@ -59,11 +59,22 @@ struct StoreF32 {
     static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = v; }
     static __device__ __forceinline__ float round(float v) { return v; }
 };
+// FP16 saturates at its largest finite value instead of rounding to
+// infinity: a time difference above 65504 (a pixel idle for more than
+// 65.5 s at T_s = 1 ms next to one that fires now) would otherwise turn the
+// frame of that pixel into inf * 0 = NaN.  Such a pixel has G > 4.29e9 and
+// beta = tau lambda sqrt(G) > 1.7e6, so its u is clamp(f) to within FP32
+// either way; p, whose ball radius is sqrt(G), saturates likewise.  NaN
+// stays NaN.
 struct StoreF16 {
     using T = _Float16;
+    static __device__ __forceinline__ float sat(float v) {
+        constexpr float kMax = 65504.0f;
+        return __builtin_fabsf(v) > kMax ? __builtin_copysignf(kMax, v) : v;
+    }
     static __device__ __forceinline__ float ld(const T* a, size_t k) { return (float)a[k]; }
-    static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = (_Float16)v; }
-    static __device__ __forceinline__ float round(float v) { return (float)(_Float16)v; }
+    static __device__ __forceinline__ void st(T* a, size_t k, float v) { a[k] = (_Float16)sat(v); }
+    static __device__ __forceinline__ float round(float v) { return (float)(_Float16)sat(v); }
 };
 struct StoreBF16 {
     using T = uint16_t;
@@ -268,6 +279,15 @@ __global__ void k_time_plane(Planes P, Frame fr, double ts, float* out) {
     const DevState* st = P.st;
     const int64_t tl = resolved_last(P.t_last[k], st->t_first);
     out[k] = ts > 0.0 ? (float)((double)(st->t_ref - tl) / ts) : 0.0f;
+}
+
+// Latest timestamps with pixels that never fired resolved to the stream's
+// first timestamp (0 before any event was accepted).
+__global__ void k_tlast_plane(Planes P, Frame fr, int64_t* out) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    out[k] = resolved_last(P.t_last[k], P.st->t_first);
 }
 
 template <class S>
@@ -1484,6 +1504,12 @@ hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, flo
     const size_t np = (size_t)fr.W * fr.H;
     return launch(k_time_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P,
                   fr, time_unit_us, out);
+}
+
+hipError_t launch_tlast_plane(const Planes& P, Frame fr, int64_t* out, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    return launch(k_tlast_plane, dim3(blocks_for(np, 256)), dim3(256), 0, s, nullptr, nullptr, P,
+                  fr, out);
 }
 
 hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s) {

@@ -110,6 +110,7 @@ struct rec_ctx {
     bool mirror_started;
     int64_t mirror_tref;
     int gap_samples;
+    int batch_refs;          // live batches holding this context (rec_destroy refuses while > 0)
     // profiling
     bool prof_on;
     std::vector<hipEvent_t> prof_pool;
@@ -625,14 +626,13 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
 }
 
 int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
-    if (!c || !out) return REC_EINVAL;
+    if (!c || !out || which < REC_U || which > REC_T_LAST) return REC_EINVAL;
     const size_t np = (size_t)c->fr.W * c->fr.H;
-    // planes that pushes write are read after the recorded pushes are scattered
-    if (which == REC_COUNT_POS || which == REC_COUNT_NEG || which == REC_T_LAST ||
-        which == REC_TIME) {
-        const int rc = flush_deferred(c);
-        if (rc) return rc;
-    }
+    // a synchronising call: recorded device-pointer pushes are scattered
+    // first, so the caller may release their arrays once this returns (and
+    // planes that pushes write see every push)
+    int rc = flush_deferred(c);
+    if (rc) return rc;
     const void* src = nullptr;
     size_t bytes = np * 4;
     hipError_t e = hipSuccess;
@@ -661,7 +661,15 @@ int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
         }
         case REC_COUNT_POS: src = c->P.npos; break;
         case REC_COUNT_NEG: src = c->P.nneg; break;
-        case REC_T_LAST: src = c->P.t_last; bytes = np * 8; break;
+        case REC_T_LAST: {
+            // pixels that never fired read as the stream's first timestamp
+            // (8 bytes per pixel: the spare dual planes hold 12)
+            int64_t* dst = on_device ? (int64_t*)out : (int64_t*)spare3;
+            e = rec::launch_tlast_plane(c->P, c->fr, dst, c->stream);
+            src = on_device ? nullptr : dst;
+            bytes = np * 8;
+            break;
+        }
         case REC_TIME: {
             float* dst = on_device ? (float*)out : spare;
             e = rec::launch_time_plane(c->P, c->fr, c->prm.time_unit_us, dst, c->stream);
@@ -682,19 +690,14 @@ int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
                            c->stream);
         if (e != hipSuccess) return REC_EDEVICE;
     }
-    rec::DevState st;
-    int rc = read_state(c, &st);
-    if (which == REC_T_LAST && !on_device) {
-        int64_t* o = (int64_t*)out;
-        for (size_t k = 0; k < np; ++k)
-            if (o[k] == rec::kNever) o[k] = st.t_first;
-    }
-    return rc;
+    return read_state(c, nullptr);
 }
 
 int rec_gap_history(rec_ctx* c, double* gap, double* energy, int32_t cap) {
     if (!c || cap < 0) return REC_EINVAL;
-    int rc = read_state(c, nullptr);
+    int rc = flush_deferred(c);
+    if (rc) return rc;
+    rc = read_state(c, nullptr);
     if (rc) return rc;
     int n = c->gap_samples < rec::kGapHistCap ? c->gap_samples : rec::kGapHistCap;
     if (n > cap) n = cap;
@@ -737,7 +740,9 @@ int rec_profile(rec_ctx* c, int enable) {
 
 int rec_profile_read(rec_ctx* c, rec_profile_t* out) {
     if (!c || !out) return REC_EINVAL;
-    const int rc = prof_flush(c);
+    int rc = flush_deferred(c);
+    if (rc) return rc;
+    rc = prof_flush(c);
     if (rc) return rc;
     for (int k = 0; k < kProfClasses; ++k) {
         out->ms[k] = c->prof_ms[k];
@@ -749,6 +754,7 @@ int rec_profile_read(rec_ctx* c, rec_profile_t* out) {
 
 int rec_destroy(rec_ctx* c) {
     if (!c) return REC_OK;
+    if (c->batch_refs > 0) return REC_ESTATE;  // a live batch still uses it
     int rc = REC_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess) rc = REC_EDEVICE;
     for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
@@ -822,6 +828,7 @@ struct rec_batch {
     bool copy_used[2];
     int parity;
     size_t max_np;
+    bool holds_refs;             // the contexts count this batch as a user
 };
 
 namespace {
@@ -1006,6 +1013,8 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
         rec_batch_destroy(b);
         return rc;
     }
+    for (rec_ctx* c : b->ctx) ++c->batch_refs;
+    b->holds_refs = true;
     *out = b;
     return REC_OK;
 }
@@ -1074,6 +1083,8 @@ int rec_batch_destroy(rec_batch* b) {
     if (!b) return REC_OK;
     int rc = REC_OK;
     if (hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
+    if (b->holds_refs)
+        for (rec_ctx* c : b->ctx) --c->batch_refs;
     for (int q = 0; q < 2; ++q) {
         if (b->copied[q]) (void)hipEventDestroy(b->copied[q]);
         if (b->h_desc[q]) (void)hipHostFree(b->h_desc[q]);

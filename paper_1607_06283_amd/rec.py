@@ -298,15 +298,21 @@ class Reconstructor:
         _check(rc, "rec_init")
         self.ctx = h
         self.shape = (self.prm.height, self.prm.width)
-        # device event tensors pushed but not yet consumed by the device: the
-        # library reads them when the next solve (or sync) runs, so they are
-        # kept alive until that work is enqueued on the stream
+        # device event tensors pushed but not yet consumed: the library reads
+        # them when the next solve runs or a synchronising call (image, sync,
+        # gap history) scatters them, so they are kept alive until such a
+        # call has succeeded (stream order covers the solve's own launches)
         self._pending = []
 
     def close(self):
+        """Release the context.  Raises RecError(REC_ESTATE) and keeps it
+        while a live Batch still holds it."""
         if getattr(self, "ctx", None):
-            rec_destroy(self.ctx)
+            rc = rec_destroy(self.ctx)
+            if rc == REC_ESTATE:
+                raise RecError(rc, "rec_destroy")
             self.ctx = None
+            self._pending.clear()
 
     def __del__(self):
         try:
@@ -340,8 +346,8 @@ class Reconstructor:
 
     def solve(self, iters: int = 0, stats: bool = False) -> Optional[rec_stats]:
         rc, st = rec_solve(self.ctx, iters, stats)
-        self._pending.clear()
         _check(rc, "rec_solve")
+        self._pending.clear()
         return st
 
     def image(self, which: int = REC_U, device: bool = False):
@@ -352,23 +358,22 @@ class Reconstructor:
         if device:
             tdt = {np.int32: self.torch.int32, np.int64: self.torch.int64}.get(dt, self.torch.float32)
             out = self.torch.empty(n, dtype=tdt, device=self.device)
-            rc = rec_get_image(self.ctx, which, out, 1)
+            _check(rec_get_image(self.ctx, which, out, 1), "rec_get_image")
             self._pending.clear()
-            _check(rc, "rec_get_image")
             return out.view(*shape)
         out = np.empty(n, dtype=dt)
-        rc = rec_get_image(self.ctx, which, out, 0)
+        _check(rec_get_image(self.ctx, which, out, 0), "rec_get_image")
         self._pending.clear()
-        _check(rc, "rec_get_image")
         return out.reshape(shape)
 
     def gap_history(self):
-        return rec_gap_history(self.ctx)
+        out = rec_gap_history(self.ctx)
+        self._pending.clear()
+        return out
 
     def sync(self) -> None:
-        rc = rec_sync(self.ctx)
+        _check(rec_sync(self.ctx), "rec_sync")
         self._pending.clear()
-        _check(rc, "rec_sync")
 
 
 def _ctx_array(ctxs):
@@ -421,10 +426,9 @@ class Batch:
         self.handle = h
 
     def solve(self, iters: int) -> None:
-        rc = rec_batch_solve(self.handle, iters)
+        _check(rec_batch_solve(self.handle, iters), "rec_batch_solve")
         for r in self.recs:
             r._pending.clear()
-        _check(rc, "rec_batch_solve")
 
     def config(self):
         return rec_batch_config(self.handle)

@@ -277,3 +277,78 @@ def test_bad_descriptors_rejected():
     th = torch.tensor([LAM, DPOS, DNEG], dtype=torch.float64, device="cuda")
     with pytest.raises(rec.RecError):
         rec.unrolled(d["u0"], d["npos"], d["nneg"], d["tx"], d["ty"], th, 5, tau=1.0, sigma=1.0)
+
+
+@pytest.mark.slow
+def test_diff16_event_blocks_against_fp64_autograd():
+    """The differentiation workload itself: 16 blocks of 2000 events from
+    346x260 streams (seeds 500-515), u0 = exp(L_gt(t0)), 100 unrolled
+    iterations, checkpoints every 10, loss 1/2 sum (log u - L_gt(t_end))^2.
+    The block data (counts, time differences) come from the FP64 oracle's
+    scatter and build.  The GPU solves all 16 images; the loss is taken on
+    two sampled images (the images are independent, so the other images
+    contribute nothing), whose gradients are compared with FP64 autograd
+    (norm-relative 1e-3 for u0 and w, 1e-3 for lambda, Delta+, Delta-).
+    These inputs put part of the image on the clamp's kinks: the fraction
+    of clamped pixels and the pixels where the FP32 and FP64 iterations end
+    on different sides of a clamp are reported."""
+    torch = _torch()
+    K, CK, W, H, NB = 100, 10, 346, 260, 16
+    blocks = evgen.diff_blocks(500, NB, W, H, 2000)
+    npos, nneg, tx, ty, u0, Lend = [], [], [], [], [], []
+    for spec, blk, L0, L1 in blocks:
+        o = oracle.Oracle(oracle.Params(W, H))
+        o.push_events(blk)
+        npos.append(o.get(oracle.NPOS))
+        nneg.append(o.get(oracle.NNEG))
+        o.build()
+        tx.append(o.get(oracle.TX32))
+        ty.append(o.get(oracle.TY32))
+        o.close()
+        u0.append(np.exp(L0).astype(np.float32))
+        Lend.append(L1)
+    inp = {"u0": np.stack(u0), "npos": np.stack(npos), "nneg": np.stack(nneg),
+           "tx": np.stack(tx), "ty": np.stack(ty), "w": np.ones((NB, H, W), np.float32)}
+    Lend = np.stack(Lend)
+    pick = [3, 12]
+    mask = np.zeros(NB)
+    mask[pick] = 1.0
+    d = _dev(inp)
+    u0t = d["u0"].clone().requires_grad_()
+    wt = d["w"].clone().requires_grad_()
+    th = torch.tensor([90.0, 0.2, 0.2], dtype=torch.float64, device="cuda", requires_grad=True)
+    print("diff16 event blocks: GPU forward + backward", flush=True)
+    u, _ = rec.unrolled(u0t, d["npos"], d["nneg"], d["tx"], d["ty"], th, K, w=wt, ckpt_every=CK)
+    m = torch.from_numpy(mask).cuda()[:, None, None]
+    loss = 0.5 * (m * (torch.log(u.double()) - torch.from_numpy(Lend).cuda()) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    g = dict(u=u.detach().cpu().numpy()[pick], u0=u0t.grad.cpu().numpy()[pick],
+             w=wt.grad.cpu().numpy()[pick], theta=th.grad.cpu().numpy())
+    print("diff16 event blocks: FP64 autograd of the two sampled images", flush=True)
+    t = lambda a: torch.from_numpy(np.asarray(a, np.float64))
+    sub = {k: v[pick] for k, v in inp.items()}
+    u0r = t(sub["u0"]).requires_grad_()
+    wr = t(sub["w"]).requires_grad_()
+    thr = torch.tensor([90.0, 0.2, 0.2], dtype=torch.float64, requires_grad=True)
+    ur, _ = autodiff.unrolled(u0r, t(sub["npos"]), t(sub["nneg"]), t(sub["tx"]), t(sub["ty"]),
+                              wr, thr[0], thr[1], thr[2], K)
+    lr = 0.5 * ((torch.log(ur) - t(Lend[pick])) ** 2).sum()
+    lr.backward()
+    ref = ur.detach().numpy()
+    clamped = (ref <= 1.0 + 1e-12) | (ref >= math.e - 1e-12)
+    gpu_clamped = (g["u"] <= np.float32(1.0)) | (g["u"] >= np.float32(math.e))
+    flips = int((clamped != gpu_clamped).sum())
+    print(f"  clamp active at the end on {clamped.mean():.2%} of pixels; "
+          f"FP32/FP64 on different sides: {flips} pixels")
+    assert np.abs(g["u"] - ref).max() <= 1e-4
+    assert abs(loss.item() - lr.item()) <= 1e-4 * abs(lr.item())
+    for k, rg in (("u0", u0r.grad.numpy()), ("w", wr.grad.numpy())):
+        e = _rel(g[k], rg)
+        print(f"  d/d{k}: relative error {e:.2e}")
+        assert e <= GRAD_RTOL, k
+    for i, name in enumerate(("lambda", "dpos", "dneg")):
+        rv = thr.grad.numpy()[i]
+        e = abs(g["theta"][i] - rv) / abs(rv)
+        print(f"  d/d{name}: {g['theta'][i]:.6e} vs {rv:.6e} ({e:.2e})")
+        assert e <= GRAD_RTOL, name

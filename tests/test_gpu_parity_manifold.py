@@ -1,0 +1,162 @@
+"""GPU parity of the full state (u and the dual field p) against the FP64
+oracle across time units of the manifold, on long streams, and on the
+many-camera batched solve.
+
+The time unit T_s sets how strongly the time surface bends the metric
+(g = I + grad tau grad tau^T, Section 3.1): T_s = 0 is the flat manifold of
+the t = const ablation (Section 4.2, standard TV-KL), T_s = 100 us turns an
+edge moving at 200 px/s into slopes of ~50 (G in the thousands, beta =
+tau lambda sqrt(G) in the thousands), the FP32 stress case; 1000 is the
+default and 10000 a nearly flat surface.
+"""
+import numpy as np
+import pytest
+
+import evgen
+import oracle
+from paper_1607_06283_amd import rec
+
+from gpu_helpers import P_RTOL, U_TOL, device_events, make, radius, u_p_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    s, _, _, _ = evgen.dvs128(seed=1, n_batches=20)
+    return s
+
+
+@pytest.mark.parametrize("ts", [1000.0, 100.0, 10000.0, 0.0])
+@pytest.mark.parametrize("on_device", [False, True])
+def test_u_and_p_across_time_units(c1, ts, on_device):
+    """128x128, 20 blocks of 500 events, 50 iterations each: after every
+    block u within 1e-4 and p within 1e-4 * sqrt(G) of the FP64 oracle, at
+    every time unit; at T_s = 0 the third dual component stays 0 (the flat
+    manifold carries the standard 2-component TV-KL dual)."""
+    r, o = make(128, 128, time_unit_us=ts)
+    worst_u = worst_p = 0.0
+    s_max = 1.0
+    for i, b in enumerate(evgen.batches(c1.events, 500)[:20]):
+        if on_device:
+            r.push(*device_events(b), on_device=True)
+        else:
+            r.push(b.t, b.x, b.y, b.p)
+        o.push_events(b)
+        r.solve(50)
+        o.solve(50)
+        du, dp = u_p_errors(r, o)
+        worst_u, worst_p = max(worst_u, du), max(worst_p, dp)
+        s_max = max(s_max, float(radius(o).max()))
+        assert du <= U_TOL, (i, du)
+        assert dp <= P_RTOL, (i, dp)
+    if ts == 0.0:
+        assert not r.image(rec.REC_STATE_P)[2].any()
+        assert np.array_equal(r.image(rec.REC_METRIC_G), np.ones((128, 128), np.float32))
+    print(f"T_s={ts} device={on_device}: max|du| {worst_u:.3e}, max|dp|/s {worst_p:.3e}, "
+          f"max sqrt(G) {s_max:.1f}")
+    r.close()
+
+
+def test_davis240_u_and_p(c1):
+    """The benchmark stream's first 20 blocks through the benchmark path
+    (device pushes folded into the first fused launch): u and p."""
+    s, bs, _, iters = evgen.davis240(seed=2, duration_us=40_000)
+    r, o = make(240, 180)
+    worst = (0.0, 0.0)
+    for b in evgen.batches(s.events, bs)[:20]:
+        r.push(*device_events(b), on_device=True)
+        o.push_events(b)
+        r.solve(iters)
+        o.solve(iters)
+        du, dp = u_p_errors(r, o)
+        worst = (max(worst[0], du), max(worst[1], dp))
+        assert du <= U_TOL and dp <= P_RTOL, (du, dp)
+    print(f"240x180: max|du| {worst[0]:.3e}, max|dp|/s {worst[1]:.3e}")
+    r.close()
+
+
+@pytest.mark.parametrize("storage,bound", [(rec.REC_STORE_F32, U_TOL),
+                                           (rec.REC_STORE_F16, 2e-3)])
+def test_stream_longer_than_fp16_range(storage, bound):
+    """A stream spanning 80 s: pixels idle since the first block sit next to
+    pixels that fire 75 s later, so their time differences reach 75000 ms,
+    beyond FP16's largest value (65504).  FP16 storage saturates there
+    instead of overflowing to infinity; the image stays finite and within
+    the FP16 bound of the FP64 oracle (FP32 storage within 1e-4)."""
+    W, H = 48, 32
+    rng = np.random.default_rng(11)
+    blocks = []
+    for k, (t_lo, t_hi, x_hi) in enumerate([(0, 1_000_000, W), (75_000_000, 76_000_000, W // 2),
+                                            (79_000_000, 80_000_000, W // 3)]):
+        n = 400
+        t = evgen.T0_US + t_lo + np.sort(rng.integers(0, t_hi - t_lo, n)).astype(np.int64)
+        if k == 0:
+            x = rng.integers(0, W, n).astype(np.uint16)
+        else:
+            x = rng.integers(0, x_hi, n).astype(np.uint16)
+        y = rng.integers(0, H, n).astype(np.uint16)
+        p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+        blocks.append(evgen.Events(t, x, y, p, np.zeros(n, np.uint8)))
+    r, o = make(W, H, storage=storage)
+    big = 0.0
+    for b in blocks:
+        r.push(*device_events(b), on_device=True)
+        o.push_events(b)
+        r.solve(50)
+        o.solve(50)
+        big = max(big, float(np.abs(o.get(oracle.TX)).max()), float(np.abs(o.get(oracle.TY)).max()))
+        u = r.image(rec.REC_U)
+        assert np.isfinite(u).all() and np.isfinite(r.image(rec.REC_STATE_P)).all()
+        d = float(np.abs(u.astype(np.float64) - o.u).max())
+        assert d <= bound, d
+    assert big > 70000.0  # the stream does leave FP16's range
+    if storage == rec.REC_STORE_F16:
+        tx = r.image(rec.REC_TX)
+        assert np.isfinite(tx).all() and np.abs(tx).max() == np.float32(65504.0)
+    r.close()
+
+
+# --------------------------------------------------------------------------
+# Many cameras in one batched solve against the oracle
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def cams():
+    return evgen.streams64(3)
+
+
+def test_streams64_batch_against_oracle(cams):
+    """The 64-camera workload of the benchmark (16 each of 128x128, 240x180,
+    346x260, 640x480; autotuned batched solve, 50 iterations per block,
+    device pushes): after each of 3 blocks, one camera of every sensor size
+    against the FP64 oracle (u within 1e-4, p within 1e-4 sqrt(G))."""
+    recs = [rec.Reconstructor(W, H) for W, H, _, _ in cams]
+    batch = rec.Batch(recs, tune_iters=50)
+    print(f"streams64 batch config {batch.config()}", flush=True)
+    pick = [0, 16, 32, 48]
+    orcs = {i: oracle.Oracle(oracle.Params(cams[i][0], cams[i][1])) for i in pick}
+    for step in range(3):
+        for i, ((W, H, bs, ev), r) in enumerate(zip(cams, recs)):
+            b = ev.slice(step * bs, (step + 1) * bs)
+            r.push(*device_events(b), on_device=True)
+            if i in orcs:
+                orcs[i].push_events(b)
+        batch.solve(50)
+        for i, o in orcs.items():
+            o.solve(50)
+            du, dp = u_p_errors(recs[i], o)
+            print(f"  block {step} camera {i} ({cams[i][0]}x{cams[i][1]}): max|du| {du:.3e} "
+                  f"max|dp|/s {dp:.3e}")
+            assert du <= U_TOL and dp <= P_RTOL, (step, i, du, dp)
+    batch.close()
+    for r in recs:
+        r.close()

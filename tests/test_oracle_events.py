@@ -159,3 +159,25 @@ def test_gap_goes_to_zero_on_stream_block(c1):
     assert g[-1] < 0.25 * g[0]
     assert g[-1] < 1e-6 * e[-1]
     assert (np.diff(e) <= 1e-9 * e[0]).all()
+
+
+def test_threaded_oracle_build_gives_the_same_bits():
+    """The OpenMP build of the oracle (the CPU baseline on all host cores)
+    computes every pixel with the same operations and keeps the gap sum
+    serial: u, p, f, the time differences and the gap history equal the
+    single-threaded build's bit for bit."""
+    s, bs, _, iters = evgen.dvs128(seed=1, n_batches=3)
+    outs = []
+    for threads in (False, True):
+        o = oracle.Oracle(oracle.Params(128, 128), threads=threads)
+        hist = []
+        for b in evgen.batches(s.events, bs)[:3]:
+            o.push_events(b)
+            g, e = o.solve(iters, gap_every=10)
+            hist.append((g, e))
+        outs.append((o.u, o.p, o.get(oracle.F), o.get(oracle.TX), hist))
+        o.close()
+    for a, b in zip(outs[0][:4], outs[1][:4]):
+        assert np.array_equal(a, b)
+    for (g0, e0), (g1, e1) in zip(outs[0][4], outs[1][4]):
+        assert np.array_equal(g0, g1) and np.array_equal(e0, e1)
