@@ -641,7 +641,8 @@ def bench_dvs128(n_blocks=200, warmup=20):
     import evgen
     from paper_1607_06283_amd import rec
 
-    s, bs, nb, iters = evgen.dvs128(seed=1, n_batches=n_blocks + warmup)
+    n_lat = 50
+    s, bs, nb, iters = evgen.dvs128(seed=1, n_batches=n_blocks + warmup + n_lat)
     ev = s.events
     dev = torch.device("cuda", 0)
     t = torch.from_numpy(ev.t).to(dev)
@@ -669,7 +670,7 @@ def bench_dvs128(n_blocks=200, warmup=20):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     lat = []
-    for i in range(warmup, warmup + 50):
+    for i in range(warmup + n_blocks, warmup + n_blocks + n_lat):
         t1 = time.perf_counter()
         step(i)
         torch.cuda.synchronize()

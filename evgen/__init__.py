@@ -346,3 +346,21 @@ def streams64(steps: int, seed: int = 400, sizes=None, per_size: int = 16):
         p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
         cams.append((W, H, bs, Events(t, x, y, p, np.zeros(n, np.uint8))))
     return cams
+
+
+def long_idle_blocks(width: int = 48, height: int = 32, seed: int = 11, n: int = 400):
+    """Three blocks of uniform random events spanning 80 s: the whole frame
+    fires in the first second, then only the left half at 75 s and the left
+    third at 79 s, so pixels idle since the first second border pixels that
+    fire 75 s later (time differences of ~75000 in milliseconds)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k, (t_lo, t_hi, x_hi) in enumerate([(0, 1_000_000, width),
+                                            (75_000_000, 76_000_000, width // 2),
+                                            (79_000_000, 80_000_000, width // 3)]):
+        t = T0_US + t_lo + np.sort(rng.integers(0, t_hi - t_lo, n)).astype(np.int64)
+        x = rng.integers(0, width if k == 0 else x_hi, n).astype(np.uint16)
+        y = rng.integers(0, height, n).astype(np.uint16)
+        p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+        out.append(Events(t, x, y, p, np.zeros(n, np.uint8)))
+    return out

@@ -41,6 +41,7 @@ class _P(ctypes.Structure):
         ("u_init", ctypes.c_double),
         ("tvl1_iters", ctypes.c_int32),
         ("tvl1_lambda", ctypes.c_double),
+        ("slope_cap", ctypes.c_double),
     ]
 
 
@@ -59,11 +60,14 @@ class Params:
     u_init: float = math.exp(0.5)
     tvl1_iters: int = 0
     tvl1_lambda: float = 1.0
+    # > 0: time differences clipped to [-slope_cap, slope_cap] (the reading
+    # of 16-bit storage, whose largest FP16 value is 65504); 0: none
+    slope_cap: float = 0.0
 
     def _c(self) -> _P:
         return _P(self.width, self.height, self.lam, self.delta_pos, self.delta_neg,
                   self.u_min, self.u_max, self.tau, self.sigma, self.time_unit_us, self.u_init,
-                  self.tvl1_iters, self.tvl1_lambda)
+                  self.tvl1_iters, self.tvl1_lambda, self.slope_cap)
 
 
 def build(force: bool = True) -> str:

@@ -44,6 +44,9 @@
  *     Chambolle-Pock iterations for  min_v TV(v) + lambda_t |v - tau|_1
  *     started at v = tau, dual 0, steps 1/sqrt(8), before the differences
  *     are taken.
+ *   - Optional slope cap (not in the paper; off by default): the time
+ *     differences are clipped to [-cap, cap], the reading used for storage
+ *     formats of bounded range (FP16 saturates at 65504).
  *
  * Optional per-pixel data weights w (not in the paper; they make the data
  * term lambda sum w (u - f log u) sqrt(G) and are the weights a learned
@@ -84,6 +87,7 @@ typedef struct {
     double u_init;
     int32_t tvl1_iters;    /* timestamp denoising iterations; 0 = off */
     double tvl1_lambda;    /* its L1 data weight */
+    double slope_cap;      /* > 0: time differences clipped to [-cap, cap]; 0 = none */
 } orc_params;
 
 typedef struct {
@@ -104,6 +108,17 @@ typedef struct {
 /* ------------------------------------------------------------------ */
 /* Operators                                                           */
 /* ------------------------------------------------------------------ */
+
+/* A time difference limited to [-cap, cap] (cap = 0: unlimited).  Not in
+ * the paper: it models storing the differences in a format whose largest
+ * finite value is cap (FP16: 65504), which saturates instead of overflowing. */
+static double clip_slope(double d, double cap) {
+    if (cap > 0.0) {
+        if (d > cap) return cap;
+        if (d < -cap) return -cap;
+    }
+    return d;
+}
 
 /* Forward differences with zero on the last column / row (Chambolle 2004). */
 void orc_grad(int W, int H, const double* v, double* gx, double* gy) {
@@ -243,6 +258,7 @@ int orc_check_params(const orc_params* P) {
     if (!(P->u_init > 0.0) || !isfinite(P->u_init)) return ORC_EINVAL;
     if (P->tvl1_iters < 0) return ORC_EINVAL;
     if (P->tvl1_iters > 0 && !(P->tvl1_lambda > 0.0)) return ORC_EINVAL;
+    if (!(P->slope_cap >= 0.0)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -347,8 +363,8 @@ void orc_build(orc_state* S) {
         for (int i = 0; i < H; ++i)
             for (int j = 0; j < W; ++j) {
                 size_t k = (size_t)i * W + j;
-                S->tx[k] = (j < W - 1) ? v[k + 1] - v[k] : 0.0;
-                S->ty[k] = (i < H - 1) ? v[k + W] - v[k] : 0.0;
+                S->tx[k] = clip_slope((j < W - 1) ? v[k + 1] - v[k] : 0.0, S->P.slope_cap);
+                S->ty[k] = clip_slope((i < H - 1) ? v[k + W] - v[k] : 0.0, S->P.slope_cap);
                 S->tx32[k] = (float)S->tx[k];
                 S->ty32[k] = (float)S->ty[k];
             }
@@ -368,8 +384,8 @@ void orc_build(orc_state* S) {
                 int64_t td = S->t_last[k + W] == ORC_NEVER ? S->t_first : S->t_last[k + W];
                 dy = (double)(tl - td) / Ts;   /* tau(i+1) - tau(i) */
             }
-            S->tx[k] = dx;
-            S->ty[k] = dy;
+            S->tx[k] = dx = clip_slope(dx, S->P.slope_cap);
+            S->ty[k] = dy = clip_slope(dy, S->P.slope_cap);
             S->tx32[k] = (float)dx;
             S->ty32[k] = (float)dy;
         }

@@ -16,7 +16,7 @@ import evgen
 import oracle
 from paper_1607_06283_amd import rec
 
-from gpu_helpers import P_RTOL, U_TOL, device_events, make, radius, u_p_errors
+from gpu_helpers import U_TOL, device_events, make, p_tol, radius, u_p_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -39,8 +39,8 @@ def c1():
 @pytest.mark.parametrize("on_device", [False, True])
 def test_u_and_p_across_time_units(c1, ts, on_device):
     """128x128, 20 blocks of 500 events, 50 iterations each: after every
-    block u within 1e-4 and p within 1e-4 * sqrt(G) of the FP64 oracle, at
-    every time unit; at T_s = 0 the third dual component stays 0 (the flat
+    block u within 1e-4 and p within the FP32 rounding bound p_tol (relative
+    to sqrt(G)) of the FP64 oracle, at every time unit; at T_s = 0 the third dual component stays 0 (the flat
     manifold carries the standard 2-component TV-KL dual)."""
     r, o = make(128, 128, time_unit_us=ts)
     worst_u = worst_p = 0.0
@@ -57,7 +57,7 @@ def test_u_and_p_across_time_units(c1, ts, on_device):
         worst_u, worst_p = max(worst_u, du), max(worst_p, dp)
         s_max = max(s_max, float(radius(o).max()))
         assert du <= U_TOL, (i, du)
-        assert dp <= P_RTOL, (i, dp)
+        assert dp <= p_tol(50 * (i + 1)), (i, dp)
     if ts == 0.0:
         assert not r.image(rec.REC_STATE_P)[2].any()
         assert np.array_equal(r.image(rec.REC_METRIC_G), np.ones((128, 128), np.float32))
@@ -72,14 +72,14 @@ def test_davis240_u_and_p(c1):
     s, bs, _, iters = evgen.davis240(seed=2, duration_us=40_000)
     r, o = make(240, 180)
     worst = (0.0, 0.0)
-    for b in evgen.batches(s.events, bs)[:20]:
+    for i, b in enumerate(evgen.batches(s.events, bs)[:20]):
         r.push(*device_events(b), on_device=True)
         o.push_events(b)
         r.solve(iters)
         o.solve(iters)
         du, dp = u_p_errors(r, o)
         worst = (max(worst[0], du), max(worst[1], dp))
-        assert du <= U_TOL and dp <= P_RTOL, (du, dp)
+        assert du <= U_TOL and dp <= p_tol(iters * (i + 1)), (i, du, dp)
     print(f"240x180: max|du| {worst[0]:.3e}, max|dp|/s {worst[1]:.3e}")
     r.close()
 
@@ -90,39 +90,36 @@ def test_stream_longer_than_fp16_range(storage, bound):
     """A stream spanning 80 s: pixels idle since the first block sit next to
     pixels that fire 75 s later, so their time differences reach 75000 ms,
     beyond FP16's largest value (65504).  FP16 storage saturates there
-    instead of overflowing to infinity; the image stays finite and within
-    the FP16 bound of the FP64 oracle (FP32 storage within 1e-4)."""
+    instead of overflowing to infinity: the image stays finite and within the
+    FP16 bound of the FP64 oracle that clips the differences the same way
+    (FP32 storage: within 1e-4 of the plain oracle).  The clipping itself
+    moves the oracle's u by up to 2.6e-3 on this stream (printed)."""
     W, H = 48, 32
-    rng = np.random.default_rng(11)
-    blocks = []
-    for k, (t_lo, t_hi, x_hi) in enumerate([(0, 1_000_000, W), (75_000_000, 76_000_000, W // 2),
-                                            (79_000_000, 80_000_000, W // 3)]):
-        n = 400
-        t = evgen.T0_US + t_lo + np.sort(rng.integers(0, t_hi - t_lo, n)).astype(np.int64)
-        if k == 0:
-            x = rng.integers(0, W, n).astype(np.uint16)
-        else:
-            x = rng.integers(0, x_hi, n).astype(np.uint16)
-        y = rng.integers(0, H, n).astype(np.uint16)
-        p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
-        blocks.append(evgen.Events(t, x, y, p, np.zeros(n, np.uint8)))
+    prm_cap = 65504.0 if storage == rec.REC_STORE_F16 else 0.0
     r, o = make(W, H, storage=storage)
-    big = 0.0
-    for b in blocks:
+    oc = oracle.Oracle(oracle.Params(W, H, slope_cap=prm_cap))
+    big = cap_effect = 0.0
+    for b in evgen.long_idle_blocks(W, H):
         r.push(*device_events(b), on_device=True)
-        o.push_events(b)
+        for q in (o, oc):
+            q.push_events(b)
+            q.solve(50)
         r.solve(50)
-        o.solve(50)
         big = max(big, float(np.abs(o.get(oracle.TX)).max()), float(np.abs(o.get(oracle.TY)).max()))
+        cap_effect = max(cap_effect, float(np.abs(o.u - oc.u).max()))
         u = r.image(rec.REC_U)
         assert np.isfinite(u).all() and np.isfinite(r.image(rec.REC_STATE_P)).all()
-        d = float(np.abs(u.astype(np.float64) - o.u).max())
+        d = float(np.abs(u.astype(np.float64) - oc.u).max())
         assert d <= bound, d
     assert big > 70000.0  # the stream does leave FP16's range
     if storage == rec.REC_STORE_F16:
         tx = r.image(rec.REC_TX)
         assert np.isfinite(tx).all() and np.abs(tx).max() == np.float32(65504.0)
+    print(f"storage {storage}: max|du| vs oracle {d:.3e}; effect of clipping on the oracle "
+          f"{cap_effect:.3e}")
     r.close()
+    o.close()
+    oc.close()
 
 
 # --------------------------------------------------------------------------
@@ -138,7 +135,7 @@ def test_streams64_batch_against_oracle(cams):
     """The 64-camera workload of the benchmark (16 each of 128x128, 240x180,
     346x260, 640x480; autotuned batched solve, 50 iterations per block,
     device pushes): after each of 3 blocks, one camera of every sensor size
-    against the FP64 oracle (u within 1e-4, p within 1e-4 sqrt(G))."""
+    against the FP64 oracle (u within 1e-4, p within p_tol sqrt(G))."""
     recs = [rec.Reconstructor(W, H) for W, H, _, _ in cams]
     batch = rec.Batch(recs, tune_iters=50)
     print(f"streams64 batch config {batch.config()}", flush=True)
@@ -156,7 +153,7 @@ def test_streams64_batch_against_oracle(cams):
             du, dp = u_p_errors(recs[i], o)
             print(f"  block {step} camera {i} ({cams[i][0]}x{cams[i][1]}): max|du| {du:.3e} "
                   f"max|dp|/s {dp:.3e}")
-            assert du <= U_TOL and dp <= P_RTOL, (step, i, du, dp)
+            assert du <= U_TOL and dp <= p_tol(50 * (step + 1)), (step, i, du, dp)
     batch.close()
     for r in recs:
         r.close()

@@ -181,3 +181,33 @@ def test_threaded_oracle_build_gives_the_same_bits():
         assert np.array_equal(a, b)
     for (g0, e0), (g1, e1) in zip(outs[0][4], outs[1][4]):
         assert np.array_equal(g0, g1) and np.array_equal(e0, e1)
+
+
+def test_slope_cap_reading(c1):
+    """The slope cap (the reading of 16-bit storage, which saturates at
+    65504) clips the time differences and nothing else: with a cap above
+    every difference the oracle gives the same bits as without one; on a
+    stream whose differences exceed the cap, the capped differences are the
+    plain ones clipped, the image stays finite, and it differs from the
+    plain oracle's only where the problem changed."""
+    blocks = evgen.batches(c1.events, 500)[:3]
+    o, oc = Oracle(Params(128, 128)), Oracle(Params(128, 128, slope_cap=1e9))
+    for b in blocks:
+        for q in (o, oc):
+            q.push_events(b)
+            q.solve(20)
+    assert np.array_equal(o.u, oc.u) and np.array_equal(o.p, oc.p)
+    assert np.array_equal(o.get(oracle.TX), oc.get(oracle.TX))
+    cap = 65504.0
+    o, oc = Oracle(Params(48, 32)), Oracle(Params(48, 32, slope_cap=cap))
+    for b in evgen.long_idle_blocks(48, 32):
+        for q in (o, oc):
+            q.push_events(b)
+            q.solve(50)
+        for plane in (oracle.TX, oracle.TY):
+            plain = o.get(plane)
+            assert np.array_equal(oc.get(plane), np.clip(plain, -cap, cap))
+        assert np.isfinite(oc.u).all()
+    assert np.abs(o.get(oracle.TX)).max() > 70000.0
+    assert 0.0 < np.abs(o.u - oc.u).max() < 1e-2
+    assert oracle.check_params(Params(8, 8, slope_cap=-1.0)) == oracle.EINVAL
