@@ -57,7 +57,9 @@
  *     next synchronising call; the rejected push changes no state.
  *
  * Threading: a context must not be used from two threads at once; distinct
- * contexts are independent.  The library has no global mutable state.
+ * contexts are independent.  The only global state of the library is the
+ * static device array of rec_diff_forward_noalloc and the per-device
+ * address of it that the library looks up once (see there).
  */
 #ifndef REC_H
 #define REC_H
@@ -79,7 +81,8 @@ enum {
     REC_ENUMERIC = -5, /* non-finite gap or energy */
     REC_ESTATE = -6,   /* call not valid in the object's state: rec_destroy of a
                           context that a live batch still holds */
-    REC_ENOMEM = -7    /* workspace too small or host allocation failed */
+    REC_ENOMEM = -7    /* workspace too small, host allocation failed, or input larger
+                          than the static array of rec_diff_forward_noalloc */
 };
 
 /* Planes readable with rec_get_image. */
@@ -379,6 +382,24 @@ size_t rec_diff_workspace_bytes(const rec_diff_desc* d);
  * The outputs must not alias the inputs or the workspace. */
 int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
                      float* p_out, void* dev_workspace, size_t ws_bytes, void* stream);
+
+/* Forward without any device allocation or workspace, for callers that
+ * cannot allocate: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same descriptor, inputs and outputs as
+ * rec_diff_forward and the same bits of (u_K, p_K), but no checkpoints are
+ * kept (ckpt_every is validated and otherwise ignored), so no
+ * rec_diff_backward can follow it.  The data image and two ping-pong
+ * states live in a static device array of 36 MiB that every device the
+ * library runs on holds until the process ends; it takes at most
+ * width * height * batch <= 1048576 pixels per call (REC_ENOMEM beyond
+ * that; split the batch).  The array is shared by all calls on a device
+ * and keeps the last call's contents: calls that overlap in time on one
+ * device (different streams or threads) race and must be ordered by the
+ * caller.  Enqueued on `stream`, no synchronisation.  REC_EINVAL for a bad
+ * descriptor or a missing required pointer, REC_EDEVICE if the array's
+ * address cannot be found or a launch fails. */
+int rec_diff_forward_noalloc(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
+                             float* p_out, void* stream);
 
 /* Backward: g_u = dJ/du_K [B][H][W] and g_p = dJ/dp_K [B][3][H][W] (either
  * may be NULL for zero); the gradients requested in `out` are overwritten.

@@ -47,6 +47,8 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <atomic>
+
 #include "pd_math.h"
 #include "rec.h"
 #include "tile.h"
@@ -877,21 +879,27 @@ void fwd_fused(const Ctx& x, State a, State b, int K, Trail rec) {
                            x.cv.f, in->tx, in->ty, in->w, in->theta, x.st);
 }
 
-int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size_t bytes,
-               Ctx& x) {
-    if (!desc_ok(d) || !in || !in->u0 || !in->npos || !in->nneg || !in->tx || !in->ty ||
-        !in->theta)
-        return REC_EINVAL;
-    if (!ws || ((uintptr_t)ws % kAlign) != 0) return REC_EINVAL;
-    x.d = d;
-    x.in = in;
-    x.cv = carve(d, (char*)ws);
-    if (bytes < x.cv.bytes) return REC_ENOMEM;
+bool inputs_ok(const rec_diff_desc* d, const rec_diff_inputs* in) {
+    return desc_ok(d) && in && in->u0 && in->npos && in->nneg && in->tx && in->ty && in->theta;
+}
+
+void set_consts(const rec_diff_desc* d, Ctx& x) {
     x.dims = Dims{d->width, d->height, (size_t)d->width * d->height};
     x.st = Steps{d->tau, (float)(d->tau / d->sigma), (float)d->sigma, (float)d->u_min,
                  (float)d->u_max, d->iters > 0 ? 1 : 0};
     x.grid = grid_of(d);
     x.fs = fused_shape(d);
+}
+
+int check_call(const rec_diff_desc* d, const rec_diff_inputs* in, void* ws, size_t bytes,
+               Ctx& x) {
+    if (!inputs_ok(d, in)) return REC_EINVAL;
+    if (!ws || ((uintptr_t)ws % kAlign) != 0) return REC_EINVAL;
+    x.d = d;
+    x.in = in;
+    x.cv = carve(d, (char*)ws);
+    if (bytes < x.cv.bytes) return REC_ENOMEM;
+    set_consts(d, x);
     return REC_OK;
 }
 
@@ -947,6 +955,36 @@ void rev_fused(const Ctx& x, StateOf state_of, int j0, int jtop, const float* g_
     side ^= 1;
 }
 
+// The forward that allocates nothing (rec_diff_forward_noalloc) keeps the
+// data image and two ping-pong states (u and the three planes of p) of at
+// most kScratchPixels pixels in this file-scope array: 9 planes of 4 MiB.
+// Each device holds its own copy, at its own address, until the process
+// ends; host code uses the address hipGetSymbolAddress returns for the
+// current device, never the array's name.
+constexpr size_t kScratchPixels = size_t(1) << 20;
+constexpr size_t kScratchPlanes = 9;
+constexpr size_t kScratchBytes = kScratchPlanes * kScratchPixels * sizeof(float);
+static_assert(kScratchPixels * sizeof(float) % kAlign == 0, "planes stay 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch_addr[kMaxDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (two threads racing on the first lookup store the same address).
+int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return REC_EDEVICE;
+    void* p = g_scratch_addr[dev].load(std::memory_order_acquire);
+    if (!p) {
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return REC_EDEVICE;
+        g_scratch_addr[dev].store(p, std::memory_order_release);
+    }
+    *out = p;
+    return REC_OK;
+}
+
 }  // namespace
 }  // namespace rec
 
@@ -993,6 +1031,50 @@ int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u
     }
     hipLaunchKernelGGL(k_diff_out, x.grid, dim3(kThreads), 0, x.s, x.dims,
                        at(x.cv.ck0, x.cv.state_floats, C), in->tx, in->ty, x.st.rot, u_out, p_out);
+    return hipGetLastError() == hipSuccess ? REC_OK : REC_EDEVICE;
+}
+
+int rec_diff_forward_noalloc(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
+                             float* p_out, void* stream) {
+    if (!inputs_ok(d, in) || !u_out) return REC_EINVAL;
+    const size_t n = (size_t)d->width * d->height * d->batch;
+    if (n > kScratchPixels) return REC_ENOMEM;
+    void* base = nullptr;
+    const int rc = scratch_address(&base);
+    if (rc != REC_OK) return rc;
+    Ctx x;
+    x.d = d;
+    x.in = in;
+    set_consts(d, x);
+    x.s = (hipStream_t)stream;
+    // f | state 0 | state 1, each state u and p1..p3 (planes of n floats,
+    // 256-byte aligned; every value is written before it is read, so no
+    // earlier call's contents matter)
+    const size_t plane = align_up(n * sizeof(float));
+    char* b = (char*)base;
+    x.cv = Carve{};
+    x.cv.f = (float*)b;
+    x.cv.state_floats = 4 * plane / sizeof(float);
+    x.cv.ck0 = State{(float*)(b + plane), (float*)(b + 2 * plane)};
+    const size_t sf = x.cv.state_floats;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(k_diff_init, x.grid, dim3(kThreads), 0, x.s, x.dims, in->u0, in->p0,
+                       in->npos, in->nneg, in->theta, in->tx, in->ty, x.st.rot, x.cv.f, x.cv.ck0);
+    int side = 0;
+    for (int a = 0; a < d->iters;) {
+        const State from = at(x.cv.ck0, sf, side), to = at(x.cv.ck0, sf, side ^ 1);
+        int K = 1;
+        if (d->unfused) {
+            step(x, from, to);
+        } else {
+            K = d->iters - a < x.fs.fk ? d->iters - a : x.fs.fk;
+            fwd_fused(x, from, to, K, Trail{nullptr, nullptr, 0});
+        }
+        a += K;
+        side ^= 1;
+    }
+    hipLaunchKernelGGL(k_diff_out, x.grid, dim3(kThreads), 0, x.s, x.dims, at(x.cv.ck0, sf, side),
+                       in->tx, in->ty, x.st.rot, u_out, p_out);
     return hipGetLastError() == hipSuccess ? REC_OK : REC_EDEVICE;
 }
 

@@ -773,7 +773,7 @@ const char* rec_strerror(int code) {
         case REC_EDEVICE: return "HIP runtime error";
         case REC_ENUMERIC: return "non-finite gap or energy";
         case REC_ESTATE: return "call not valid in the current state";
-        case REC_ENOMEM: return "workspace too small or allocation failed";
+        case REC_ENOMEM: return "workspace too small, allocation failed, or input beyond a static scratch limit";
         default: return "unknown status code";
     }
 }

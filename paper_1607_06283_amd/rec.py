@@ -75,6 +75,7 @@ EXPORTS = (
     "rec_sync", "rec_profile", "rec_profile_read", "rec_destroy", "rec_strerror",
     "rec_batch_workspace_bytes", "rec_batch_init", "rec_batch_solve", "rec_batch_config",
     "rec_batch_destroy", "rec_diff_workspace_bytes", "rec_diff_forward", "rec_diff_backward",
+    "rec_diff_forward_noalloc",
 )
 
 
@@ -155,6 +156,8 @@ def load() -> ctypes.CDLL:
     lib.rec_diff_forward.restype = ctypes.c_int
     lib.rec_diff_forward.argtypes = [D, ctypes.POINTER(rec_diff_inputs), _vp, _vp, _vp,
                                      ctypes.c_size_t, _vp]
+    lib.rec_diff_forward_noalloc.restype = ctypes.c_int
+    lib.rec_diff_forward_noalloc.argtypes = [D, ctypes.POINTER(rec_diff_inputs), _vp, _vp, _vp]
     lib.rec_diff_backward.restype = ctypes.c_int
     lib.rec_diff_backward.argtypes = [D, ctypes.POINTER(rec_diff_inputs), _vp, _vp,
                                       ctypes.POINTER(rec_diff_grads), _vp, ctypes.c_size_t, _vp]
@@ -473,6 +476,12 @@ def rec_diff_forward(desc: rec_diff_desc, inputs: rec_diff_inputs, u_out, p_out,
                      workspace_bytes: int, stream_ptr) -> int:
     return load().rec_diff_forward(ctypes.byref(desc), ctypes.byref(inputs), _addr(u_out),
                                    _addr(p_out), workspace_ptr, int(workspace_bytes), stream_ptr)
+
+
+def rec_diff_forward_noalloc(desc: rec_diff_desc, inputs: rec_diff_inputs, u_out, p_out,
+                             stream_ptr) -> int:
+    return load().rec_diff_forward_noalloc(ctypes.byref(desc), ctypes.byref(inputs),
+                                           _addr(u_out), _addr(p_out), stream_ptr)
 
 
 def rec_diff_backward(desc: rec_diff_desc, inputs: rec_diff_inputs, g_u, g_p,
