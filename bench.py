@@ -47,10 +47,10 @@ MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
     ("davis240", "f32"): ("bc17ad4b7dc66c01", 2 * 1024 * 1070.5, 1024 * 820.7),
     ("probe", "f32"): ("bc17ad4b7dc66c01", 2 * 1024 * 553321.7, 1024 * 546294.9),
-    # the batched launch of all 64 cameras, 6 rows x 8 wavefronts, 6 iterations
-    ("streams64", "f32"): ("bc17ad4b7dc66c01", 2 * 1024 * 99517.6, 1024 * 130221.6),
+    # the batched solve of all 64 cameras: bytes of one whole solve (every
+    # launch of every class chain), for the class geometries below
 }
-STREAMS64_MEASURED_SHAPE = (6, 8, 6)
+STREAMS64_MEASURED_SHAPE = None  # class geometries the counters were taken with
 
 
 def kernel_source_hash() -> str:
@@ -188,21 +188,32 @@ def streams64(steps, seed=400):
     return evgen.streams64(steps, seed)
 
 
-def run_streams64(steps, warmup, iters, batched, profile, tune=True):
-    """Time `steps` blocks of all 64 cameras; batched or one solve per camera."""
+BATCH_MODES = {"serial": 0, "streams": 1, "graph": 2}
+
+
+def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph")):
+    """Time `steps` blocks of all 64 cameras: the batched solve in each of
+    `modes` (each pass after 2 warm-up blocks of its own; the first listed
+    is also profiled), then one solve per camera.  Returns per-pass seconds,
+    the profile of the first mode, the class configuration, the pixel count
+    and the events per block."""
     import torch
     from paper_1607_06283_amd import rec
 
-    cams = streams64(warmup + steps)
+    passes = len(modes) + 2  # the modes, the profiled pass, the per-camera solves
+    cams = streams64(warmup + passes * (steps + 2))
     dev = torch.device("cuda", 0)
     recs, bufs = [], []
     for W, H, bs, ev in cams:
         recs.append(rec.Reconstructor(W, H))
         bufs.append((torch.from_numpy(ev.t).to(dev), torch.from_numpy(ev.x.view(np.int16)).to(dev),
                      torch.from_numpy(ev.y.view(np.int16)).to(dev), torch.from_numpy(ev.p).to(dev), bs))
-    batch = rec.Batch(recs, tune_iters=iters if tune else 0) if batched else None
+    batch = rec.Batch(recs, tune_iters=iters if tune else 0)
+    block = [0]
 
-    def step(i):
+    def step(batched):
+        i = block[0]
+        block[0] += 1
         for r, (t, x, y, p, bs) in zip(recs, bufs):
             a = i * bs
             rc = rec.rec_push_events(r.ctx, t.data_ptr() + 8 * a, x.data_ptr() + 2 * a,
@@ -217,25 +228,81 @@ def run_streams64(steps, warmup, iters, batched, profile, tune=True):
                 if rc:
                     raise rec.RecError(rc, "rec_solve")
 
-    for i in range(warmup):
-        step(i)
-    torch.cuda.synchronize()
-    if profile:
-        rec.rec_profile(recs[0].ctx, True)
-    t0 = time.perf_counter()
-    for i in range(warmup, warmup + steps):
-        step(i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = rec.rec_profile_read(recs[0].ctx) if profile else None
-    cfg = batch.config() if batch else None
+    def timed_pass(batched, n_warm=2):
+        for _ in range(n_warm):
+            step(batched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(batched)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for _ in range(warmup):
+        step(True)
+    out = {}
+    for m in modes:
+        batch.set_mode(BATCH_MODES[m])
+        out[m] = timed_pass(True)
+    batch.set_mode(BATCH_MODES[modes[0]])
+    rec.rec_profile(recs[0].ctx, True)
+    timed_pass(True)
+    prof = rec.rec_profile_read(recs[0].ctx)
+    rec.rec_profile(recs[0].ctx, False)
+    out["per_camera"] = timed_pass(False)
+    cfg = batch.config()
     px = sum(W * H for W, H, _, _ in cams)
     ev_per_step = sum(bs for _, _, bs, _ in cams)
-    if batch:
-        batch.close()
+    batch.close()
     for r in recs:
         r.close()
-    return dt, prof, cfg, px, ev_per_step
+    return out, prof, cfg, px, ev_per_step
+
+
+def streams64_result(steps, warmup, iters, tune=True):
+    """The 64-camera workload: the batched solve in its default mode (the
+    first of the timed modes) with the other modes and one solve per camera
+    beside it, the class geometries, and the roofline of the batched launch."""
+    dts, prof, cfg, px, evs = run_streams64(steps, warmup, iters, tune=tune)
+    dt = dts["streams"]
+    rate = lambda d: round(steps * iters * px / d / 1e6, 2)
+    res = {
+        "value": rate(dt), "ms_per_step": round(dt / steps * 1e3, 4),
+        "events_per_s": round(steps * evs / dt, 1),
+        "modes": {m: {"PD iter*Mpix/s": rate(d), "ms_per_step": round(d / steps * 1e3, 4)}
+                  for m, d in dts.items() if m != "per_camera"},
+        "per_camera_solves": {"PD iter*Mpix/s": rate(dts["per_camera"]),
+                              "ms_per_step": round(dts["per_camera"] / steps * 1e3, 4)},
+        "batched_speedup": round(dts["per_camera"] / dt, 3),
+        "classes": [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in c.items()}
+                    for c in cfg],
+        "roofline": batch_roofline(dt / steps, px * iters, cfg, prof),
+    }
+    return res
+
+
+def batch_roofline(step_s, px_iters, cfg, prof):
+    """Roofline of the batched solve, whose class chains run concurrently:
+    algorithmic bytes (44 per pixel-iteration) of one solve over the wall
+    time of one solve; traffic = the counters' HBM bytes of one solve (all
+    class launches) over the same time, when they were taken for these
+    sources and class geometries.  The per-launch kernel times (events in
+    the launch packets, overlapping across classes) are given beside it."""
+    achieved = BYTES_PER_PX_ITER * px_iters / step_s / 1e9
+    shapes = [(c["rows"], c["waves"], c["cols"], c["kiters"]) for c in cfg]
+    m = MEASURED_TRAFFIC.get(("streams64", "f32"))
+    traffic = None
+    if m and m[0] == kernel_source_hash() and shapes == STREAMS64_MEASURED_SHAPE:
+        traffic = round((m[1] + m[2]) / step_s / 1e9, 1)
+    solves = max(1.0, prof.pd_pixel_iters / px_iters)
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_frac": None if traffic is None else round(traffic / HBM_PEAK_GBS, 4),
+            "kernel": "k_pd_fused_batch, all class chains of one solve (wall time per solve)",
+            "bytes_per_px_iter": BYTES_PER_PX_ITER,
+            "algorithmic_bytes_per_solve": BYTES_PER_PX_ITER * px_iters,
+            "kernel_us_sum_per_solve": round(prof.ms[2] * 1e3 / solves, 1),
+            "launches_per_solve": round(prof.launches[2] / solves, 2)}
 
 
 def host_cpu_model() -> str:
@@ -349,29 +416,17 @@ def main_streams64(args):
     steps = min(args.steps, 40)
     warmup = min(args.warmup, 5)
     IT = WORKLOADS["streams64"][3]
-    log("bench: 64 cameras, batched")
-    tune = not args.no_tune
-    dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False, tune=tune)
-    _, prof, cfg_p, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True, tune=tune)
-    log("bench: 64 cameras, one solve per camera")
-    dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
-    value = steps * IT * px / dt / 1e6
+    log("bench: 64 cameras (batched in each mode, then one solve per camera)")
+    r = streams64_result(steps, warmup, IT, tune=not args.no_tune)
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "PD iter*Mpix/s", "n_gpus": 1,
-        "steps": steps, "warmup": warmup, "ms_per_step": round(dt / steps * 1e3, 4),
+        "metric": METRIC, "value": r.pop("value"), "unit": "PD iter*Mpix/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": r.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "storage": "f32", "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT["streams64"], "cameras": 64, "pixels": px,
-                   "events_per_step": evs, "iters_per_batch": IT,
-                   "tile_rows": cfg[0], "tile_waves": cfg[1], "fuse_iters": cfg[2],
-                   "autotuned": tune},
-        "events_per_s": round(steps * evs / dt, 1),
-        "per_camera_solves": {"value": round(steps * IT * px / dt_solo / 1e6, 2),
-                              "ms_per_step": round(dt_solo / steps * 1e3, 4)},
-        "batched_speedup": round(dt_solo / dt, 3),
-        "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused_batch", ("streams64", "f32"),
-                             tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE),
+        "config": {"workload": WORKLOAD_TEXT["streams64"], "cameras": 64,
+                   "iters_per_batch": IT, "autotuned": not args.no_tune},
     }
+    out.update(r)
     print(json.dumps(out), flush=True)
 
 
@@ -688,20 +743,12 @@ def bench_dvs128(n_blocks=200, warmup=20):
 
 
 def bench_streams64(steps=20, warmup=3):
-    """64 cameras batched (autotuned), against one solve per camera."""
+    """64 cameras batched (autotuned), each launch mode, against one solve per camera."""
     IT = WORKLOADS["streams64"][3]
-    dt, _, cfg, px, evs = run_streams64(steps, warmup, IT, batched=True, profile=False)
-    _, prof, cfg_p, _, _ = run_streams64(steps, warmup, IT, batched=True, profile=True)
-    dt_solo, _, _, _, _ = run_streams64(steps, warmup, IT, batched=False, profile=False)
-    return {"workload": WORKLOAD_TEXT["streams64"], "steps": steps, "warmup": warmup,
-            "PD iter*Mpix/s": round(steps * IT * px / dt / 1e6, 2),
-            "ms_per_step": round(dt / steps * 1e3, 4), "events_per_s": round(steps * evs / dt, 1),
-            "config": {"tile_rows": cfg[0], "tile_waves": cfg[1], "fuse_iters": cfg[2]},
-            "per_camera_solves": {"PD iter*Mpix/s": round(steps * IT * px / dt_solo / 1e6, 2),
-                                  "ms_per_step": round(dt_solo / steps * 1e3, 4)},
-            "batched_speedup": round(dt_solo / dt, 3),
-            "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused_batch", ("streams64", "f32"),
-                                 tuple(cfg_p[:3]) == STREAMS64_MEASURED_SHAPE)}
+    r = streams64_result(steps, warmup, IT)
+    r = {"workload": WORKLOAD_TEXT["streams64"], "steps": steps, "warmup": warmup,
+         "PD iter*Mpix/s": r.pop("value"), **r}
+    return r
 
 
 def bench_probe(steps=10, warmup=2):

@@ -42,9 +42,11 @@
  * Streams and synchronisation
  *   - All device work of a context -- pushes, builds, iterations, gap
  *     evaluations and readbacks -- is enqueued in order on the one
- *     hipStream_t given to rec_init (NULL = the default stream); the library
- *     creates no stream of its own.  Work the caller enqueues on that stream
- *     after a call returns is ordered after that call's work.
+ *     hipStream_t given to rec_init (NULL = the default stream); only a
+ *     batch (rec_batch_init) creates streams of its own, which it forks from
+ *     and joins back into that stream within each solve.  Work the caller
+ *     enqueues on that stream after a call returns is ordered after that
+ *     call's work.
  *   - Device-pointer pushes are not launched when made: the first fused
  *     launch of the next rec_solve validates and bins them itself (or, for
  *     more pushes or events than it takes, they are scattered by kernels of
@@ -268,39 +270,99 @@ const char* rec_strerror(int code);
 
 /* ---------------------------------------------------------------------
  * Batched solves.  Many independent streams (cameras of different sizes
- * and event rates) are solved together: every launch of a batched solve
- * covers the tiles of all streams, so a solve costs ceil(iters / K)
- * launches for the whole batch instead of per stream.  Results are the
- * same bits as solving each stream alone with the same iterations per
- * launch.  (Not in the paper, which reconstructs one camera.)
+ * and event rates) are solved together.  Every sensor size (or run of
+ * sizes by pixel count, when there are more than 8 sizes) gets a tile
+ * geometry and iterations per launch K; the sizes sharing a geometry form
+ * a class, and a solve runs one chain of ceil(iters / K_c) launches per
+ * class, every launch covering the tiles of all streams of the class.
+ * Results are the same bits as solving each stream alone (the per-pixel
+ * arithmetic does not depend on the tiling or on K).  (Not in the paper,
+ * which reconstructs one camera.)
  * ------------------------------------------------------------------- */
 typedef struct rec_batch rec_batch;
+
+/* How a batched solve issues the class chains. */
+enum {
+    REC_BATCH_SERIAL = 0,   /* one after another on the contexts' stream */
+    REC_BATCH_STREAMS = 1,  /* concurrently: every class but the first on a stream of
+                               the batch's own, forked from the contexts' stream after
+                               the solve's descriptor upload and joined back into it
+                               (default) */
+    REC_BATCH_GRAPH = 2     /* the fork/join of REC_BATCH_STREAMS captured once into a
+                               HIP graph per (iterations, descriptor buffer, classes
+                               with folded events) and replayed on a stream of the
+                               batch's own, ordered after the contexts' stream and
+                               before its later work; the descriptor upload stays
+                               outside the graph */
+};
+
+/* One class of a batch (rec_batch_config). */
+typedef struct {
+    int32_t width, height;  /* sensor size of the class's first stream */
+    int32_t streams;        /* streams in the class */
+    int32_t rows, waves;    /* tile geometry: rows per lane, wavefronts per workgroup, */
+    int32_t cols;           /*   columns (64 or 32) */
+    int32_t kiters;         /* iterations per launch K_c */
+    int32_t tiles;          /* workgroups per launch of the class */
+    double tuned_us;        /* autotuner's time of the whole tuned schedule for its
+                               tune_iters iterations (0 when not tuned) */
+} rec_batch_class;
 
 /* Device workspace bytes for a batch of these contexts (0 if invalid). */
 size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n);
 
 /* Group n contexts.  They must share device, stream and storage, use the
  * fused loop, and have no timestamp denoising and no gap sampling.  The
- * contexts stay owned by the caller and must outlive the batch.  With
- * tune_iters > 0 an autotuner times every candidate tile geometry (rows
- * per lane, wavefronts, iterations per launch) on the streams' current
- * state without changing it, and keeps the one that runs tune_iters
- * iterations fastest (synchronises); with 0 the automatic geometry for a
- * frame of the batch's total pixel count is used. */
+ * contexts stay owned by the caller and must outlive the batch.  Without
+ * tuning (tune_iters == 0) all sizes share the automatic geometry of a
+ * frame of the batch's total pixel count (one class).  With tune_iters > 0
+ * an autotuner times the whole schedule of tune_iters iterations for every
+ * candidate geometry shared by all sizes, keeps the fastest, then runs a
+ * coordinate descent over the sizes (largest first), each trying every
+ * candidate (rows, waves, columns, K) with the others fixed; sizes that end
+ * with equal geometries share one class.  The timed launches read the
+ * streams' current state and write only their spare buffers, so no state
+ * changes (synchronises).
+ * The batch creates one stream (default priority, non-blocking) per class
+ * beyond the first and one for graph replays, released by
+ * rec_batch_destroy.  REC_EINVAL for mixed or
+ * repeated contexts, REC_ENOMEM for a short workspace or host allocation,
+ * REC_EDEVICE for a failed HIP call. */
 int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t ws_bytes,
                    int32_t tune_iters, rec_batch** out);
 
 /* Solve the pending block of every stream of the batch with `iters`
  * iterations (each stream's pushes since its last solve; a stream without
- * new events smooths its previous image).  Does not synchronise. */
+ * new events smooths its previous image).  Does not synchronise: work the
+ * caller enqueues on the contexts' stream afterwards is ordered after every
+ * class chain. */
 int rec_batch_solve(rec_batch* b, int32_t iters);
 
-/* The geometry in use and the autotuner's measured time per launch (us,
- * 0 when not tuned).  Any output may be NULL. */
-int rec_batch_config(const rec_batch* b, int32_t* rows, int32_t* waves, int32_t* kiters,
-                     double* launch_us);
+/* Number of classes of the batch (>= 1), or REC_EINVAL. */
+int rec_batch_classes(const rec_batch* b);
 
-/* Release the batch (after synchronising its stream).  NULL is a no-op. */
+/* The geometry of class cls (0 .. rec_batch_classes - 1). */
+int rec_batch_config(const rec_batch* b, int32_t cls, rec_batch_class* out);
+
+/* Set the geometry of the streams of one sensor size (of every size that
+ * shares its group when the batch has more than 8 sizes), instead of the
+ * automatic or tuned one: rows per lane, wavefronts, columns (64 or 32) as
+ * listed for rec_params.tile_rows / tile_cols in the batched launch's set
+ * (64 columns: 2x16 4x8 4x16 6x8 8x4 8x8, 32 columns: 1x16 2x8; 16-bit
+ * storage without 6x8 and 1x16), and iterations per launch
+ * 1 <= kiters <= (min(columns, tile rows) - 1) / 2.  For instance to reuse
+ * an earlier tuning without timing again.  The classes are formed again;
+ * synchronises.  REC_EINVAL for an unsupported geometry or a size not in
+ * the batch, REC_ENOMEM if the tiles exceed the workspace. */
+int rec_batch_set_geometry(rec_batch* b, int32_t width, int32_t height, int32_t rows,
+                           int32_t waves, int32_t cols, int32_t kiters);
+
+/* Select how solves issue the class chains (REC_BATCH_*); the same bits in
+ * every mode.  While profiling is on (rec_profile on the first context of
+ * the batch) REC_BATCH_GRAPH solves issue the chains directly. */
+int rec_batch_set_mode(rec_batch* b, int32_t mode);
+
+/* Release the batch (after synchronising its streams).  NULL is a no-op. */
 int rec_batch_destroy(rec_batch* b);
 
 /* -------------------------------------------------------------------

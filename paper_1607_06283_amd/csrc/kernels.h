@@ -167,9 +167,9 @@ hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipS
 // K iterations in this launch, KG the halo of the tile geometry (K <= KG),
 // li the launch's index within the solve, bins: some stream folds events.
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
-                           int li, bool last, bool bins, int rows, int waves, int storage,
-                           hipStream_t s, LaunchEv ev = {});
-bool batch_shape_supported(int rows, int waves, int storage);
+                           int li, bool last, bool bins, int rows, int waves, int cols,
+                           int storage, hipStream_t s, LaunchEv ev = {});
+bool batch_shape_supported(int rows, int waves, int cols, int storage);
 hipError_t launch_finish_batch(const StreamDesc* descs, int nstreams, size_t max_np,
                                hipStream_t s);
 

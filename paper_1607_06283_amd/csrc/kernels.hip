@@ -1030,7 +1030,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterCo
 // constants and folded events.  launch = index of this launch in the solve
 // (selects the stream's first-launch and second-launch modes and the
 // ping-pong parity); last: the solve's last launch.
-template <int R, int NW, class S, bool B>
+template <int R, int NW, int CW, class S, bool B>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __restrict__ descs,
                                                             const int2* __restrict__ work,
                                                             int nwork, int K, int KG,
@@ -1040,7 +1040,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __
     const StreamDesc& d = descs[w.x];
     const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
     const int mode = (launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0)) | (last ? kRotOut : 0);
-    pd_tile<R, NW, 64, S, B>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode,
+    pd_tile<R, NW, CW, S, B>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode,
                              txi, tyi, w.y == 0, dyn_lds);
 }
 
@@ -1191,17 +1191,18 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
                   ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
 }
 
-template <int R, int NW, class S>
+template <int R, int NW, int CW, class S>
 hipError_t batch_launch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
                         int launch_idx, bool last, bool bins, hipStream_t s, LaunchEv ev) {
-    if (K < 1 || K > KG || 64 - 2 * KG <= 0 || NW * R - 2 * KG <= 0) return hipErrorInvalidValue;
+    constexpr int RH = NW * (64 / CW) * R;
+    if (K < 1 || K > KG || CW - 2 * KG <= 0 || RH - 2 * KG <= 0) return hipErrorInvalidValue;
     // every stream's first-launch mode builds (launch 0 only)
-    const size_t lds = fused_lds_bytes(R, NW, 64, bins ? kEvents : 0);
+    const size_t lds = fused_lds_bytes(R, NW, CW, bins ? kEvents : 0);
     if (launch_idx == 0)
-        return launch(k_pd_fused_batch<R, NW, S, true>, dim3(nwork), dim3(64 * NW), lds, s,
+        return launch(k_pd_fused_batch<R, NW, CW, S, true>, dim3(nwork), dim3(64 * NW), lds, s,
                       ev.start, ev.stop, descs, work, nwork, K, KG, launch_idx, last ? 1 : 0);
-    return launch(k_pd_fused_batch<R, NW, S, false>, dim3(nwork), dim3(64 * NW), lds, s, ev.start,
-                  ev.stop, descs, work, nwork, K, KG, launch_idx, last ? 1 : 0);
+    return launch(k_pd_fused_batch<R, NW, CW, S, false>, dim3(nwork), dim3(64 * NW), lds, s,
+                  ev.start, ev.stop, descs, work, nwork, K, KG, launch_idx, last ? 1 : 0);
 }
 
 }  // namespace
@@ -1429,46 +1430,54 @@ hipError_t launch_pd_fused(const Planes& P, Frame fr, IterConsts kc, BuildConsts
 #undef REC_FUSED_CASE
 #undef REC_FUSED_CASE16
 
-#define REC_BATCH_CASE(R, NW)                                                                   \
-    case R * 100 + NW:                                                                          \
-        return batch_launch<R, NW, StoreF32>(descs, work, nwork, K, KG, li, last, bins, s, ev);
-#define REC_BATCH_CASE16(R, NW)                                                                  \
-    case R * 100 + NW:                                                                          \
+#define REC_BATCH_CASE(R, NW, CW)                                                               \
+    case (CW == 32 ? 10000 : 0) + R * 100 + NW:                                                \
+        return batch_launch<R, NW, CW, StoreF32>(descs, work, nwork, K, KG, li, last, bins, s,  \
+                                                 ev);
+#define REC_BATCH_CASE16(R, NW, CW)                                                             \
+    case (CW == 32 ? 10000 : 0) + R * 100 + NW:                                                \
         return storage == kStoreF16                                                             \
-                   ? batch_launch<R, NW, StoreF16>(descs, work, nwork, K, KG, li, last, bins, s, \
-                                                   ev)                                          \
-                   : batch_launch<R, NW, StoreBF16>(descs, work, nwork, K, KG, li, last, bins,  \
-                                                    s, ev);
+                   ? batch_launch<R, NW, CW, StoreF16>(descs, work, nwork, K, KG, li, last,     \
+                                                       bins, s, ev)                             \
+                   : batch_launch<R, NW, CW, StoreBF16>(descs, work, nwork, K, KG, li, last,    \
+                                                        bins, s, ev);
 
 hipError_t launch_pd_batch(const StreamDesc* descs, const int2* work, int nwork, int K, int KG,
-                           int li, bool last, bool bins, int rows, int waves, int storage,
-                           hipStream_t s, LaunchEv ev) {
-    if (!batch_shape_supported(rows, waves, storage) || nwork <= 0) return hipErrorInvalidValue;
+                           int li, bool last, bool bins, int rows, int waves, int cols,
+                           int storage, hipStream_t s, LaunchEv ev) {
+    if (!batch_shape_supported(rows, waves, cols, storage) || nwork <= 0)
+        return hipErrorInvalidValue;
+    const int key = (cols == 32 ? 10000 : 0) + rows * 100 + waves;
     if (storage != kStoreF32) {
-        switch (rows * 100 + waves) {
-            REC_BATCH_CASE16(2, 16)
-            REC_BATCH_CASE16(4, 16)
-            REC_BATCH_CASE16(4, 8)
-            REC_BATCH_CASE16(8, 4)
-            REC_BATCH_CASE16(8, 8)
+        switch (key) {
+            REC_BATCH_CASE16(2, 16, 64)
+            REC_BATCH_CASE16(4, 16, 64)
+            REC_BATCH_CASE16(4, 8, 64)
+            REC_BATCH_CASE16(8, 4, 64)
+            REC_BATCH_CASE16(8, 8, 64)
+            REC_BATCH_CASE16(2, 8, 32)
             default: return hipErrorInvalidValue;
         }
     }
-    switch (rows * 100 + waves) {
-        REC_BATCH_CASE(2, 16)
-        REC_BATCH_CASE(4, 8)
-        REC_BATCH_CASE(4, 16)
-        REC_BATCH_CASE(6, 8)
-        REC_BATCH_CASE(8, 4)
-        REC_BATCH_CASE(8, 8)
+    switch (key) {
+        REC_BATCH_CASE(2, 16, 64)
+        REC_BATCH_CASE(4, 8, 64)
+        REC_BATCH_CASE(4, 16, 64)
+        REC_BATCH_CASE(6, 8, 64)
+        REC_BATCH_CASE(8, 4, 64)
+        REC_BATCH_CASE(8, 8, 64)
+        REC_BATCH_CASE(1, 16, 32)
+        REC_BATCH_CASE(2, 8, 32)
         default: return hipErrorInvalidValue;
     }
 }
 #undef REC_BATCH_CASE
 #undef REC_BATCH_CASE16
 
-bool batch_shape_supported(int rows, int waves, int storage) {
+bool batch_shape_supported(int rows, int waves, int cols, int storage) {
     const int key = rows * 100 + waves;
+    if (cols == 32) return key == 208 || (storage == kStoreF32 && key == 116);
+    if (cols != 64) return false;
     if (storage == kStoreF32 && key == 608) return true;
     return key == 216 || key == 408 || key == 416 || key == 804 || key == 808;
 }

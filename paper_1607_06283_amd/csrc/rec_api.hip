@@ -781,53 +781,106 @@ const char* rec_strerror(int code) {
 }  // extern "C"
 
 // ------------------------------------------------------------------------
-// Batched solves: many streams, one launch per block of iterations.
+// Batched solves: many streams, one launch chain per tile-geometry class.
+//
+// Streams are grouped into classes (one per sensor size, at most
+// kMaxClasses); every class has its own tile geometry and iterations per
+// launch and a work list of its (stream, tile) pairs, so a solve runs one
+// chain of ceil(iters / K_c) launches per class.  The chains run one after
+// another on the batch's stream (REC_BATCH_SERIAL), concurrently on one
+// stream per class forked from and joined back into the batch's stream
+// (REC_BATCH_STREAMS), or as a HIP graph of that fork/join captured once
+// per (iterations, descriptor buffer, folded-event classes) and replayed
+// (REC_BATCH_GRAPH).  The descriptors are uploaded before the chains, into
+// one of two fixed device buffers, so a captured graph stays valid.
 // ------------------------------------------------------------------------
 
 namespace {
 
 struct Shape {
-    int rows, waves, k;
+    int rows, waves, cols, k;
+    bool operator==(const Shape& o) const {
+        return rows == o.rows && waves == o.waves && cols == o.cols && k == o.k;
+    }
 };
 
-// Candidate tile geometries of the batched launch.
+constexpr int kMaxClasses = 8;
+constexpr int kMaxGraphs = 8;
+
+// Candidate tile geometries of the batched launch (rows per lane x
+// wavefronts x columns) and iterations per launch.
 std::vector<Shape> batch_candidates(int storage) {
     std::vector<Shape> v;
-    const int shapes[][2] = {{2, 16}, {4, 8}, {4, 16}, {6, 8}, {8, 4}, {8, 8}};
-    const int ks[] = {4, 6, 8, 10, 13, 15};
+    const int shapes[][3] = {{2, 16, 64}, {4, 8, 64}, {4, 16, 64}, {6, 8, 64},
+                             {8, 4, 64},  {8, 8, 64}, {1, 16, 32}, {2, 8, 32}};
+    const int ks[] = {4, 6, 8, 9, 10, 13, 15};
     for (auto& sh : shapes) {
-        if (!rec::batch_shape_supported(sh[0], sh[1], storage)) continue;
+        if (!rec::batch_shape_supported(sh[0], sh[1], sh[2], storage)) continue;
+        const int rh = sh[0] * sh[1] * (64 / sh[2]);
         for (int k : ks)
-            if (k <= (sh[0] * sh[1] - 1) / 2 && k <= 31) v.push_back(Shape{sh[0], sh[1], k});
+            if (k <= (rh - 1) / 2 && k <= (sh[2] - 1) / 2)
+                v.push_back(Shape{sh[0], sh[1], sh[2], k});
     }
     return v;
 }
 
-int64_t batch_tiles(rec_ctx* const* ctxs, int n, Shape sh) {
-    int64_t t = 0;
-    for (int i = 0; i < n; ++i) t += rec::fused_tiles(ctxs[i]->fr, sh.rows, sh.waves, 64, sh.k);
-    return t;
+int shape_tiles(rec::Frame fr, Shape sh) {
+    return rec::fused_tiles(fr, sh.rows, sh.waves, sh.cols, sh.k);
 }
 
 }  // namespace
 
-struct rec_batch {
+// Streams of one sensor size (or one run of sizes) and their geometry.
+struct BatchGroup {
     std::vector<rec_ctx*> ctx;
+    Shape shape;
+    size_t max_np;          // largest frame of the group (pixels)
+    int64_t px;             // pixels of all its streams
+};
+
+// Streams sharing one tile geometry: the groups of equal geometry, whose
+// tiles one launch chain covers.
+struct BatchClass {
+    Shape shape;
+    int s0, ns;             // its streams: descriptors s0 .. s0 + ns - 1
+    int64_t work0;          // its (stream, tile) pairs: work list entries work0 ..
+    int nwork;              //   work0 + nwork - 1
+    size_t max_np;          // largest frame of the class (pixels)
+};
+
+struct GraphEntry {
+    int iters, q;
+    unsigned fold;          // classes whose first launch bins folded events
+    hipGraphExec_t exec;
+};
+
+struct rec_batch {
+    rec_ctx* lead;               // the caller's first context: holds the profiling state
+    std::vector<BatchGroup> grp;
+    std::vector<rec_ctx*> ctx;   // in descriptor order: grouped by class
+    std::vector<BatchClass> cls;
+    hipStream_t side[kMaxClasses];  // class ci > 0 runs on side[ci] (concurrent chains)
+    hipEvent_t done[kMaxClasses];   //   and records done[ci] after its chain
     hipStream_t stream;
     int storage;
-    Shape shape;
-    double tuned_us;             // measured time of one launch of the chosen shape (0: not tuned)
+    int mode;                    // REC_BATCH_SERIAL, _STREAMS or _GRAPH
+    double tuned_us;             // measured time of the tuned schedule (0: not tuned)
     // device workspace
     rec::StreamDesc* d_desc[2];  // alternating per solve
     int2* d_work;
     int64_t work_cap;
-    int nwork;
     // pinned staging of the descriptors
     rec::StreamDesc* h_desc[2];
     hipEvent_t copied[2];
     bool copy_used[2];
     int parity;
-    size_t max_np;
+    hipEvent_t fork;
+    // graphs are captured on and replayed in a stream of the batch's own
+    // (the contexts' stream may be the null stream, which cannot capture),
+    // ordered after and before the contexts' stream by two events
+    hipStream_t cap;
+    hipEvent_t pre, post;
+    std::vector<GraphEntry> graphs;
     bool holds_refs;             // the contexts count this batch as a user
 };
 
@@ -835,58 +888,180 @@ namespace {
 
 size_t batch_desc_bytes(int n) { return align_up((size_t)n * sizeof(rec::StreamDesc)); }
 
+// Groups the contexts into classes: one per distinct sensor size, or, with
+// more sizes than kMaxClasses, runs of sizes ordered by pixel count.
+// Returns the class index of every context.
+std::vector<int> group_sizes(rec_ctx* const* ctxs, int n, int* nclasses) {
+    std::vector<int64_t> keys;
+    for (int i = 0; i < n; ++i) {
+        const int64_t key = ((int64_t)ctxs[i]->fr.W << 32) | (uint32_t)ctxs[i]->fr.H;
+        bool seen = false;
+        for (int64_t k : keys) seen = seen || k == key;
+        if (!seen) keys.push_back(key);
+    }
+    // sizes ordered by pixel count (then width)
+    auto px = [](int64_t key) { return (key >> 32) * (key & 0xffffffff); };
+    for (size_t i = 1; i < keys.size(); ++i)
+        for (size_t j = i; j > 0 && (px(keys[j]) < px(keys[j - 1]) ||
+                                     (px(keys[j]) == px(keys[j - 1]) && keys[j] < keys[j - 1]));
+             --j) {
+            const int64_t t = keys[j];
+            keys[j] = keys[j - 1];
+            keys[j - 1] = t;
+        }
+    const int nk = (int)keys.size();
+    const int nc = nk < kMaxClasses ? nk : kMaxClasses;
+    std::vector<int> out(n);
+    for (int i = 0; i < n; ++i) {
+        const int64_t key = ((int64_t)ctxs[i]->fr.W << 32) | (uint32_t)ctxs[i]->fr.H;
+        int r = 0;
+        while (keys[r] != key) ++r;
+        out[i] = (int)((int64_t)r * nc / nk);  // consecutive sizes share a class
+    }
+    *nclasses = nc;
+    return out;
+}
+
+// Classes from the groups' geometries: groups of equal geometry form one
+// class (one launch chain); the descriptor order follows the classes.
+void build_classes(rec_batch* b) {
+    std::vector<int> order(b->grp.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = (int)g;
+    auto key = [&](int g) {
+        const Shape& sh = b->grp[g].shape;
+        return ((int64_t)sh.rows << 24) | ((int64_t)sh.waves << 16) | ((int64_t)sh.cols << 8) |
+               sh.k;
+    };
+    for (size_t i = 1; i < order.size(); ++i)  // stable: equal geometries keep group order
+        for (size_t j = i; j > 0 && key(order[j]) < key(order[j - 1]); --j) {
+            const int t = order[j];
+            order[j] = order[j - 1];
+            order[j - 1] = t;
+        }
+    b->ctx.clear();
+    b->cls.clear();
+    for (int g : order) {
+        const BatchGroup& gr = b->grp[g];
+        if (b->cls.empty() || !(b->cls.back().shape == gr.shape)) {
+            BatchClass c{};
+            c.shape = gr.shape;
+            c.s0 = (int)b->ctx.size();
+            b->cls.push_back(c);
+        }
+        BatchClass& c = b->cls.back();
+        for (rec_ctx* x : gr.ctx) b->ctx.push_back(x);
+        c.ns += (int)gr.ctx.size();
+        if (gr.max_np > c.max_np) c.max_np = gr.max_np;
+    }
+}
+
 int upload_work(rec_batch* b) {
     std::vector<int2> w;
-    for (size_t s = 0; s < b->ctx.size(); ++s) {
-        const int t =
-            rec::fused_tiles(b->ctx[s]->fr, b->shape.rows, b->shape.waves, 64, b->shape.k);
-        if (t <= 0) return REC_EINVAL;
-        for (int q = 0; q < t; ++q) w.push_back(make_int2((int)s, q));
+    for (BatchClass& c : b->cls) {
+        c.work0 = (int64_t)w.size();
+        for (int s = c.s0; s < c.s0 + c.ns; ++s) {
+            const int t = shape_tiles(b->ctx[s]->fr, c.shape);
+            if (t <= 0) return REC_EINVAL;
+            for (int q = 0; q < t; ++q) w.push_back(make_int2(s, q));
+        }
+        c.nwork = (int)((int64_t)w.size() - c.work0);
     }
     if ((int64_t)w.size() > b->work_cap) return REC_ENOMEM;
-    b->nwork = (int)w.size();
     if (hipMemcpy(b->d_work, w.data(), w.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
         return REC_EDEVICE;
     return REC_OK;
 }
 
-void fill_desc(rec_batch* b, rec::StreamDesc* d, bool* any_fold) {
-    for (size_t s = 0; s < b->ctx.size(); ++s) {
-        rec_ctx* c = b->ctx[s];
-        rec::StreamDesc& e = d[s];
-        memset(&e, 0, sizeof(e));
-        e.P = c->P;
-        e.fr = c->fr;
-        e.kc = c->kc;
-        e.bc = rec::BuildConsts{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
-        e.cur = c->cur;
-        const int ow = 64 - 2 * b->shape.k;
-        e.tiles_x = (c->fr.W + ow - 1) / ow;
-        const bool fold = !c->deferred.empty();
-        if (fold) {
-            for (size_t q = 0; q < c->deferred.size(); ++q) {
-                e.segs.t[q] = c->deferred[q].t;
-                e.segs.x[q] = c->deferred[q].x;
-                e.segs.y[q] = c->deferred[q].y;
-                e.segs.p[q] = c->deferred[q].p;
-                e.segs.n[q] = c->deferred[q].n;
+// Descriptors of every stream; *fold receives the classes (bit mask) in
+// which some stream folds pushed events into its first launch.
+void fill_desc(rec_batch* b, rec::StreamDesc* d, unsigned* fold) {
+    *fold = 0;
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        const BatchClass& cl = b->cls[ci];
+        for (int s = cl.s0; s < cl.s0 + cl.ns; ++s) {
+            rec_ctx* c = b->ctx[s];
+            rec::StreamDesc& e = d[s];
+            memset(&e, 0, sizeof(e));
+            e.P = c->P;
+            e.fr = c->fr;
+            e.kc = c->kc;
+            e.bc = rec::BuildConsts{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
+            e.cur = c->cur;
+            const int ow = cl.shape.cols - 2 * cl.shape.k;
+            e.tiles_x = (c->fr.W + ow - 1) / ow;
+            const bool f = !c->deferred.empty();
+            if (f) {
+                for (size_t q = 0; q < c->deferred.size(); ++q) {
+                    e.segs.t[q] = c->deferred[q].t;
+                    e.segs.x[q] = c->deferred[q].x;
+                    e.segs.y[q] = c->deferred[q].y;
+                    e.segs.p[q] = c->deferred[q].p;
+                    e.segs.n[q] = c->deferred[q].n;
+                }
+                e.segs.count = (int32_t)c->deferred.size();
+                *fold |= 1u << ci;
             }
-            e.segs.count = (int32_t)c->deferred.size();
-            *any_fold = true;
+            e.mode0 = rec::kBuild | (f ? rec::kEvents : 0) |
+                      (c->counts_dirty ? rec::kCounts : 0) | rec::kRotIn;
+            e.mode1 = rec::kCommit | (c->counts_dirty ? rec::kZero : 0);
         }
-        e.mode0 = rec::kBuild | (fold ? rec::kEvents : 0) | (c->counts_dirty ? rec::kCounts : 0) |
-                  rec::kRotIn;
-        e.mode1 = rec::kCommit | (c->counts_dirty ? rec::kZero : 0);
     }
 }
 
-// Time `reps` side-effect-free launches (mode 0: read buffer cur, write the
-// other; the host keeps cur) of one geometry; returns microseconds per launch.
-int time_shape(rec_batch* b, int reps, double* us) {
+// Enqueues the launch chains of every class for `iters` iterations on the
+// descriptors in buffer q, on stream `main`.  concurrent: each class but the
+// first runs on its own stream, forked from and joined back into `main`.
+// timing: side-effect-free launches for the autotuner (every launch reads
+// the current buffers and writes the others, modes 0, no folded events).
+int enqueue_chains(rec_batch* b, hipStream_t main, int q, int iters, unsigned fold,
+                   bool concurrent, bool timing) {
+    const bool fork = concurrent && b->cls.size() > 1;
+    if (fork) {
+        if (hipEventRecord(b->fork, main) != hipSuccess) return REC_EDEVICE;
+        for (size_t ci = 1; ci < b->cls.size(); ++ci)
+            if (hipStreamWaitEvent(b->side[ci], b->fork, 0) != hipSuccess) return REC_EDEVICE;
+    }
+    rec_ctx* c0 = b->lead;
+    for (size_t ci = 0; ci < b->cls.size(); ++ci) {
+        const BatchClass& cl = b->cls[ci];
+        hipStream_t s = (fork && ci > 0) ? b->side[ci] : main;
+        const int K = cl.shape.k;
+        const int nl = (iters + K - 1) / K;
+        for (int li = 0; li < nl; ++li) {
+            const int m = iters / nl + (li < iters % nl ? 1 : 0);
+            int64_t work = 0;
+            if (c0->prof_on && !timing)
+                for (int si = cl.s0; si < cl.s0 + cl.ns; ++si)
+                    work += (int64_t)b->ctx[si]->fr.W * b->ctx[si]->fr.H * m;
+            auto go = [&](rec::LaunchEv ev) {
+                return rec::launch_pd_batch(b->d_desc[q], b->d_work + cl.work0, cl.nwork, m, K,
+                                            timing ? 2 : li, !timing && li == nl - 1,
+                                            !timing && li == 0 && ((fold >> ci) & 1u),
+                                            cl.shape.rows, cl.shape.waves, cl.shape.cols,
+                                            b->storage, s, ev);
+            };
+            const int rc = timing ? dev_err(go(rec::LaunchEv{})) : timed(c0, 2, work, go);
+            if (rc) return rc;
+        }
+        if (nl == 1 && !timing &&
+            hipSuccess != rec::launch_finish_batch(b->d_desc[q] + cl.s0, cl.ns, cl.max_np, s))
+            return REC_EDEVICE;
+        if (fork && ci > 0 && hipEventRecord(b->done[ci], s) != hipSuccess) return REC_EDEVICE;
+    }
+    if (fork)
+        for (size_t ci = 1; ci < b->cls.size(); ++ci)
+            if (hipStreamWaitEvent(main, b->done[ci], 0) != hipSuccess) return REC_EDEVICE;
+    return REC_OK;
+}
+
+// Time `reps` side-effect-free runs of the whole schedule of the current
+// geometries (concurrent chains, `iters` iterations); microseconds per run.
+int time_schedule(rec_batch* b, int iters, int reps, double* us) {
+    build_classes(b);
     int rc = upload_work(b);
     if (rc) return rc;
     rec::StreamDesc* h = b->h_desc[0];
-    bool fold = false;
+    unsigned fold = 0;
     fill_desc(b, h, &fold);
     for (size_t s = 0; s < b->ctx.size(); ++s) h[s].mode0 = h[s].mode1 = 0;
     if (hipMemcpy(b->d_desc[0], h, b->ctx.size() * sizeof(rec::StreamDesc), hipMemcpyHostToDevice) !=
@@ -898,23 +1073,49 @@ int time_shape(rec_batch* b, int reps, double* us) {
         (void)hipEventDestroy(e0);
         return REC_EDEVICE;
     }
-    hipError_t e = hipSuccess;
-    for (int q = 0; q < reps + 2 && e == hipSuccess; ++q) {
-        rec::LaunchEv ev;
-        if (q == 2) ev.start = e0;
-        if (q == reps + 1) ev.stop = e1;
-        // launch index 2: mode 0 for every stream, parity of launch 0
-        e = rec::launch_pd_batch(b->d_desc[0], b->d_work, b->nwork, b->shape.k, b->shape.k, 2,
-                                 false, false, b->shape.rows, b->shape.waves, b->storage,
-                                 b->stream, ev);
-    }
+    rc = enqueue_chains(b, b->stream, 0, iters, 0, true, true);  // warm-up run
+    if (!rc && hipEventRecord(e0, b->stream) != hipSuccess) rc = REC_EDEVICE;
+    for (int r = 0; r < reps && !rc; ++r)
+        rc = enqueue_chains(b, b->stream, 0, iters, 0, true, true);
+    if (!rc && hipEventRecord(e1, b->stream) != hipSuccess) rc = REC_EDEVICE;
     float ms = 0.0f;
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (!rc && (hipStreamSynchronize(b->stream) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        rc = REC_EDEVICE;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (e != hipSuccess) return REC_EDEVICE;
-    *us = (double)ms * 1e3 / reps;
+    if (!rc) *us = (double)ms * 1e3 / reps;
+    return rc;
+}
+
+void drop_graphs(rec_batch* b) {
+    for (GraphEntry& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+}
+
+// The captured fork/join of a solve (built on first use).
+int graph_for(rec_batch* b, int q, int iters, unsigned fold, hipGraphExec_t* out) {
+    for (const GraphEntry& g : b->graphs)
+        if (g.iters == iters && g.q == q && g.fold == fold) {
+            *out = g.exec;
+            return REC_OK;
+        }
+    if ((int)b->graphs.size() == kMaxGraphs) drop_graphs(b);
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed) != hipSuccess)
+        return REC_EDEVICE;
+    const int rc = enqueue_chains(b, b->cap, q, iters, fold, true, false);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(b->cap, &g);
+    if (rc || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc ? rc : REC_EDEVICE;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return REC_EDEVICE;
+    b->graphs.push_back(GraphEntry{iters, q, fold, exec});
+    *out = exec;
     return REC_OK;
 }
 
@@ -926,10 +1127,16 @@ size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n) {
     if (!ctxs || n < 1) return 0;
     for (int i = 0; i < n; ++i)
         if (!ctxs[i]) return 0;
+    // every stream may get any candidate geometry
+    const std::vector<Shape> cand = batch_candidates(ctxs[0]->prm.storage);
     int64_t tiles = 0;
-    for (const Shape& sh : batch_candidates(ctxs[0]->prm.storage)) {
-        const int64_t t = batch_tiles(ctxs, n, sh);
-        if (t > tiles) tiles = t;
+    for (int i = 0; i < n; ++i) {
+        int64_t t = 0;
+        for (const Shape& sh : cand) {
+            const int64_t ti = shape_tiles(ctxs[i]->fr, sh);
+            if (ti > t) t = ti;
+        }
+        tiles += t;
     }
     return 2 * batch_desc_bytes(n) + align_up((size_t)tiles * sizeof(int2));
 }
@@ -953,60 +1160,116 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
     if (ws_bytes < need) return REC_ENOMEM;
     rec_batch* b = new (std::nothrow) rec_batch();
     if (!b) return REC_ENOMEM;
-    b->ctx.assign(ctxs, ctxs + n);
     b->stream = ctxs[0]->stream;
     b->storage = ctxs[0]->prm.storage;
+    b->mode = REC_BATCH_STREAMS;
+    b->lead = ctxs[0];
+    int ng = 0;
+    const std::vector<int> grp_of = group_sizes(ctxs, n, &ng);
+    b->grp.resize(ng);
+    for (int i = 0; i < n; ++i) {
+        BatchGroup& g = b->grp[grp_of[i]];
+        g.ctx.push_back(ctxs[i]);
+        const size_t np = (size_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
+        if (np > g.max_np) g.max_np = np;
+        g.px += (int64_t)np;
+    }
+    // default geometry, one for every group: the automatic choice for a frame
+    // of the batch's total pixel count (64-column tiles)
+    {
+        int64_t total = 0;
+        for (const BatchGroup& g : b->grp) total += g.px;
+        int r, w, cw, k;
+        choose_shape(&ctxs[0]->prm, total, false, &r, &w, &cw, &k);
+        if (!rec::batch_shape_supported(r, w, cw, b->storage)) {
+            r = 4;
+            w = 8;
+            cw = 64;
+            if (k > 15) k = 15;
+        }
+        for (BatchGroup& g : b->grp) g.shape = Shape{r, w, cw, k};
+    }
+    build_classes(b);
     char* base = (char*)dev_workspace;
     b->d_desc[0] = (rec::StreamDesc*)base;
     b->d_desc[1] = (rec::StreamDesc*)(base + batch_desc_bytes(n));
     b->d_work = (int2*)(base + 2 * batch_desc_bytes(n));
     b->work_cap = (int64_t)((ws_bytes - 2 * batch_desc_bytes(n)) / sizeof(int2));
-    for (int i = 0; i < n; ++i) {
-        const size_t np = (size_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
-        if (np > b->max_np) b->max_np = np;
-    }
-    for (int q = 0; q < 2; ++q) {
-        if (hipHostMalloc((void**)&b->h_desc[q], (size_t)n * sizeof(rec::StreamDesc),
-                          hipHostMallocDefault) != hipSuccess ||
-            hipEventCreateWithFlags(&b->copied[q], hipEventDisableTiming) != hipSuccess) {
-            rec_batch_destroy(b);
-            return REC_ENOMEM;
-        }
-    }
-    // default geometry: the automatic choice for the batch's total pixel
-    // count (the launches cover every stream's tiles at once)
-    int r, w, cw, k;
-    int64_t total = 0;
-    for (int i = 0; i < n; ++i) total += (int64_t)ctxs[i]->fr.W * ctxs[i]->fr.H;
-    choose_shape(&ctxs[0]->prm, total, false, &r, &w, &cw, &k);
-    if (cw != 64 || !rec::batch_shape_supported(r, w, ctxs[0]->prm.storage)) {
-        r = 4;
-        w = 8;
-        if (k > 15) k = 15;
-    }
-    b->shape = Shape{r, w, k};
     int rc = REC_OK;
+    for (int q = 0; q < 2 && !rc; ++q) {
+        if (hipHostMalloc((void**)&b->h_desc[q], (size_t)n * sizeof(rec::StreamDesc),
+                          hipHostMallocDefault) != hipSuccess)
+            rc = REC_ENOMEM;
+        else if (hipEventCreateWithFlags(&b->copied[q], hipEventDisableTiming) != hipSuccess)
+            rc = REC_EDEVICE;
+    }
+    if (!rc && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->pre, hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&b->post, hipEventDisableTiming) != hipSuccess ||
+                hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess))
+        rc = REC_EDEVICE;
+    for (int ci = 1; ci < ng && !rc; ++ci) {
+        // default priority (work on streams of different priorities is not mixed)
+        if (hipStreamCreateWithFlags(&b->side[ci], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->done[ci], hipEventDisableTiming) != hipSuccess)
+            rc = REC_EDEVICE;
+    }
     // all streams' pending work must be on the stream before timing reads it
-    if (hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
+    if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
     if (!rc && tune_iters > 0) {
-        // autotuner: time every candidate geometry; keep the one that runs
-        // tune_iters iterations fastest (ceil(iters / K) launches)
+        // autotuner on the measured time of the whole schedule (all class
+        // chains, concurrent) for tune_iters iterations:
+        //  1. one geometry for every group (one launch chain): best candidate;
+        //  2. coordinate descent over the groups, largest first, each trying
+        //     every candidate with the others fixed (groups that end up
+        //     with equal geometries share one launch chain).
+        const std::vector<Shape> cand = batch_candidates(b->storage);
+        auto measure = [&](double* us) {
+            const int r = time_schedule(b, tune_iters, 3, us);
+            return r == REC_ENOMEM || r == REC_EINVAL ? 1 : r;  // 1: does not fit
+        };
         double best = 1e300;
-        Shape pick = b->shape;
-        for (const Shape& sh : batch_candidates(ctxs[0]->prm.storage)) {
-            if (batch_tiles(ctxs, n, sh) > b->work_cap) continue;
-            b->shape = sh;
+        std::vector<Shape> keep(ng);
+        for (int g = 0; g < ng; ++g) keep[g] = b->grp[g].shape;
+        for (size_t ci = 0; ci < cand.size() && (rc == REC_OK || rc == 1); ++ci) {
+            for (BatchGroup& g : b->grp) g.shape = cand[ci];
             double us = 0.0;
-            rc = time_shape(b, 5, &us);
-            if (rc) break;
-            const double est = us * ((tune_iters + sh.k - 1) / sh.k);
-            if (est < best) {
-                best = est;
-                pick = sh;
-                b->tuned_us = us;
+            rc = measure(&us);
+            if (rc == REC_OK && us < best) {
+                best = us;
+                for (int g = 0; g < ng; ++g) keep[g] = cand[ci];
             }
         }
-        b->shape = pick;
+        if (rc == 1) rc = REC_OK;
+        std::vector<int> order(ng);
+        for (int g = 0; g < ng; ++g) order[g] = g;
+        for (int i = 1; i < ng; ++i)
+            for (int j = i; j > 0 && b->grp[order[j]].px > b->grp[order[j - 1]].px; --j) {
+                const int t = order[j];
+                order[j] = order[j - 1];
+                order[j - 1] = t;
+            }
+        for (int oi = 0; oi < ng && ng > 1 && !rc; ++oi) {
+            const int g = order[oi];
+            for (const Shape& sh : cand) {
+                if (sh == keep[g]) continue;
+                for (int h = 0; h < ng; ++h) b->grp[h].shape = h == g ? sh : keep[h];
+                double us = 0.0;
+                rc = measure(&us);
+                if (rc == 1) {
+                    rc = REC_OK;
+                    continue;
+                }
+                if (rc) break;
+                if (us < best) {
+                    best = us;
+                    keep[g] = sh;
+                }
+            }
+        }
+        for (int g = 0; g < ng; ++g) b->grp[g].shape = keep[g];
+        b->tuned_us = best < 1e300 ? best : 0.0;
+        build_classes(b);
     }
     if (!rc) rc = upload_work(b);
     if (rc) {
@@ -1023,17 +1286,18 @@ int rec_batch_solve(rec_batch* b, int32_t iters) {
     if (!b || iters < 1) return REC_EINVAL;
     int rc;
     // pushes the first launch cannot fold are scattered first
-    for (rec_ctx* c : b->ctx) {
-        const int64_t tiles =
-            rec::fused_tiles(c->fr, b->shape.rows, b->shape.waves, 64, b->shape.k);
-        if (c->deferred_events > kFoldMaxEvents || c->deferred_events * tiles > kFoldMaxWork) {
-            rc = flush_deferred(c);
-            if (rc) return rc;
+    for (const BatchClass& cl : b->cls)
+        for (int s = cl.s0; s < cl.s0 + cl.ns; ++s) {
+            rec_ctx* c = b->ctx[s];
+            const int64_t tiles = shape_tiles(c->fr, cl.shape);
+            if (c->deferred_events > kFoldMaxEvents || c->deferred_events * tiles > kFoldMaxWork) {
+                rc = flush_deferred(c);
+                if (rc) return rc;
+            }
         }
-    }
     const int q = b->parity;
     if (b->copy_used[q] && hipEventSynchronize(b->copied[q]) != hipSuccess) return REC_EDEVICE;
-    bool fold = false;
+    unsigned fold = 0;
     fill_desc(b, b->h_desc[q], &fold);
     const size_t n = b->ctx.size();
     if (hipMemcpyAsync(b->d_desc[q], b->h_desc[q], n * sizeof(rec::StreamDesc),
@@ -1042,40 +1306,84 @@ int rec_batch_solve(rec_batch* b, int32_t iters) {
         return REC_EDEVICE;
     b->copy_used[q] = true;
     b->parity ^= 1;
-    const int K = b->shape.k;
-    const int nl = (iters + K - 1) / K;
-    rec_ctx* c0 = b->ctx[0];
-    for (int li = 0; li < nl; ++li) {
-        const int m = iters / nl + (li < iters % nl ? 1 : 0);
-        int64_t work = 0;
-        if (c0->prof_on)
-            for (rec_ctx* c : b->ctx) work += (int64_t)c->fr.W * c->fr.H * m;
-        rc = timed(c0, 2, work, [&](rec::LaunchEv ev) {
-            return rec::launch_pd_batch(b->d_desc[q], b->d_work, b->nwork, m, K, li, li == nl - 1,
-                                        fold && li == 0, b->shape.rows, b->shape.waves,
-                                        b->storage, b->stream, ev);
-        });
+    if (b->mode == REC_BATCH_GRAPH && !b->lead->prof_on) {
+        hipGraphExec_t exec = nullptr;
+        rc = graph_for(b, q, iters, fold, &exec);
+        if (rc) return rc;
+        if (hipEventRecord(b->pre, b->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->cap, b->pre, 0) != hipSuccess ||
+            hipGraphLaunch(exec, b->cap) != hipSuccess ||
+            hipEventRecord(b->post, b->cap) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->post, 0) != hipSuccess)
+            return REC_EDEVICE;
+    } else {
+        rc = enqueue_chains(b, b->stream, q, iters, fold, b->mode != REC_BATCH_SERIAL, false);
         if (rc) return rc;
     }
-    if (nl == 1 && hipSuccess != rec::launch_finish_batch(b->d_desc[q], (int)n, b->max_np, b->stream))
-        return REC_EDEVICE;
-    for (rec_ctx* c : b->ctx) {
-        c->cur ^= (nl & 1);
-        c->deferred.clear();
-        c->deferred_events = 0;
-        c->counts_dirty = false;
-        c->gap_samples = 0;
+    for (const BatchClass& cl : b->cls) {
+        const int nl = (iters + cl.shape.k - 1) / cl.shape.k;
+        for (int s = cl.s0; s < cl.s0 + cl.ns; ++s) {
+            rec_ctx* c = b->ctx[s];
+            c->cur ^= (nl & 1);
+            c->deferred.clear();
+            c->deferred_events = 0;
+            c->counts_dirty = false;
+            c->gap_samples = 0;
+        }
     }
     return REC_OK;
 }
 
-int rec_batch_config(const rec_batch* b, int32_t* rows, int32_t* waves, int32_t* kiters,
-                     double* launch_us) {
+int rec_batch_classes(const rec_batch* b) {
     if (!b) return REC_EINVAL;
-    if (rows) *rows = b->shape.rows;
-    if (waves) *waves = b->shape.waves;
-    if (kiters) *kiters = b->shape.k;
-    if (launch_us) *launch_us = b->tuned_us;
+    return (int)b->cls.size();
+}
+
+int rec_batch_config(const rec_batch* b, int32_t cls, rec_batch_class* out) {
+    if (!b || !out || cls < 0 || cls >= (int)b->cls.size()) return REC_EINVAL;
+    const BatchClass& cl = b->cls[cls];
+    out->width = b->ctx[cl.s0]->fr.W;
+    out->height = b->ctx[cl.s0]->fr.H;
+    out->streams = cl.ns;
+    out->rows = cl.shape.rows;
+    out->waves = cl.shape.waves;
+    out->cols = cl.shape.cols;
+    out->kiters = cl.shape.k;
+    out->tiles = cl.nwork;
+    out->tuned_us = b->tuned_us;
+    return REC_OK;
+}
+
+int rec_batch_set_geometry(rec_batch* b, int32_t width, int32_t height, int32_t rows,
+                           int32_t waves, int32_t cols, int32_t kiters) {
+    if (!b || !rec::batch_shape_supported(rows, waves, cols, b->storage) || kiters < 1 ||
+        kiters > (cols - 1) / 2 || kiters > (rows * waves * (64 / cols) - 1) / 2)
+        return REC_EINVAL;
+    BatchGroup* grp = nullptr;
+    for (BatchGroup& g : b->grp)
+        for (rec_ctx* c : g.ctx)
+            if (c->fr.W == width && c->fr.H == height) grp = &g;
+    if (!grp) return REC_EINVAL;
+    // the work list may still be read by the previous solve's launches
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return REC_EDEVICE;
+    const Shape old = grp->shape;
+    grp->shape = Shape{rows, waves, cols, kiters};
+    drop_graphs(b);
+    build_classes(b);
+    int rc = upload_work(b);
+    if (rc) {
+        grp->shape = old;
+        build_classes(b);
+        const int r2 = upload_work(b);
+        return rc ? rc : r2;
+    }
+    return REC_OK;
+}
+
+int rec_batch_set_mode(rec_batch* b, int32_t mode) {
+    if (!b || (mode != REC_BATCH_SERIAL && mode != REC_BATCH_STREAMS && mode != REC_BATCH_GRAPH))
+        return REC_EINVAL;
+    b->mode = mode;
     return REC_OK;
 }
 
@@ -1085,6 +1393,21 @@ int rec_batch_destroy(rec_batch* b) {
     if (hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
     if (b->holds_refs)
         for (rec_ctx* c : b->ctx) --c->batch_refs;
+    drop_graphs(b);
+    for (int ci = 0; ci < kMaxClasses; ++ci) {
+        if (b->side[ci]) {
+            if (hipStreamSynchronize(b->side[ci]) != hipSuccess) rc = REC_EDEVICE;
+            (void)hipStreamDestroy(b->side[ci]);
+        }
+        if (b->done[ci]) (void)hipEventDestroy(b->done[ci]);
+    }
+    if (b->cap) {
+        if (hipStreamSynchronize(b->cap) != hipSuccess) rc = REC_EDEVICE;
+        (void)hipStreamDestroy(b->cap);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->pre) (void)hipEventDestroy(b->pre);
+    if (b->post) (void)hipEventDestroy(b->post);
     for (int q = 0; q < 2; ++q) {
         if (b->copied[q]) (void)hipEventDestroy(b->copied[q]);
         if (b->h_desc[q]) (void)hipHostFree(b->h_desc[q]);

@@ -26,6 +26,7 @@ REC_OK, REC_EINVAL, REC_ERANGE, REC_EORDER, REC_EDEVICE, REC_ENUMERIC, REC_ESTAT
  REC_COUNT_NEG, REC_T_LAST) = range(10)
 
 REC_STORE_F32, REC_STORE_BF16, REC_STORE_F16 = 0, 1, 2
+REC_BATCH_SERIAL, REC_BATCH_STREAMS, REC_BATCH_GRAPH = 0, 1, 2
 
 _PLANE_DTYPE = {REC_COUNT_POS: np.int32, REC_COUNT_NEG: np.int32, REC_T_LAST: np.int64}
 
@@ -74,9 +75,18 @@ EXPORTS = (
     "rec_init", "rec_push_events", "rec_solve", "rec_get_image", "rec_gap_history",
     "rec_sync", "rec_profile", "rec_profile_read", "rec_destroy", "rec_strerror",
     "rec_batch_workspace_bytes", "rec_batch_init", "rec_batch_solve", "rec_batch_config",
-    "rec_batch_destroy", "rec_diff_workspace_bytes", "rec_diff_forward", "rec_diff_backward",
+    "rec_batch_classes", "rec_batch_set_geometry", "rec_batch_set_mode", "rec_batch_destroy",
+    "rec_diff_workspace_bytes", "rec_diff_forward", "rec_diff_backward",
     "rec_diff_forward_noalloc",
 )
+
+
+class rec_batch_class(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("streams", ctypes.c_int32),
+        ("rows", ctypes.c_int32), ("waves", ctypes.c_int32), ("cols", ctypes.c_int32),
+        ("kiters", ctypes.c_int32), ("tiles", ctypes.c_int32), ("tuned_us", ctypes.c_double),
+    ]
 
 
 class rec_diff_desc(ctypes.Structure):
@@ -146,8 +156,13 @@ def load() -> ctypes.CDLL:
     lib.rec_batch_solve.restype = ctypes.c_int
     lib.rec_batch_solve.argtypes = [_vp, ctypes.c_int32]
     lib.rec_batch_config.restype = ctypes.c_int
-    lib.rec_batch_config.argtypes = [_vp] + [ctypes.POINTER(ctypes.c_int32)] * 3 + [
-        ctypes.POINTER(ctypes.c_double)]
+    lib.rec_batch_config.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(rec_batch_class)]
+    lib.rec_batch_classes.restype = ctypes.c_int
+    lib.rec_batch_classes.argtypes = [_vp]
+    lib.rec_batch_set_geometry.restype = ctypes.c_int
+    lib.rec_batch_set_geometry.argtypes = [_vp] + [ctypes.c_int32] * 6
+    lib.rec_batch_set_mode.restype = ctypes.c_int
+    lib.rec_batch_set_mode.argtypes = [_vp, ctypes.c_int32]
     lib.rec_batch_destroy.restype = ctypes.c_int
     lib.rec_batch_destroy.argtypes = [_vp]
     D = ctypes.POINTER(rec_diff_desc)
@@ -399,12 +414,24 @@ def rec_batch_solve(batch: int, iters: int) -> int:
     return load().rec_batch_solve(batch, int(iters))
 
 
-def rec_batch_config(batch: int):
-    r, w, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    us = ctypes.c_double()
-    _check(load().rec_batch_config(batch, ctypes.byref(r), ctypes.byref(w), ctypes.byref(k),
-                                   ctypes.byref(us)), "rec_batch_config")
-    return r.value, w.value, k.value, us.value
+def rec_batch_classes(batch: int) -> int:
+    return load().rec_batch_classes(batch)
+
+
+def rec_batch_config(batch: int, cls: int) -> dict:
+    c = rec_batch_class()
+    _check(load().rec_batch_config(batch, int(cls), ctypes.byref(c)), "rec_batch_config")
+    return {f: getattr(c, f) for f, _ in rec_batch_class._fields_}
+
+
+def rec_batch_set_geometry(batch: int, width: int, height: int, rows: int, waves: int,
+                           cols: int, kiters: int) -> int:
+    return load().rec_batch_set_geometry(batch, int(width), int(height), int(rows), int(waves),
+                                         int(cols), int(kiters))
+
+
+def rec_batch_set_mode(batch: int, mode: int) -> int:
+    return load().rec_batch_set_mode(batch, int(mode))
 
 
 def rec_batch_destroy(batch: Optional[int]) -> int:
@@ -434,7 +461,16 @@ class Batch:
             r._pending.clear()
 
     def config(self):
-        return rec_batch_config(self.handle)
+        """Per class: sensor size, streams, tile geometry, K, tiles, tuned time."""
+        return [rec_batch_config(self.handle, c) for c in range(rec_batch_classes(self.handle))]
+
+    def set_mode(self, mode: int) -> None:
+        _check(rec_batch_set_mode(self.handle, mode), "rec_batch_set_mode")
+
+    def set_geometry(self, width: int, height: int, rows: int, waves: int, cols: int,
+                     kiters: int) -> None:
+        _check(rec_batch_set_geometry(self.handle, width, height, rows, waves, cols, kiters),
+               "rec_batch_set_geometry")
 
     def close(self):
         if getattr(self, "handle", None):

@@ -693,40 +693,89 @@ def test_denoising_flattens_noise_spikes(noisy):
 # Batched solves of several streams
 # --------------------------------------------------------------------------
 
-BATCH_SHAPES = [(128, 128), (240, 180), (67, 45), (346, 260), (1, 37), (200, 7)]
+BATCH_SHAPES = [(128, 128), (240, 180), (67, 45), (346, 260), (1, 37), (200, 7), (128, 128),
+                (240, 180)]
 
 
-def test_batch_equals_individual_solves():
-    """A batched solve gives each stream the same bits as solving it alone
-    with the same iterations per launch; the autotuner leaves state alone."""
-    import torch
+@pytest.mark.parametrize("mode,tune", [(rec.REC_BATCH_SERIAL, 0), (rec.REC_BATCH_STREAMS, 0),
+                                       (rec.REC_BATCH_GRAPH, 0), (rec.REC_BATCH_STREAMS, 50),
+                                       (rec.REC_BATCH_GRAPH, 50)])
+def test_batch_equals_individual_solves(mode, tune):
+    """A batched solve gives each stream the same bits as solving it alone,
+    whatever the class geometries (one class per sensor size, each with its
+    own autotuned tile and iterations per launch) and however the class
+    chains are issued; the autotuner leaves state alone.  In graph mode the
+    captured solves are replayed over several blocks (two descriptor
+    buffers, folded and scattered pushes, two iteration counts) with the
+    program's own eager work and readbacks between replays, and every
+    replay is checked.  Untuned, all sizes share one geometry; tuned, the
+    sizes may get several."""
     rng = np.random.default_rng(4)
+    steps = 6
     streams = []
-    for (W, H) in BATCH_SHAPES:
+    for i, (W, H) in enumerate(BATCH_SHAPES):
         n = int(rng.integers(200, 3000))
-        streams.append(_random_stream(W, H, 3 * n, seed=W * 31 + H))
+        streams.append(_random_stream(W, H, steps * n, seed=W * 31 + H + i))
     recs = [rec.Reconstructor(W, H) for (W, H) in BATCH_SHAPES]
     u_before = [r.image(rec.REC_U) for r in recs]
-    batch = rec.Batch(recs, tune_iters=50)
-    rows, waves, K, us = batch.config()
-    assert rows * waves > 2 * K and us > 0
+    batch = rec.Batch(recs, tune_iters=tune)
+    if not tune:
+        # several classes: geometries set per sensor size (32- and 64-column
+        # tiles, different iterations per launch)
+        assert len(batch.config()) == 1
+        for (W, H), geo in zip(BATCH_SHAPES, [(1, 16, 32, 10), (2, 8, 32, 8), (8, 8, 64, 6),
+                                              (4, 16, 64, 13)]):
+            batch.set_geometry(W, H, *geo)
+    cfg = batch.config()
+    print(f"mode {mode} tune {tune}: classes {cfg}", flush=True)
+    assert 1 <= len(cfg) <= len(set(BATCH_SHAPES))
+    assert len(cfg) == 5 or tune
+    assert sum(c["streams"] for c in cfg) == len(BATCH_SHAPES)
+    for c in cfg:
+        assert c["rows"] * c["waves"] * (64 // c["cols"]) > 2 * c["kiters"]
+        assert (c["tuned_us"] > 0) == (tune > 0)
     for r, u in zip(recs, u_before):
         assert np.array_equal(r.image(rec.REC_U), u)
-    solo = [rec.Reconstructor(W, H, fuse_iters=K) for (W, H) in BATCH_SHAPES]
-    for step in range(3):
+    batch.set_mode(mode)
+    solo = [rec.Reconstructor(W, H) for (W, H) in BATCH_SHAPES]
+    for step in range(steps):
+        iters = 50 if step == 4 else 37
+        host = step == 3  # scattered pushes: no class folds events into its first launch
         for (t, x, y, p), r, s in zip(streams, recs, solo):
-            n = len(t) // 3
+            n = len(t) // steps
             sl = slice(step * n, (step + 1) * n)
             ev = evgen.Events(t[sl], x[sl], y[sl], p[sl], np.zeros(n, np.uint8))
-            r.push(*device_events(ev), on_device=True)
-            s.push(*device_events(ev), on_device=True)
-        batch.solve(37)
+            if host:
+                r.push(ev.t, ev.x, ev.y, ev.p)
+                s.push(ev.t, ev.x, ev.y, ev.p)
+            else:
+                r.push(*device_events(ev), on_device=True)
+                s.push(*device_events(ev), on_device=True)
+        batch.solve(iters)
         for s in solo:
-            s.solve(37)
-    for r, s in zip(recs, solo):
-        assert np.array_equal(r.image(rec.REC_U), s.image(rec.REC_U))
-        assert np.array_equal(r.image(rec.REC_STATE_P), s.image(rec.REC_STATE_P))
-        assert np.array_equal(r.image(rec.REC_T_LAST), s.image(rec.REC_T_LAST))
+            s.solve(iters)
+        for i, (r, s) in enumerate(zip(recs, solo)):
+            assert np.array_equal(r.image(rec.REC_U), s.image(rec.REC_U)), (step, i)
+            assert np.array_equal(r.image(rec.REC_STATE_P), s.image(rec.REC_STATE_P)), (step, i)
+            assert np.array_equal(r.image(rec.REC_T_LAST), s.image(rec.REC_T_LAST)), (step, i)
+    batch.close()
+
+
+def test_batch_geometry_checks():
+    """Geometries outside the batched launch's set, halos that leave no
+    interior and sizes not in the batch are refused and change nothing."""
+    recs = [rec.Reconstructor(64, 32), rec.Reconstructor(40, 40)]
+    batch = rec.Batch(recs, tune_iters=0)
+    before = batch.config()
+    for args in [(64, 32, 3, 3, 64, 4), (64, 32, 8, 8, 48, 4), (64, 32, 1, 16, 64, 4),
+                 (64, 32, 8, 8, 64, 32), (64, 32, 1, 16, 32, 16), (64, 32, 8, 8, 64, 0),
+                 (65, 32, 8, 8, 64, 6)]:
+        with pytest.raises(rec.RecError) as e:
+            batch.set_geometry(*args)
+        assert e.value.code == rec.REC_EINVAL
+    assert batch.config() == before
+    batch.set_geometry(40, 40, 2, 8, 32, 15)
+    assert len(batch.config()) == 2
     batch.close()
 
 
