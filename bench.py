@@ -45,12 +45,16 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "rec_api.hip")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("bc17ad4b7dc66c01", 2 * 1024 * 1070.5, 1024 * 820.7),
-    ("probe", "f32"): ("bc17ad4b7dc66c01", 2 * 1024 * 553321.7, 1024 * 546294.9),
+    ("davis240", "f32"): ("e4963692c81c9f05", 2 * 1024 * 1070.5, 1024 * 820.7),
+    ("probe", "f32"): ("e4963692c81c9f05", 2 * 1024 * 553343.0, 1024 * 546325.4),
     # the batched solve of all 64 cameras: bytes of one whole solve (every
     # launch of every class chain), for the class geometries below
+    ("streams64", "f32"): ("e4963692c81c9f05", 2 * 1024 * 816963.9, 1024 * 1068848.3),
 }
-STREAMS64_MEASURED_SHAPE = None  # class geometries the counters were taken with
+# class geometries the 64-camera counters were taken with: (width, height of
+# the class's first camera, rows, waves, columns, iterations per launch)
+STREAMS64_MEASURED_SHAPE = [(640, 480, 8, 8, 64, 6), (240, 180, 8, 8, 64, 8),
+                            (346, 260, 8, 8, 64, 9), (128, 128, 8, 8, 64, 10)]
 
 
 def kernel_source_hash() -> str:
@@ -191,7 +195,8 @@ def streams64(steps, seed=400):
 BATCH_MODES = {"serial": 0, "streams": 1, "graph": 2}
 
 
-def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph")):
+def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph"),
+                  geometry=None, per_camera=True, profile=True):
     """Time `steps` blocks of all 64 cameras: the batched solve in each of
     `modes` (each pass after 2 warm-up blocks of its own; the first listed
     is also profiled), then one solve per camera.  Returns per-pass seconds,
@@ -200,7 +205,7 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
     import torch
     from paper_1607_06283_amd import rec
 
-    passes = len(modes) + 2  # the modes, the profiled pass, the per-camera solves
+    passes = len(modes) + int(per_camera) + int(profile)
     cams = streams64(warmup + passes * (steps + 2))
     dev = torch.device("cuda", 0)
     recs, bufs = [], []
@@ -208,7 +213,9 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
         recs.append(rec.Reconstructor(W, H))
         bufs.append((torch.from_numpy(ev.t).to(dev), torch.from_numpy(ev.x.view(np.int16)).to(dev),
                      torch.from_numpy(ev.y.view(np.int16)).to(dev), torch.from_numpy(ev.p).to(dev), bs))
-    batch = rec.Batch(recs, tune_iters=iters if tune else 0)
+    batch = rec.Batch(recs, tune_iters=iters if tune and not geometry else 0)
+    for g in geometry or ():
+        batch.set_geometry(*g)
     block = [0]
 
     def step(batched):
@@ -245,11 +252,14 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
         batch.set_mode(BATCH_MODES[m])
         out[m] = timed_pass(True)
     batch.set_mode(BATCH_MODES[modes[0]])
-    rec.rec_profile(recs[0].ctx, True)
-    timed_pass(True)
-    prof = rec.rec_profile_read(recs[0].ctx)
-    rec.rec_profile(recs[0].ctx, False)
-    out["per_camera"] = timed_pass(False)
+    prof = None
+    if profile:
+        rec.rec_profile(recs[0].ctx, True)
+        timed_pass(True)
+        prof = rec.rec_profile_read(recs[0].ctx)
+        rec.rec_profile(recs[0].ctx, False)
+    if per_camera:
+        out["per_camera"] = timed_pass(False)
     cfg = batch.config()
     px = sum(W * H for W, H, _, _ in cams)
     ev_per_step = sum(bs for _, _, bs, _ in cams)
@@ -259,25 +269,30 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
     return out, prof, cfg, px, ev_per_step
 
 
-def streams64_result(steps, warmup, iters, tune=True):
+def streams64_result(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph"),
+                     geometry=None, per_camera=True, profile=True):
     """The 64-camera workload: the batched solve in its default mode (the
     first of the timed modes) with the other modes and one solve per camera
     beside it, the class geometries, and the roofline of the batched launch."""
-    dts, prof, cfg, px, evs = run_streams64(steps, warmup, iters, tune=tune)
-    dt = dts["streams"]
+    dts, prof, cfg, px, evs = run_streams64(steps, warmup, iters, tune=tune, modes=modes,
+                                            geometry=geometry, per_camera=per_camera,
+                                            profile=profile)
+    dt = dts[modes[0]]
     rate = lambda d: round(steps * iters * px / d / 1e6, 2)
     res = {
         "value": rate(dt), "ms_per_step": round(dt / steps * 1e3, 4),
         "events_per_s": round(steps * evs / dt, 1),
         "modes": {m: {"PD iter*Mpix/s": rate(d), "ms_per_step": round(d / steps * 1e3, 4)}
                   for m, d in dts.items() if m != "per_camera"},
-        "per_camera_solves": {"PD iter*Mpix/s": rate(dts["per_camera"]),
-                              "ms_per_step": round(dts["per_camera"] / steps * 1e3, 4)},
-        "batched_speedup": round(dts["per_camera"] / dt, 3),
         "classes": [{k: (round(v, 1) if isinstance(v, float) else v) for k, v in c.items()}
                     for c in cfg],
-        "roofline": batch_roofline(dt / steps, px * iters, cfg, prof),
     }
+    if per_camera:
+        res["per_camera_solves"] = {"PD iter*Mpix/s": rate(dts["per_camera"]),
+                                    "ms_per_step": round(dts["per_camera"] / steps * 1e3, 4)}
+        res["batched_speedup"] = round(dts["per_camera"] / dt, 3)
+    if profile:
+        res["roofline"] = batch_roofline(dt / steps, px * iters, cfg, prof)
     return res
 
 
@@ -289,7 +304,8 @@ def batch_roofline(step_s, px_iters, cfg, prof):
     sources and class geometries.  The per-launch kernel times (events in
     the launch packets, overlapping across classes) are given beside it."""
     achieved = BYTES_PER_PX_ITER * px_iters / step_s / 1e9
-    shapes = [(c["rows"], c["waves"], c["cols"], c["kiters"]) for c in cfg]
+    shapes = [(c["width"], c["height"], c["rows"], c["waves"], c["cols"], c["kiters"])
+              for c in cfg]
     m = MEASURED_TRAFFIC.get(("streams64", "f32"))
     traffic = None
     if m and m[0] == kernel_source_hash() and shapes == STREAMS64_MEASURED_SHAPE:
@@ -412,19 +428,52 @@ def copy_probe(mib=256, reps=5):
           flush=True)
 
 
+# Grids of the sync probe: the 240x180 workload's fused launch (234 tiles of
+# 32x32 pixels, 1024 threads), and 512 workgroups of 512 threads, the most
+# that are co-resident with the 64-camera batched launch's 8x8 tiles (two
+# per compute unit), which a persistent form of that launch would run.
+SYNC_PROBE_GRIDS = [(234, 1024), (512, 512)]
+
+
+def sync_probe():
+    import subprocess
+
+    exe = os.path.join(ROOT, "paper_1607_06283_amd", "sync_probe")
+    if not os.path.exists(exe):
+        raise SystemExit(f"{exe} is missing: run paper_1607_06283_amd.build.build()")
+    for nb, nt in SYNC_PROBE_GRIDS:
+        log(f"bench: sync probe {nb} x {nt}")
+        out = subprocess.run([exe, str(nb), str(nt)], capture_output=True, text=True, timeout=120)
+        if out.returncode != 0:
+            raise SystemExit(f"sync_probe failed ({out.returncode}): {out.stderr.strip()}")
+        print(out.stdout.strip(), flush=True)
+
+
 def main_streams64(args):
     steps = min(args.steps, 40)
     warmup = min(args.warmup, 5)
     IT = WORKLOADS["streams64"][3]
     log("bench: 64 cameras (batched in each mode, then one solve per camera)")
-    r = streams64_result(steps, warmup, IT, tune=not args.no_tune)
+    geometry = None
+    if args.batch_geometry:
+        # W x H : rows x waves x cols : K, comma separated
+        geometry = []
+        for item in args.batch_geometry.split(","):
+            size, shape, k = item.split(":")
+            w, h = size.split("x")
+            r, wv, c = shape.split("x")
+            geometry.append((int(w), int(h), int(r), int(wv), int(c), int(k)))
+    modes = tuple(args.batch_modes.split(","))
+    r = streams64_result(steps, warmup, IT, tune=not args.no_tune, modes=modes, geometry=geometry,
+                         per_camera=not args.no_per_camera, profile=not args.no_profile)
     out = {
         "metric": METRIC, "value": r.pop("value"), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": r.pop("ms_per_step"),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "storage": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["streams64"], "cameras": 64,
-                   "iters_per_batch": IT, "autotuned": not args.no_tune},
+                   "iters_per_batch": IT, "autotuned": not (args.no_tune or geometry),
+                   "mode": modes[0]},
     }
     out.update(r)
     print(json.dumps(out), flush=True)
@@ -579,8 +628,19 @@ def main():
                          "oracle's 128x128 / differentiation-forward timings")
     ap.add_argument("--no-tune", action="store_true",
                     help="streams64: keep the default tile geometry instead of autotuning")
+    ap.add_argument("--batch-geometry", default="",
+                    help="streams64: fixed geometries instead of the autotuner, e.g. "
+                         "640x480:8x8x64:6,240x180:8x8x64:8 (size:rows x waves x cols:K)")
+    ap.add_argument("--batch-modes", default="streams,serial,graph",
+                    help="streams64: launch modes to time, the first is the reported value")
+    ap.add_argument("--no-per-camera", action="store_true",
+                    help="streams64: skip the one-solve-per-camera comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 256 MiB device-to-device copy (calibrates HBM byte counters)")
+    ap.add_argument("--sync-probe", action="store_true",
+                    help="only time the launch-to-launch and grid-barrier alternatives on the "
+                         "240x180 fused launch's grid and on a co-resident grid at the 64-camera "
+                         "scale (runs the sync_probe program built beside the library)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the reconstruction of one event stream runs on "
@@ -596,6 +656,8 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    if args.sync_probe:
+        return sync_probe()
     if args.workload == "diff16":
         return main_diff16(args)
     if args.workload == "streams64":

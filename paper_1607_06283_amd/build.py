@@ -1,4 +1,5 @@
-"""Builds ``librec.so`` (the C-ABI library) in-tree with hipcc for gfx950."""
+"""Builds ``librec.so`` (the C-ABI library) and the benchmark's launch /
+grid-synchronisation probe ``sync_probe`` in-tree with hipcc for gfx950."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librec.so")
+PROBE_PATH = os.path.join(HERE, "sync_probe")
 SOURCES = ["kernels.hip", "rec_api.hip", "adjoint.hip"]
 ARCH = "gfx950"
 
@@ -46,6 +48,12 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB_PATH)
+    # the launch / grid-synchronisation probe of the benchmark harness
+    cmd = [hipcc(), *HIPCC_FLAGS, "-o", PROBE_PATH + ".tmp", os.path.join(CSRC, "sync_probe.hip")]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(PROBE_PATH + ".tmp", PROBE_PATH)
     return LIB_PATH
 
 
