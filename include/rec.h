@@ -53,10 +53,15 @@
  *     their own at that point).  Host-pointer pushes are validated on the
  *     host, copied through the pinned staging buffer and scattered at once.
  *   - rec_push_events and rec_solve without stats do not synchronise.
- *     rec_solve with stats, rec_get_image, rec_gap_history,
- *     rec_profile_read, rec_sync and rec_destroy synchronise the stream.
+ *     rec_solve with stats, rec_get_image, rec_gap_history, rec_get_times,
+ *     rec_set_state, rec_profile_read, rec_sync and rec_destroy synchronise
+ *     the stream.
  *   - Errors found on the device (device-pointer pushes) are reported by the
  *     next synchronising call; the rejected push changes no state.
+ *   - After REC_EDEVICE the context's state is undefined: destroy it, or
+ *     restore a checkpoint with rec_set_state.  (Tests force this path with
+ *     REC_FAULT_AFTER=n in the environment: every launch after the process's
+ *     first n fails without being issued.)
  *
  * Threading: a context must not be used from two threads at once; distinct
  * contexts are independent.  The only global state of the library is the
@@ -82,7 +87,8 @@ enum {
     REC_EDEVICE = -4,  /* a HIP runtime call failed */
     REC_ENUMERIC = -5, /* non-finite gap or energy */
     REC_ESTATE = -6,   /* call not valid in the object's state: rec_destroy of a
-                          context that a live batch still holds */
+                          context that a live batch still holds, rec_set_state
+                          with pushes pending */
     REC_ENOMEM = -7    /* workspace too small, host allocation failed, or input larger
                           than the static array of rec_diff_forward_noalloc */
 };
@@ -245,6 +251,30 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats);
  * pushes are scattered first, so count, time and latest-timestamp planes
  * include them.  REC_EINVAL for an unknown plane or NULL out. */
 int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device);
+
+/* The stream's first and latest accepted timestamps (0, 0 and *started = 0
+ * before any event).  Synchronises; scatters recorded device pushes first and
+ * reports deferred push errors.  Any output may be NULL. */
+int rec_get_times(rec_ctx* c, int64_t* t_first, int64_t* t_ref, int32_t* started);
+
+/* Checkpoint / resume (not in the paper, whose state between blocks is the
+ * warm start (u, p) of Section 3.2 and the time surface of Section 3.1):
+ * replace the context's state with u (float[H*W], each finite and > 0), p
+ * (float[3*H*W] in the standard basis, planes p1, p2, p3, as rec_get_image
+ * REC_STATE_P returns it; NULL for zero) and the latest timestamps t_last
+ * (int64[H*W], as REC_T_LAST returns it) with t_ref the stream's latest
+ * timestamp (rec_get_times); t_ref == INT64_MIN imports a stream that has
+ * seen no event (t_last ignored, may be NULL).  With the planes exported
+ * from another context of the same parameters after a solve, the next
+ * pushes and solves give the same bits as that context would.  Planes of
+ * the last solve (f, tx, ty, G) are not imported: the next solve rebuilds
+ * them; the stream's first timestamp becomes the earliest imported one.
+ * Host arrays (on_device == 0) are validated: REC_EINVAL for a bad u
+ * or p value, REC_EORDER for a t_last above t_ref; device arrays are not
+ * and must not overlap the workspace.  REC_ESTATE while pushes are pending
+ * (solve them first).  Synchronises. */
+int rec_set_state(rec_ctx* c, const float* u, const float* p, const int64_t* t_last,
+                  int64_t t_ref, int on_device);
 
 /* Gap and energy samples of the last rec_solve, in order; returns the number
  * of samples (>= 0) or an error.  At most cap values are written. */

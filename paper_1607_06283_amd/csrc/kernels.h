@@ -163,6 +163,12 @@ hipError_t launch_time_plane(const Planes& P, Frame fr, double time_unit_us, flo
 hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* out, hipStream_t s);
 hipError_t launch_tlast_plane(const Planes& P, Frame fr, int64_t* out, hipStream_t s);
 hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s);
+// State import into the current planes (u, p in the standard basis or NULL
+// for zero, latest timestamps; kNever everywhere when !started); the
+// stream state must have been written first, with t_first = INT64_MAX when
+// started (the launch lowers it to the earliest imported timestamp).
+hipError_t launch_import(const Planes& P, Frame fr, int cur, int storage, const float* u,
+                         const float* p, const int64_t* t_last, bool started, hipStream_t s);
 // Batched solve: one launch over the work list of (stream, tile) pairs.
 // K iterations in this launch, KG the halo of the tile geometry (K <= KG),
 // li the launch's index within the solve, bins: some stream folds events.

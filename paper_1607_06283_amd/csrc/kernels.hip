@@ -15,6 +15,9 @@
 //   k_gap, k_gap_final  primal-dual gap and energy (FP64 accumulation)
 //   k_time_plane, k_metric_plane   readback helpers
 #include <hip/hip_ext.h>
+#include <stdlib.h>
+
+#include <atomic>
 
 #include "kernels.h"
 #include "pd_math.h"
@@ -36,10 +39,26 @@ __device__ __forceinline__ int64_t resolved_last(int64_t tl, int64_t t_first) {
     return tl == kNever ? t_first : tl;
 }
 
+// Fault injection for tests of the error paths: with REC_FAULT_AFTER=n in
+// the environment (read at the first launch), every launch after the
+// process's first n fails with hipErrorLaunchFailure and is not issued.
+std::atomic<long long> g_launches{0};
+
+long long fault_after() {
+    static const long long n = [] {
+        const char* e = getenv("REC_FAULT_AFTER");
+        return e && *e ? atoll(e) : -1LL;
+    }();
+    return n;
+}
+
 // Launch with optional timing events carried by the dispatch itself.
 template <typename Kern, typename... Args>
 hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, hipEvent_t a,
                   hipEvent_t z, Args... args) {
+    const long long fa = fault_after();
+    if (fa >= 0 && g_launches.fetch_add(1, std::memory_order_relaxed) >= fa)
+        return hipErrorLaunchFailure;
     if (a || z)
         hipExtLaunchKernelGGL(kernel, grid, block, lds, s, a, z, 0, args...);
     else
@@ -288,6 +307,32 @@ __global__ void k_tlast_plane(Planes P, Frame fr, int64_t* out) {
     const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= np) return;
     out[k] = resolved_last(P.t_last[k], P.st->t_first);
+}
+
+// State import: u, p (standard basis) and the latest timestamps into the
+// current planes; counts cleared.  The stream state was written by the host
+// before the launch, with t_first = INT64_MAX when started: the stream's
+// first timestamp becomes the earliest imported one.
+template <class S>
+__global__ void k_import(Planes P, size_t np, int cur, const float* u, const float* p,
+                         const int64_t* t_last, int started) {
+    const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= np) return;
+    // each thread reads its own pixel of the staging before any write, and
+    // only its own pixel is written: staging and state may overlap no other
+    // thread's data
+    const float uu = u[k];
+    const float a = p ? p[k] : 0.0f, b = p ? p[np + k] : 0.0f, c = p ? p[2 * np + k] : 0.0f;
+    const int64_t tl = started ? t_last[k] : kNever;
+    typename S::T* pc = (typename S::T*)P.p[cur];
+    P.u[cur][k] = uu;
+    S::st(pc, k, a);
+    S::st(pc, np + k, b);
+    S::st(pc, 2 * np + k, c);
+    P.t_last[k] = tl;
+    P.npos[k] = 0;
+    P.nneg[k] = 0;
+    if (started) atomicMin((long long*)&P.st->t_first, (long long)tl);
 }
 
 template <class S>
@@ -1529,6 +1574,20 @@ hipError_t launch_metric_plane(const Planes& P, Frame fr, int storage, float* ou
     if (storage == kStoreBF16)
         return launch(k_metric_plane<StoreBF16>, g, b, 0, s, nullptr, nullptr, P, fr, out);
     return launch(k_metric_plane<StoreF32>, g, b, 0, s, nullptr, nullptr, P, fr, out);
+}
+
+hipError_t launch_import(const Planes& P, Frame fr, int cur, int storage, const float* u,
+                         const float* p, const int64_t* t_last, bool started, hipStream_t s) {
+    const size_t np = (size_t)fr.W * fr.H;
+    const dim3 g(blocks_for(np, 256)), b(256);
+    const int st = started ? 1 : 0;
+    if (storage == kStoreF16)
+        return launch(k_import<StoreF16>, g, b, 0, s, nullptr, nullptr, P, np, cur, u, p, t_last,
+                      st);
+    if (storage == kStoreBF16)
+        return launch(k_import<StoreBF16>, g, b, 0, s, nullptr, nullptr, P, np, cur, u, p, t_last,
+                      st);
+    return launch(k_import<StoreF32>, g, b, 0, s, nullptr, nullptr, P, np, cur, u, p, t_last, st);
 }
 
 hipError_t launch_widen(const void* src, int storage, float* out, size_t n, hipStream_t s) {

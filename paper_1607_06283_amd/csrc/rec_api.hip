@@ -752,6 +752,75 @@ int rec_profile_read(rec_ctx* c, rec_profile_t* out) {
     return REC_OK;
 }
 
+int rec_get_times(rec_ctx* c, int64_t* t_first, int64_t* t_ref, int32_t* started) {
+    if (!c) return REC_EINVAL;
+    int rc = flush_deferred(c);
+    if (rc) return rc;
+    rec::DevState st;
+    rc = read_state(c, &st);
+    if (rc) return rc;
+    if (t_first) *t_first = st.started ? st.t_first : 0;
+    if (t_ref) *t_ref = st.started ? st.t_ref : 0;
+    if (started) *started = st.started;
+    return REC_OK;
+}
+
+int rec_set_state(rec_ctx* c, const float* u, const float* p, const int64_t* t_last,
+                  int64_t t_ref, int on_device) {
+    if (!c || !u) return REC_EINVAL;
+    const bool started = t_ref != INT64_MIN;
+    if (started && !t_last) return REC_EINVAL;
+    // only between blocks: no pushed events may be pending
+    if (!c->deferred.empty() || c->counts_dirty) return REC_ESTATE;
+    const size_t np = (size_t)c->fr.W * c->fr.H;
+    if (!on_device) {
+        for (size_t k = 0; k < np; ++k)
+            if (!(isfinite(u[k]) && u[k] > 0.0f)) return REC_EINVAL;
+        for (size_t k = 0; p && k < 3 * np; ++k)
+            if (!isfinite(p[k])) return REC_EINVAL;
+        for (size_t k = 0; started && k < np; ++k)
+            if (t_last[k] > t_ref) return REC_EORDER;
+    }
+    // host arrays go straight into the current planes (the import kernel
+    // then rewrites each pixel from its own value) or, for p in 16-bit
+    // storage, through the spare FP32-sized dual planes
+    const float* du = u;
+    const float* dp = p;
+    const int64_t* dt = t_last;
+    hipError_t e = hipSuccess;
+    if (!on_device) {
+        const bool f32 = c->prm.storage == rec::kStoreF32;
+        float* pst = f32 ? c->P.p[c->cur] : c->P.p[c->cur ^ 1];
+        e = hipMemcpyAsync(c->P.u[c->cur], u, np * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && p)
+            e = hipMemcpyAsync(pst, p, 3 * np * 4, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess && started)
+            e = hipMemcpyAsync(c->P.t_last, t_last, np * 8, hipMemcpyHostToDevice, c->stream);
+        du = c->P.u[c->cur];
+        dp = p ? pst : nullptr;
+        dt = started ? c->P.t_last : nullptr;
+    }
+    // the stream state, written once the copies above are done
+    rec::DevState st;
+    memset(&st, 0, sizeof(st));
+    st.t_ref = started ? t_ref : 0;
+    st.t_first = started ? INT64_MAX : 0;
+    st.first_bad = rec::kNoBad;
+    st.started = started ? 1 : 0;
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(c->P.st, &st, sizeof(st), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = rec::launch_import(c->P, c->fr, c->cur, c->prm.storage, du, dp, dt, started,
+                               c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return REC_EDEVICE;
+    c->mirror_known = true;
+    c->mirror_started = started;
+    c->mirror_tref = started ? t_ref : 0;
+    c->gap_samples = 0;
+    return REC_OK;
+}
+
 int rec_destroy(rec_ctx* c) {
     if (!c) return REC_OK;
     if (c->batch_refs > 0) return REC_ESTATE;  // a live batch still uses it

@@ -73,6 +73,7 @@ class rec_profile_t(ctypes.Structure):
 EXPORTS = (
     "rec_default_params", "rec_check_params", "rec_workspace_bytes", "rec_check_events",
     "rec_init", "rec_push_events", "rec_solve", "rec_get_image", "rec_gap_history",
+    "rec_get_times", "rec_set_state",
     "rec_sync", "rec_profile", "rec_profile_read", "rec_destroy", "rec_strerror",
     "rec_batch_workspace_bytes", "rec_batch_init", "rec_batch_solve", "rec_batch_config",
     "rec_batch_classes", "rec_batch_set_geometry", "rec_batch_set_mode", "rec_batch_destroy",
@@ -138,6 +139,11 @@ def load() -> ctypes.CDLL:
     lib.rec_get_image.argtypes = [_vp, ctypes.c_int32, _vp, ctypes.c_int]
     lib.rec_gap_history.restype = ctypes.c_int
     lib.rec_gap_history.argtypes = [_vp, _vp, _vp, ctypes.c_int32]
+    lib.rec_get_times.restype = ctypes.c_int
+    lib.rec_get_times.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]
+    lib.rec_set_state.restype = ctypes.c_int
+    lib.rec_set_state.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, ctypes.c_int]
     lib.rec_sync.restype = ctypes.c_int
     lib.rec_sync.argtypes = [_vp]
     lib.rec_profile.restype = ctypes.c_int
@@ -260,6 +266,21 @@ def rec_gap_history(ctx: int, cap: int = 4096) -> Tuple[np.ndarray, np.ndarray]:
     n = _check(load().rec_gap_history(ctx, g.ctypes.data, e.ctypes.data, int(cap)),
                "rec_gap_history")
     return g[:n], e[:n]
+
+
+def rec_get_times(ctx: int) -> Tuple[int, int, int, int]:
+    """(status, t_first, t_ref, started)."""
+    tf, tr, st = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+    rc = load().rec_get_times(ctx, ctypes.byref(tf), ctypes.byref(tr), ctypes.byref(st))
+    return rc, tf.value, tr.value, st.value
+
+
+NO_EVENT = -(1 << 63)  # t_ref of rec_set_state for a stream that has seen no event
+
+
+def rec_set_state(ctx: int, u, p, t_last, t_ref: int, on_device: int) -> int:
+    return load().rec_set_state(ctx, _addr(u), _addr(p), _addr(t_last), int(t_ref),
+                                int(on_device))
 
 
 def rec_sync(ctx: int) -> int:
@@ -392,6 +413,30 @@ class Reconstructor:
     def sync(self) -> None:
         _check(rec_sync(self.ctx), "rec_sync")
         self._pending.clear()
+
+    def times(self) -> Tuple[int, int, bool]:
+        """(first, latest accepted timestamp, whether any event was accepted)."""
+        rc, tf, tr, st = rec_get_times(self.ctx)
+        _check(rc, "rec_get_times")
+        self._pending.clear()
+        return tf, tr, bool(st)
+
+    def state(self) -> dict:
+        """A checkpoint of the stream: u, p, latest timestamps and t_ref
+        (host arrays), for ``set_state`` of this or another context."""
+        _, t_ref, started = self.times()
+        return {"u": self.image(REC_U), "p": self.image(REC_STATE_P),
+                "t_last": self.image(REC_T_LAST), "t_ref": t_ref if started else NO_EVENT}
+
+    def set_state(self, u, p, t_last, t_ref: int) -> None:
+        """Import a checkpoint (numpy arrays, or device tensors)."""
+        on_device = not isinstance(u, np.ndarray)
+        if not on_device:
+            u = np.ascontiguousarray(u, np.float32)
+            p = None if p is None else np.ascontiguousarray(p, np.float32)
+            t_last = None if t_last is None else np.ascontiguousarray(t_last, np.int64)
+        _check(rec_set_state(self.ctx, u, p, t_last, t_ref, 1 if on_device else 0),
+               "rec_set_state")
 
 
 def _ctx_array(ctxs):
