@@ -813,18 +813,38 @@ def bench_streams64(steps=20, warmup=3):
     return r
 
 
+# The HBM-bound form of the probe: one iteration per launch, so every
+# pixel-iteration reads and writes the whole state (44 B) once; the tile that
+# streams best in this form (2 rows x 8 wavefronts x 64 columns, a sweep of 11
+# shapes in profiles/k_pd_fused_probe_hbm.md).
+PROBE_K1_TILE = (2, 8, 64)
+
+
 def bench_probe(steps=10, warmup=2):
     """5120x5760 frame, uniform random events, blocks of 20000, 50 iterations:
-    a state beyond the Infinity Cache, so the fused loop streams from HBM."""
+    a state beyond the Infinity Cache, so the fused loop streams from HBM.
+    Also the one-iteration-per-launch form, whose algorithmic bytes are its
+    HBM bytes."""
     W, H, B, IT = WORKLOADS["probe"]
     ev = random_stream(W, H, (steps + warmup) * B)
     kw = dict(shape=(W, H), batch=B, iters=IT)
     dt, _, _ = run_gpu(ev, steps, warmup, -1, profile=False, **kw)
     _, prof, _ = run_gpu(ev, steps, warmup, -1, profile=True, **kw)
-    return {"workload": WORKLOAD_TEXT["probe"], "steps": steps, "warmup": warmup,
-            "PD iter*Mpix/s": round(steps * IT * W * H / dt / 1e6, 2),
-            "ms_per_step": round(dt / steps * 1e3, 4),
-            "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused", ("probe", "f32"))}
+    out = {"workload": WORKLOAD_TEXT["probe"], "steps": steps, "warmup": warmup,
+           "PD iter*Mpix/s": round(steps * IT * W * H / dt / 1e6, 2),
+           "ms_per_step": round(dt / steps * 1e3, 4),
+           "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused", ("probe", "f32"))}
+    r, w, c = PROBE_K1_TILE
+    k1 = dict(kw, rows=r, waves=w, cols=c)
+    s1, w1 = max(2, steps // 3), 1
+    dt, _, _ = run_gpu(ev, s1, w1, 1, profile=False, **k1)
+    _, prof, _ = run_gpu(ev, s1, w1, 1, profile=True, **k1)
+    out["one_iteration_per_launch"] = {
+        "tile": {"rows": r, "waves": w, "cols": c}, "steps": s1, "warmup": w1,
+        "PD iter*Mpix/s": round(s1 * IT * W * H / dt / 1e6, 2),
+        "ms_per_step": round(dt / s1 * 1e3, 4),
+        "roofline": roofline(prof, BYTES_PER_PX_ITER, "k_pd_fused", ("probe_k1", "f32"))}
+    return out
 
 
 if __name__ == "__main__":

@@ -171,6 +171,18 @@ def test_null_context_calls():
     assert rec.rec_solve(None, 5)[0] == rec.REC_EINVAL
     assert rec.rec_sync(None) == rec.REC_EINVAL
     assert rec.rec_destroy(None) == rec.REC_OK
+    assert rec.rec_get_times(None)[0] == rec.REC_EINVAL
+    u = np.ones(4, np.float32)
+    assert rec.rec_set_state(None, u, None, None, rec.NO_EVENT, 0) == rec.REC_EINVAL
+    assert rec.rec_batch_classes(None) == rec.REC_EINVAL
+    assert rec.rec_batch_set_mode(None, rec.REC_BATCH_GRAPH) == rec.REC_EINVAL
+    assert rec.rec_batch_set_geometry(None, 64, 32, 8, 8, 64, 6) == rec.REC_EINVAL
+    assert rec.rec_batch_solve(None, 10) == rec.REC_EINVAL
+    assert rec.rec_batch_destroy(None) == rec.REC_OK
+    import ctypes
+    c = rec.rec_batch_class()
+    assert rec.load().rec_batch_config(None, 0, ctypes.byref(c)) == rec.REC_EINVAL
+    assert ctypes.sizeof(rec.rec_batch_class) == 40
 
 
 def _diff_desc(**kw):
