@@ -990,10 +990,11 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         if (v == NV - 1) xu[NV][col] = 0.0f;
     }
 
-    // With few rows per lane the loop runs two iterations per trip, with u
-    // alternating between two register sets, so that passing u from one
-    // iteration to the next needs no register copies (with 8 or more rows
-    // the register pressure undoes the gain).  With 2 rows per lane (many
+    // With up to 8 rows per lane the loop runs two iterations per trip, with
+    // u alternating between two register sets, so that passing u from one
+    // iteration to the next needs no register copies (8 rows: 31 instead of
+    // 32 VALU instructions per pixel-iteration in the same 120 VGPRs; with
+    // 16 rows the register pressure undoes the gain).  With 2 rows per lane (many
     // wavefronts) a wavefront skips the iterations that cannot reach the
     // exact interior (about a third of them at K = 13).
     constexpr bool kSkip = R <= 2 && NW > 1;
@@ -1014,7 +1015,7 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
             tile_skip<NW>();
     };
     int it = 0;
-    if constexpr (R <= 6) {
+    if constexpr (R <= 8) {
         float ub[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) ub[r] = u[r];
