@@ -45,16 +45,19 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "rec_api.hip")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("e4963692c81c9f05", 2 * 1024 * 1070.5, 1024 * 820.7),
-    ("probe", "f32"): ("e4963692c81c9f05", 2 * 1024 * 553343.0, 1024 * 546325.4),
+    ("davis240", "f32"): ("b501431c04d4d34f", 2 * 1024 * 1072.0, 1024 * 820.7),
+    ("probe", "f32"): ("b501431c04d4d34f", 2 * 1024 * 553308.3, 1024 * 546416.9),
+    # the probe with one iteration per launch on 2 x 8 x 64 tiles
+    ("probe_k1", "f32"): ("b501431c04d4d34f", 2 * 1024 * 410600.0, 1024 * 477650.3),
     # the batched solve of all 64 cameras: bytes of one whole solve (every
     # launch of every class chain), for the class geometries below
-    ("streams64", "f32"): ("e4963692c81c9f05", 2 * 1024 * 816963.9, 1024 * 1068848.3),
+    ("streams64", "f32"): ("b501431c04d4d34f", 2 * 1024 * 818110.7, 1024 * 1068855.1),
 }
 # class geometries the 64-camera counters were taken with: (width, height of
 # the class's first camera, rows, waves, columns, iterations per launch)
 STREAMS64_MEASURED_SHAPE = [(640, 480, 8, 8, 64, 6), (240, 180, 8, 8, 64, 8),
                             (346, 260, 8, 8, 64, 9), (128, 128, 8, 8, 64, 10)]
+STREAMS64_PINNED = "640x480:8x8x64:6,240x180:8x8x64:8,346x260:8x8x64:9,128x128:8x8x64:10"
 
 
 def kernel_source_hash() -> str:
@@ -454,15 +457,7 @@ def main_streams64(args):
     warmup = min(args.warmup, 5)
     IT = WORKLOADS["streams64"][3]
     log("bench: 64 cameras (batched in each mode, then one solve per camera)")
-    geometry = None
-    if args.batch_geometry:
-        # W x H : rows x waves x cols : K, comma separated
-        geometry = []
-        for item in args.batch_geometry.split(","):
-            size, shape, k = item.split(":")
-            w, h = size.split("x")
-            r, wv, c = shape.split("x")
-            geometry.append((int(w), int(h), int(r), int(wv), int(c), int(k)))
+    geometry = parse_geometry(args.batch_geometry) if args.batch_geometry else None
     modes = tuple(args.batch_modes.split(","))
     r = streams64_result(steps, warmup, IT, tune=not args.no_tune, modes=modes, geometry=geometry,
                          per_camera=not args.no_per_camera, profile=not args.no_profile)
@@ -804,12 +799,29 @@ def bench_dvs128(n_blocks=200, warmup=20):
             "paper_context": PAPER_REALTIME}
 
 
+def parse_geometry(text):
+    """'WxH:RxWVxC:K,...' -> [(W, H, rows, waves, cols, K), ...]"""
+    out = []
+    for item in text.split(","):
+        size, shape, k = item.split(":")
+        w, h = size.split("x")
+        r, wv, c = shape.split("x")
+        out.append((int(w), int(h), int(r), int(wv), int(c), int(k)))
+    return out
+
+
 def bench_streams64(steps=20, warmup=3):
-    """64 cameras batched (autotuned), each launch mode, against one solve per camera."""
+    """64 cameras batched (autotuned), each launch mode, against one solve per
+    camera; then the same cameras with the geometry the HBM counters were
+    taken with, whose roofline carries the measured traffic."""
     IT = WORKLOADS["streams64"][3]
     r = streams64_result(steps, warmup, IT)
     r = {"workload": WORKLOAD_TEXT["streams64"], "steps": steps, "warmup": warmup,
          "PD iter*Mpix/s": r.pop("value"), **r}
+    p = streams64_result(steps, warmup, IT, tune=False, modes=("streams",),
+                         geometry=parse_geometry(STREAMS64_PINNED), per_camera=False)
+    r["pinned_geometry"] = {"geometry": STREAMS64_PINNED, "PD iter*Mpix/s": p["value"],
+                            "ms_per_step": p["ms_per_step"], "roofline": p["roofline"]}
     return r
 
 

@@ -14,6 +14,11 @@
 //   atomic_sync_us   one barrier on an atomic counter (agent scope, bounded spin)
 //   atomic_xchg_us   one such barrier with a store and a reload of 16 bytes per
 //                    thread around it (the halo exchange of a persistent solve)
+//   cross_stream_us  what a round trip through a second stream adds to a chain
+//                    of dependent launches: per group of 6 launches, an event
+//                    recorded after the 2nd, waited for by a second stream that
+//                    records an event of its own, which the next group's first
+//                    launch waits for (work moved off the chain would pay this)
 //
 // usage: sync_probe BLOCKS THREADS
 // Every spin is bounded: a grid that is not co-resident makes the barrier
@@ -184,15 +189,46 @@ int main(int argc, char** argv) {
         CHECK(hipFree(to));
         CHECK(hipFree(buf));
     }
+    // cross-stream round trip inside a chain of dependent launches
+    float cross = -1.0f;
+    {
+        hipStream_t b2;
+        hipEvent_t ea, eb;
+        CHECK(hipStreamCreateWithFlags(&b2, hipStreamNonBlocking));
+        CHECK(hipEventCreateWithFlags(&ea, hipEventDisableTiming));
+        CHECK(hipEventCreateWithFlags(&eb, hipEventDisableTiming));
+        const int groups = 200;
+        auto chain = [&](bool via) {
+            return tm.us(s, groups, [&] {
+                if (via) CHECK(hipStreamWaitEvent(s, eb, 0));
+                for (int k = 0; k < 6; ++k) {
+                    hipLaunchKernelGGL(k_empty, dim3(nb), dim3(nt), 0, s, nullptr);
+                    if (via && k == 1) {
+                        CHECK(hipEventRecord(ea, s));
+                        CHECK(hipStreamWaitEvent(b2, ea, 0));
+                        CHECK(hipEventRecord(eb, b2));
+                    }
+                }
+            });
+        };
+        CHECK(hipEventRecord(eb, b2));
+        const float plain6 = chain(false), via6 = chain(true);
+        cross = via6 - plain6;
+        CHECK(hipStreamSynchronize(b2));
+        CHECK(hipEventDestroy(ea));
+        CHECK(hipEventDestroy(eb));
+        CHECK(hipStreamDestroy(b2));
+    }
     auto per = [](float with, float without, int n) {
         return with < 0.0f || without < 0.0f ? -1.0f : (with - without) / n;
     };
     printf("{\"device\": \"%s\", \"cus\": %d, \"blocks\": %d, \"threads\": %d, "
            "\"coresident_blocks_per_cu\": %d, \"plain_us\": %.3f, \"graph_us\": %.3f, "
            "\"coop_launch_us\": %.3f, \"coop_sync_us\": %.3f, \"atomic_launch_us\": %.3f, "
-           "\"atomic_sync_us\": %.3f, \"atomic_xchg_us\": %.3f, \"barrier_timeout\": %d}\n",
+           "\"atomic_sync_us\": %.3f, \"atomic_xchg_us\": %.3f, \"cross_stream_us\": %.3f, "
+           "\"barrier_timeout\": %d}\n",
            pr.gcnArchName, cus, nb, nt, occ_atomic, plain, graph, coop0, per(coop5, coop0, 5), at0,
-           per(at5, at0, 5), per(ax5, at0, 5), timed_out);
+           per(at5, at0, 5), per(ax5, at0, 5), cross, timed_out);
     CHECK(hipStreamDestroy(s));
     return timed_out ? 3 : 0;
 }
