@@ -49,6 +49,8 @@
 
 #include <atomic>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "pd_math.h"
 #include "rec.h"
 #include "tile.h"
@@ -990,6 +992,16 @@ int scratch_address(void** out) {
 
 using namespace rec;
 
+namespace {
+// A roctx range around an entry point (rocprofv3 --marker-trace).
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+}  // namespace
+
 extern "C" {
 
 size_t rec_diff_workspace_bytes(const rec_diff_desc* d) {
@@ -999,6 +1011,7 @@ size_t rec_diff_workspace_bytes(const rec_diff_desc* d) {
 
 int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
                      float* p_out, void* dev_workspace, size_t ws_bytes, void* stream) {
+    Range range("rec_diff_forward");
     Ctx x;
     int rc = check_call(d, in, dev_workspace, ws_bytes, x);
     if (rc != REC_OK) return rc;
@@ -1036,6 +1049,7 @@ int rec_diff_forward(const rec_diff_desc* d, const rec_diff_inputs* in, float* u
 
 int rec_diff_forward_noalloc(const rec_diff_desc* d, const rec_diff_inputs* in, float* u_out,
                              float* p_out, void* stream) {
+    Range range("rec_diff_forward_noalloc");
     if (!inputs_ok(d, in) || !u_out) return REC_EINVAL;
     const size_t n = (size_t)d->width * d->height * d->batch;
     if (n > kScratchPixels) return REC_ENOMEM;
@@ -1081,6 +1095,7 @@ int rec_diff_forward_noalloc(const rec_diff_desc* d, const rec_diff_inputs* in, 
 int rec_diff_backward(const rec_diff_desc* d, const rec_diff_inputs* in, const float* g_u,
                       const float* g_p, const rec_diff_grads* out, void* dev_workspace,
                       size_t ws_bytes, void* stream) {
+    Range range("rec_diff_backward");
     Ctx x;
     int rc = check_call(d, in, dev_workspace, ws_bytes, x);
     if (rc != REC_OK) return rc;

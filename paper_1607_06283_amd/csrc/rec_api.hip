@@ -18,6 +18,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "kernels.h"
 #include "rec.h"
 
@@ -72,6 +74,15 @@ size_t carve(const rec_params* prm, char* base, Planes* P) {
 }
 
 bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+// A roctx range around an entry point, so that a marker trace
+// (rocprofv3 --marker-trace) shows each call beside the kernels it enqueues.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 struct Seg {
     const int64_t* t;
@@ -351,6 +362,7 @@ int rec_check_events(const int64_t* t_us, const uint16_t* x, const uint16_t* y,
 
 int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* hip_stream,
              const float* u0, rec_ctx** out) {
+    Range range("rec_init");
     if (!out) return REC_EINVAL;
     *out = nullptr;
     int rc = rec_check_params(prm);
@@ -416,6 +428,7 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
 
 int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const uint16_t* y,
                     const int8_t* polarity, int64_t n, int on_device) {
+    Range range("rec_push_events");
     if (!c || n < 0) return REC_EINVAL;
     if (n == 0) return REC_OK;
     if (!t_us || !x || !y || !polarity) return REC_EINVAL;
@@ -481,6 +494,7 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
 }
 
 int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
+    Range range("rec_solve");
     if (!c) return REC_EINVAL;
     if (iters <= 0) iters = c->prm.iters;
     const int64_t np = (int64_t)c->fr.W * c->fr.H;
@@ -626,6 +640,7 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
 }
 
 int rec_get_image(rec_ctx* c, int32_t which, void* out, int on_device) {
+    Range range("rec_get_image");
     if (!c || !out || which < REC_U || which > REC_T_LAST) return REC_EINVAL;
     const size_t np = (size_t)c->fr.W * c->fr.H;
     // a synchronising call: recorded device-pointer pushes are scattered
@@ -753,6 +768,7 @@ int rec_profile_read(rec_ctx* c, rec_profile_t* out) {
 }
 
 int rec_get_times(rec_ctx* c, int64_t* t_first, int64_t* t_ref, int32_t* started) {
+    Range range("rec_get_times");
     if (!c) return REC_EINVAL;
     int rc = flush_deferred(c);
     if (rc) return rc;
@@ -767,6 +783,7 @@ int rec_get_times(rec_ctx* c, int64_t* t_first, int64_t* t_ref, int32_t* started
 
 int rec_set_state(rec_ctx* c, const float* u, const float* p, const int64_t* t_last,
                   int64_t t_ref, int on_device) {
+    Range range("rec_set_state");
     if (!c || !u) return REC_EINVAL;
     const bool started = t_ref != INT64_MIN;
     if (started && !t_last) return REC_EINVAL;
@@ -1212,6 +1229,7 @@ size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n) {
 
 int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t ws_bytes,
                    int32_t tune_iters, rec_batch** out) {
+    Range range("rec_batch_init");
     if (!out) return REC_EINVAL;
     *out = nullptr;
     if (!ctxs || n < 1 || tune_iters < 0) return REC_EINVAL;
@@ -1352,6 +1370,7 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
 }
 
 int rec_batch_solve(rec_batch* b, int32_t iters) {
+    Range range("rec_batch_solve");
     if (!b || iters < 1) return REC_EINVAL;
     int rc;
     // pushes the first launch cannot fold are scattered first
@@ -1425,6 +1444,7 @@ int rec_batch_config(const rec_batch* b, int32_t cls, rec_batch_class* out) {
 
 int rec_batch_set_geometry(rec_batch* b, int32_t width, int32_t height, int32_t rows,
                            int32_t waves, int32_t cols, int32_t kiters) {
+    Range range("rec_batch_set_geometry");
     if (!b || !rec::batch_shape_supported(rows, waves, cols, b->storage) || kiters < 1 ||
         kiters > (cols - 1) / 2 || kiters > (rows * waves * (64 / cols) - 1) / 2)
         return REC_EINVAL;

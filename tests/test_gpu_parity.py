@@ -761,6 +761,39 @@ def test_batch_equals_individual_solves(mode, tune):
     batch.close()
 
 
+@pytest.mark.parametrize("storage", [rec.REC_STORE_F16, rec.REC_STORE_BF16])
+def test_batch_16bit_storage_equals_individual_solves(storage):
+    """16-bit storage of p and tx, ty in a batch (64- and 32-column classes):
+    the same bits as each stream solved alone with the same storage and the
+    same iterations per launch (16-bit storage rounds p at the end of every
+    launch, so unlike FP32 its bits depend on where the launches split a
+    solve, though not on the tile shape)."""
+    shapes = [(128, 128), (240, 180), (67, 45)]
+    streams = [_random_stream(W, H, 3 * 800, seed=W + 7 * H) for (W, H) in shapes]
+    recs = [rec.Reconstructor(W, H, storage=storage) for (W, H) in shapes]
+    batch = rec.Batch(recs, tune_iters=0)
+    batch.set_geometry(240, 180, 2, 8, 32, 7)
+    cfg = batch.config()
+    assert len(cfg) == 2
+    k_of = {(c["width"], c["height"]): c["kiters"] for c in cfg}
+    k_def = [c["kiters"] for c in cfg if (c["width"], c["height"]) != (240, 180)][0]
+    solo = [rec.Reconstructor(W, H, storage=storage, fuse_iters=k_of.get((W, H), k_def))
+            for (W, H) in shapes]
+    for step in range(3):
+        for (t, x, y, p), r, s in zip(streams, recs, solo):
+            sl = slice(step * 800, (step + 1) * 800)
+            ev = evgen.Events(t[sl], x[sl], y[sl], p[sl], np.zeros(800, np.uint8))
+            r.push(*device_events(ev), on_device=True)
+            s.push(*device_events(ev), on_device=True)
+        batch.solve(30)
+        for s in solo:
+            s.solve(30)
+    for r, s in zip(recs, solo):
+        assert np.array_equal(r.image(rec.REC_U), s.image(rec.REC_U))
+        assert np.array_equal(r.image(rec.REC_STATE_P), s.image(rec.REC_STATE_P))
+    batch.close()
+
+
 def test_batch_geometry_checks():
     """Geometries outside the batched launch's set, halos that leave no
     interior and sizes not in the batch are refused and change nothing."""
