@@ -73,6 +73,30 @@ struct BuildConsts {
     double ts;          // microseconds per unit of tau (0: flat manifold)
 };
 
+// Division by a launch constant d (1 <= d < 2^31) of any 0 <= n < 2^31 with
+// a multiply-high, an add and a shift (Granlund and Montgomery, "Division by
+// invariant integers using multiplication", 1994: with l = ceil(log2 d) and
+// m' = ceil(2^(32+l) / d), floor(n / d) = floor(n m' / 2^(32+l)); m' - 2^32
+// fits 32 bits and n + mulhi(n, m' - 2^32) does not overflow for n < 2^31).
+// A tile index turns into its tile row and column this way at the start of
+// every fused launch, where a general integer division would delay the
+// first loads.
+struct Divider {
+    uint32_t m;  // m' - 2^32
+    uint32_t l;
+};
+inline Divider make_divider(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;
+    const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
+    const uint64_t mp = (uint64_t)((num + d - 1) / d);
+    return Divider{(uint32_t)(mp - (1ull << 32)), l};
+}
+__device__ __forceinline__ int divide(int n, Divider dv) {
+    const uint32_t un = (uint32_t)n;
+    return (int)((un + __umulhi(un, dv.m)) >> dv.l);
+}
+
 // Device-pointer pushes not scattered yet: consumed by the first fused
 // launch of the next solve, in order, each all-or-nothing.
 constexpr int kMaxSegs = 4;
@@ -115,6 +139,7 @@ struct StreamDesc {
     int32_t mode0;   // mode of the solve's first launch
     int32_t mode1;   // mode of its second launch
     int32_t tiles_x; // tiles per row for the batch's tile geometry
+    Divider tiles_x_div;  // the same as a divider
 };
 
 // Optional timing events around a launch (recorded by the launch packet).

@@ -68,6 +68,22 @@ hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
+// Element e of a plane addressed from a base pointer with a 32-bit offset
+// (byte offset computed in 32 bits), so that the load or store takes the
+// scalar-base + 32-bit vector-offset form.  The base passes through the
+// global address space: the planes are device memory, and pointers that a
+// kernel reads from memory (the batched launch's descriptors) would
+// otherwise be accessed with flat instructions.
+using gchar = __attribute__((address_space(1))) char;
+template <class T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t e) {
+    return (const T*)((const gchar*)base + e * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T* at(T* base, uint32_t e) {
+    return (T*)((gchar*)base + e * (uint32_t)sizeof(T));
+}
+
 // Storage of the dual field p and of the time differences tx, ty.  The
 // arithmetic is FP32 in every case; 16-bit forms round on store (RNE) and
 // widen exactly on load.  tx, ty are rounded before use, so every launch
@@ -892,6 +908,22 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         }
     }
 
+    // Tile-relative 32-bit element offsets.  The tile's rows lie within RH
+    // image rows of its first row clamped into the image (yb), so an offset
+    // from the per-tile plane bases fits 32 bits for every frame size, and
+    // the loads and stores take the scalar-base + vector-offset form.  Coordinates are clamped into the image: outside the image a
+    // lane reads an edge pixel's (finite) values, which never reach a pixel
+    // inside it, because the outside pixel's coefficients are zero.
+    const int yb = min(max(ry0, 0), fr.H - 1);
+    const size_t tb0 = (size_t)yb * fr.W;
+    const uint32_t gxc = (uint32_t)min(max(gx, 0), fr.W - 1);
+    auto eoff = [&](int r) -> uint32_t {  // (row offset < RH, W < 2^16: 24-bit product)
+        const int gyc = min(max(gy0 + r, 0), fr.H - 1);
+        return __umul24((uint32_t)(gyc - yb), (uint32_t)fr.W) + gxc;
+    };
+    const typename S::T* __restrict__ txb = txs + tb0;
+    const typename S::T* __restrict__ tyb = tys + tb0;
+
     float u[R], p1[R], p2[R], p3[R], txr[R], tyr[R];
     CoefT c[R];
 #pragma unroll
@@ -899,7 +931,16 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         const int gy = gy0 + r;
         const bool in = col_in && gy >= 0 && gy < fr.H;
         float uu = 1.0f, a = 0.0f, b = 0.0f, d = 0.0f, f = 1.0f, tx = 0.0f, ty = 0.0f;
-        if (in) {
+        if constexpr (!build) {
+            const uint32_t e = eoff(r);
+            uu = *at(uin + tb0, e);
+            a = S::ld(at(pin + tb0, e), 0);
+            b = S::ld(at(pin + np + tb0, e), 0);
+            d = S::ld(at(pin + 2 * np + tb0, e), 0);
+            f = *at(P.f + tb0, e);
+            tx = S::ld(at(txb, e), 0);
+            ty = S::ld(at(tyb, e), 0);
+        } else if (in) {
             const size_t k = (size_t)gy * fr.W + gx;
             if constexpr (kEarly) {
                 uu = eu[r];
@@ -956,10 +997,6 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
                     }
                     if (events) P.t_last[k] = tl;
                 }
-            } else {
-                f = P.f[k];
-                tx = S::ld(txs, k);
-                ty = S::ld(tys, k);
             }
         }
         // pixels outside the image get all-zero coefficients, so their q is 0
@@ -978,6 +1015,13 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
 #pragma unroll
         for (int r = 0; r < R; ++r) to_frame(make_basis(txr[r], tyr[r]), p1[r], p2[r], p3[r]);
     }
+
+    // The output planes' bases are read before the loop and held in scalar
+    // registers (read after it, their loads would sit on the launch's
+    // critical path before the stores).
+    float* __restrict__ uout = P.u[cur ^ 1];
+    typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];
+    asm volatile("" : "+s"(uout), "+s"(pout));
 
     // Rows that cross lane rows go through LDS.  xq[v + 1] holds lane row
     // v's last q_y row and xu[v] its first extrapolated row; xq[0] and
@@ -1026,19 +1070,26 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     }
     for (; it < K; ++it) step(it + 1, u, u);
 
-    float* __restrict__ uout = P.u[cur ^ 1];
-    typename S::T* __restrict__ pout = (typename S::T*)P.p[cur ^ 1];
+    // The offsets are formed again after the loop (a few instructions per
+    // row) instead of being held in registers through it; a stored pixel
+    // lies inside the image, so its offset needs no clamping.
+    int gy0e = gy0, gxe = gx;
+    asm volatile("" : "+v"(gy0e), "+v"(gxe));
+    auto eoff2 = [&](int r) -> uint32_t {
+        const int gyc = min(max(gy0e + r, 0), fr.H - 1);
+        return __umul24((uint32_t)(gyc - yb), (uint32_t)fr.W) +
+               (uint32_t)min(max(gxe, 0), fr.W - 1);
+    };
+    auto eoff_in = [&](int r) -> uint32_t {
+        return __umul24((uint32_t)(gy0e + r - yb), (uint32_t)fr.W) + (uint32_t)gxe;
+    };
     if (mode & kRotOut) {
         // tx, ty as stored (this launch wrote them if it built them)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int gy = gy0 + r;
-            txr[r] = tyr[r] = 0.0f;
-            if (col_in && gy >= 0 && gy < fr.H) {
-                const size_t k = (size_t)gy * fr.W + gx;
-                txr[r] = S::ld(txs, k);
-                tyr[r] = S::ld(tys, k);
-            }
+            const uint32_t e = eoff2(r);
+            txr[r] = S::ld(at(txb, e), 0);
+            tyr[r] = S::ld(at(tyb, e), 0);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) from_frame(make_basis(txr[r], tyr[r]), p1[r], p2[r], p3[r]);
@@ -1048,14 +1099,14 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         const int row = v * R + r;
         const int gy = gy0 + r;
         if (col_out && row >= KG && row < RH - KG && gy >= 0 && gy < fr.H) {
-            const size_t k = (size_t)gy * fr.W + gx;
-            uout[k] = u[r];
-            S::st(pout, k, p1[r]);
-            S::st(pout, np + k, p2[r]);
-            S::st(pout, 2 * np + k, p3[r]);
+            const uint32_t e = eoff_in(r);
+            *at(uout + tb0, e) = u[r];
+            S::st(at(pout + tb0, e), 0, p1[r]);
+            S::st(at(pout + np + tb0, e), 0, p2[r]);
+            S::st(at(pout + 2 * np + tb0, e), 0, p3[r]);
             if (mode & kZero) {
-                P.npos[k] = 0;
-                P.nneg[k] = 0;
+                *at(P.npos + tb0, e) = 0;
+                *at(P.nneg + tb0, e) = 0;
             }
         }
     }
@@ -1064,10 +1115,11 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
 template <int R, int NW, int CW, class S, bool B>
 __global__ __launch_bounds__(64 * NW) void k_pd_fused(Planes P, Frame fr, IterConsts kc,
                                                       BuildConsts bc, EventSegs segs, int cur,
-                                                      int K, int mode, int tiles_x, int ntiles) {
+                                                      int K, int mode, int tiles_x,
+                                                      Divider tiles_x_div, int ntiles) {
     extern __shared__ unsigned char dyn_lds[];
     const int tile = xcd_tile(blockIdx.x, ntiles);
-    const int tyi = tile / tiles_x, txi = tile - tyi * tiles_x;
+    const int tyi = divide(tile, tiles_x_div), txi = tile - tyi * tiles_x;
     pd_tile<R, NW, CW, S, B>(P, fr, kc, bc, segs, cur, K, K, mode, txi, tyi, tile == 0, dyn_lds);
 }
 
@@ -1084,7 +1136,7 @@ __global__ __launch_bounds__(64 * NW) void k_pd_fused_batch(const StreamDesc* __
     extern __shared__ unsigned char dyn_lds[];
     const int2 w = work[xcd_tile(blockIdx.x, nwork)];
     const StreamDesc& d = descs[w.x];
-    const int tyi = w.y / d.tiles_x, txi = w.y - tyi * d.tiles_x;
+    const int tyi = divide(w.y, d.tiles_x_div), txi = w.y - tyi * d.tiles_x;
     const int mode = (launch == 0 ? d.mode0 : (launch == 1 ? d.mode1 : 0)) | (last ? kRotOut : 0);
     pd_tile<R, NW, CW, S, B>(d.P, d.fr, d.kc, d.bc, d.segs, d.cur ^ (launch & 1), K, KG, mode,
                              txi, tyi, w.y == 0, dyn_lds);
@@ -1230,11 +1282,12 @@ hipError_t fused_launch(const Planes& P, Frame fr, IterConsts kc, BuildConsts bc
     const int tiles_y = (fr.H + OH - 1) / OH;
     const int ntiles = tiles_x * tiles_y;
     const size_t lds = fused_lds_bytes(R, NW, CW, mode);
+    const Divider txd = make_divider((uint32_t)tiles_x);
     if (mode & kBuild)
         return launch(k_pd_fused<R, NW, CW, S, true>, dim3(ntiles), dim3(64 * NW), lds, s,
-                      ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
+                      ev.start, ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, txd, ntiles);
     return launch(k_pd_fused<R, NW, CW, S, false>, dim3(ntiles), dim3(64 * NW), lds, s, ev.start,
-                  ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, ntiles);
+                  ev.stop, P, fr, kc, bc, segs, cur, K, mode, tiles_x, txd, ntiles);
 }
 
 template <int R, int NW, int CW, class S>

@@ -1075,6 +1075,7 @@ void fill_desc(rec_batch* b, rec::StreamDesc* d, unsigned* fold) {
             e.cur = c->cur;
             const int ow = cl.shape.cols - 2 * cl.shape.k;
             e.tiles_x = (c->fr.W + ow - 1) / ow;
+            e.tiles_x_div = rec::make_divider((uint32_t)e.tiles_x);
             const bool f = !c->deferred.empty();
             if (f) {
                 for (size_t q = 0; q < c->deferred.size(); ++q) {
