@@ -415,13 +415,17 @@ __device__ void bin_clear(int RH, int CW, unsigned char* lds, TileBins& tb) {
     __syncthreads();
 }
 
+// Bins one event (its fields already loaded).
+__device__ __forceinline__ void bin_event(int64_t t, int x, int y, int8_t pol, int RH, int CW,
+                                          int rx0, int ry0, TileBins& tb) {
+    const int lc = x - rx0, lr = y - ry0;
+    if (lc < 0 || lc > CW || lr < 0 || lr > RH) return;
+    atomicMax(&tb.tmax[lr * (CW + 1) + lc], (long long)t);
+    if (lc < CW && lr < RH) atomicAdd(pol > 0 ? &tb.pos[lr * CW + lc] : &tb.neg[lr * CW + lc], 1);
+}
 __device__ __forceinline__ void bin_one(const EventSegs& segs, int s, int64_t i, int RH, int CW,
                                         int rx0, int ry0, TileBins& tb) {
-    const int lc = (int)segs.x[s][i] - rx0, lr = (int)segs.y[s][i] - ry0;
-    if (lc < 0 || lc > CW || lr < 0 || lr > RH) return;
-    atomicMax(&tb.tmax[lr * (CW + 1) + lc], (long long)segs.t[s][i]);
-    if (lc < CW && lr < RH)
-        atomicAdd(segs.p[s][i] > 0 ? &tb.pos[lr * CW + lc] : &tb.neg[lr * CW + lc], 1);
+    bin_event(segs.t[s][i], segs.x[s][i], segs.y[s][i], segs.p[s][i], RH, CW, rx0, ry0, tb);
 }
 
 __device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int RH, int CW,
@@ -451,14 +455,23 @@ __device__ void bin_scan(const Planes& P, Frame fr, const EventSegs& segs, int R
     }
     // per-event checks (each push's first event is checked against the
     // running reference time in sequence below), binning as we go
+    // (all fields of an event, and the previous timestamp, are loaded before
+    // any check, so that their loads are in flight together instead of
+    // waiting on each other through the checks' branches)
     for (int s = 0; s < segs.count; ++s) {
         const int64_t* t = segs.t[s];
+        const uint16_t* xs = segs.x[s];
+        const uint16_t* ys = segs.y[s];
+        const int8_t* ps = segs.p[s];
         for (int64_t i = tid; i < segs.n[s]; i += nt) {
-            const int64_t prev = i ? t[i - 1] : INT64_MIN;
-            if (event_error(t[i], prev, segs.x[s][i], segs.y[s][i], segs.p[s][i], fr.W, fr.H))
+            int64_t ti = t[i], tp = t[i > 0 ? i - 1 : 0];
+            int xi = xs[i], yi = ys[i], pi = ps[i];
+            asm volatile("" : "+v"(ti), "+v"(tp), "+v"(xi), "+v"(yi), "+v"(pi));
+            const int64_t prev = i > 0 ? tp : INT64_MIN;
+            if (event_error(ti, prev, (uint16_t)xi, (uint16_t)yi, (int8_t)pi, fr.W, fr.H))
                 atomicMin(&ss.seg_bad[s], (unsigned long long)i);
             else
-                bin_one(segs, s, i, RH, CW, rx0, ry0, tb);
+                bin_event(ti, xi, yi, (int8_t)pi, RH, CW, rx0, ry0, tb);
         }
     }
     __syncthreads();
