@@ -71,7 +71,14 @@ struct IterConsts {
 struct BuildConsts {
     double dpos, dneg;  // contrast thresholds Delta+, Delta-
     double ts;          // microseconds per unit of tau (0: flat manifold)
+    double its;         // 1 / ts rounded to nearest, or 0 where a division is used instead
 };
+// Build constants of a stream; its is set for 2^-100 <= ts <= 2^100, where
+// x / ts for any |x| < 2^63 stays clear of overflow and underflow.
+inline BuildConsts make_build_consts(double dpos, double dneg, double ts) {
+    const bool ok = ts >= 0x1p-100 && ts <= 0x1p100;
+    return BuildConsts{dpos, dneg, ts, ok ? 1.0 / ts : 0.0};
+}
 
 // Division by a launch constant d (1 <= d < 2^31) of any 0 <= n < 2^31 with
 // a multiply-high, an add and a shift (Granlund and Montgomery, "Division by

@@ -247,6 +247,19 @@ __global__ void k_push_finalize(Planes P, Frame fr, const int64_t* t, const uint
 // tau(x+1) - tau(x) = (t_last(x) - t_last(x+1)) / T_s from the exact int64
 // difference, divided in FP64 and rounded once; 0 on the last column / row
 // and everywhere when T_s = 0 (flat manifold).
+// x / ts in FP64, rounded to nearest.  With its = RN(1 / ts), q = RN(x its)
+// is within an ulp of the quotient, the remainder x - q ts is exact in one
+// fused multiply-add, and RN(q + r its) is the correctly rounded quotient
+// (Markstein, "Computation of elementary functions on the IBM RISC
+// System/6000 processor", 1990), so this equals the IEEE division, at three
+// FP64 operations instead of the division's sequence.
+__device__ __forceinline__ double div_ts(double x, const BuildConsts& b) {
+    if (b.its == 0.0) return x / b.ts;
+    const double q = x * b.its;
+    const double r = __builtin_fma(-q, b.ts, x);
+    return __builtin_fma(r, b.its, q);
+}
+
 __device__ __forceinline__ void time_diffs(int64_t tl, int64_t tr, int64_t td, bool has_r,
                                            bool has_d, int64_t t0, const BuildConsts& b,
                                            float& dx, float& dy) {
@@ -254,8 +267,8 @@ __device__ __forceinline__ void time_diffs(int64_t tl, int64_t tr, int64_t td, b
     dy = 0.0f;
     if (b.ts > 0.0) {
         const int64_t l = resolved_last(tl, t0);
-        if (has_r) dx = (float)((double)(l - resolved_last(tr, t0)) / b.ts);
-        if (has_d) dy = (float)((double)(l - resolved_last(td, t0)) / b.ts);
+        if (has_r) dx = (float)div_ts((double)(l - resolved_last(tr, t0)), b);
+        if (has_d) dy = (float)div_ts((double)(l - resolved_last(td, t0)), b);
     }
 }
 
@@ -993,7 +1006,9 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
                     tr = max(tr, (int64_t)tb.tmax[lr * (CW + 1) + col + 1]);
                     td = max(td, (int64_t)tb.tmax[(lr + 1) * (CW + 1) + col]);
                 }
-                f = data_image(uu, npos, nneg, bc.dpos, bc.dneg);
+                // (without events the factor is exp(0) = 1: f = u_prev exactly,
+                // and a row of lanes without events skips the FP64 exp)
+                f = (npos | nneg) != 0 ? data_image(uu, npos, nneg, bc.dpos, bc.dneg) : uu;
                 if (mode & kTimeMem) {
                     tx = S::ld(txs, k);
                     ty = S::ld(tys, k);

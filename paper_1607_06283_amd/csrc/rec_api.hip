@@ -498,7 +498,8 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
     if (!c) return REC_EINVAL;
     if (iters <= 0) iters = c->prm.iters;
     const int64_t np = (int64_t)c->fr.W * c->fr.H;
-    const rec::BuildConsts bc{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
+    const rec::BuildConsts bc =
+        rec::make_build_consts(c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us);
     const bool fused = c->prm.fuse_iters != 0 && iters > 0;
     const bool denoise = c->prm.tvl1_iters > 0 && c->prm.time_unit_us > 0.0;
     int rc;
@@ -1071,7 +1072,7 @@ void fill_desc(rec_batch* b, rec::StreamDesc* d, unsigned* fold) {
             e.P = c->P;
             e.fr = c->fr;
             e.kc = c->kc;
-            e.bc = rec::BuildConsts{c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us};
+            e.bc = rec::make_build_consts(c->prm.delta_pos, c->prm.delta_neg, c->prm.time_unit_us);
             e.cur = c->cur;
             const int ow = cl.shape.cols - 2 * cl.shape.k;
             e.tiles_x = (c->fr.W + ow - 1) / ow;
