@@ -429,9 +429,15 @@ struct Trail {
 };
 
 // Where a tile sits; interior(): the pixel is written by this tile.
+// Planes are addressed from per-tile bases with 32-bit offsets: the tile's
+// rows lie within RH image rows of its first row clamped into the image
+// (yb), so an offset from plane + tb (image planes) or plane + tbf + c np
+// (component c of a field) fits 32 bits for every size.
 struct TilePos {
-    int lane, wave, gx, gy0, b;
+    int lane, wave, gx, gy0, b, yb;
     size_t img, fld;  // offsets of image b in an image plane / a 3-plane field
+    size_t tb, tbf;   // the tile's bases: img + yb W, fld + yb W
+    uint32_t gxc;     // gx clamped into the image
     bool col_in, col_out;
 };
 
@@ -450,9 +456,22 @@ __device__ __forceinline__ TilePos tile_pos(const Dims& d, const TileGrid& g) {
     t.gy0 = tyi * OH - g.kg + t.wave * R;
     t.img = (size_t)t.b * d.np;
     t.fld = 3 * t.img;
+    t.yb = min(max(tyi * OH - g.kg, 0), d.H - 1);
+    t.tb = t.img + (size_t)t.yb * d.W;
+    t.tbf = t.fld + (size_t)t.yb * d.W;
+    t.gxc = (uint32_t)min(max(t.gx, 0), d.W - 1);
     t.col_in = t.gx >= 0 && t.gx < d.W;
     t.col_out = t.col_in && t.lane >= g.kg && t.lane < 64 - g.kg;
     return t;
+}
+
+// Offset of row r of the lane from the tile's bases, the coordinates
+// clamped into the image: outside the image a lane reads an edge pixel's
+// (finite) values, which reach no pixel inside, because the coefficients of
+// a pixel outside the image are zero.
+__device__ __forceinline__ uint32_t eoff(const Dims& d, const TilePos& t, int r) {
+    const int gyc = min(max(t.gy0 + r, 0), d.H - 1);
+    return __umul24((uint32_t)(gyc - t.yb), (uint32_t)d.W) + t.gxc;
 }
 
 template <int R, int NW>
@@ -471,16 +490,16 @@ __device__ __forceinline__ void store_state(const Dims& d, const TileGrid& g, co
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!interior<R, NW>(d, g, t, r)) continue;
-        const size_t k = (size_t)(t.gy0 + r) * d.W + t.gx;
-        U[t.img + k] = u[r];
-        P[t.fld + k] = p1[r];
-        P[t.fld + d.np + k] = p2[r];
-        P[t.fld + 2 * d.np + k] = p3[r];
+        const uint32_t e = __umul24((uint32_t)(t.gy0 + r - t.yb), (uint32_t)d.W) + (uint32_t)t.gx;
+        *at(U + t.tb, e) = u[r];
+        *at(P + t.tbf, e) = p1[r];
+        *at(P + t.tbf + d.np, e) = p2[r];
+        *at(P + t.tbf + 2 * d.np, e) = p3[r];
     }
 }
 
 // Metric constants of a tile's rows (pixels outside the image: zero
-// coefficients, f = 1, as in the forward solve's tiles).
+// coefficients, as in the forward solve's tiles).
 template <int R>
 __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, const float* f,
                                            const float* tx, const float* ty, const float* w,
@@ -489,16 +508,12 @@ __device__ __forceinline__ void tile_coefs(const Dims& d, const TilePos& t, cons
     for (int r = 0; r < R; ++r) {
         const int gy = t.gy0 + r;
         const bool in = t.col_in && gy >= 0 && gy < d.H;
-        float ff = 1.0f, x = 0.0f, y = 0.0f, tlw = tl;
-        if (in) {
-            const size_t k = t.img + (size_t)gy * d.W + t.gx;
-            ff = f[k];
-            x = tx[k];
-            y = ty[k];
-            if (w) tlw = tl * w[k];
-        }
+        const uint32_t e = eoff(d, t, r);
+        const float ff = *at(f + t.tb, e);
+        const float tlw = w ? tl * *at(w + t.tb, e) : tl;
         fr[r] = ff;
-        c[r] = coef(x, y, ff, tlw, sigma, in && t.gx < d.W - 1, in && gy < d.H - 1);
+        c[r] = coef(*at(tx + t.tb, e), *at(ty + t.tb, e), ff, tlw, sigma,
+                    in && t.gx < d.W - 1, in && gy < d.H - 1);
     }
 }
 
@@ -520,16 +535,11 @@ __global__ __launch_bounds__(64 * NW) void k_dfwd_fused(Dims d, TileGrid g, Stat
                  fr);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int gy = t.gy0 + r;
-        u[r] = 1.0f;
-        p1[r] = p2[r] = p3[r] = 0.0f;
-        if (t.col_in && gy >= 0 && gy < d.H) {
-            const size_t k = (size_t)gy * d.W + t.gx;
-            u[r] = in.u[t.img + k];
-            p1[r] = in.p[t.fld + k];
-            p2[r] = in.p[t.fld + d.np + k];
-            p3[r] = in.p[t.fld + 2 * d.np + k];
-        }
+        const uint32_t e = eoff(d, t, r);
+        u[r] = *at(in.u + t.tb, e);
+        p1[r] = *at(in.p + t.tbf, e);
+        p2[r] = *at(in.p + t.tbf + d.np, e);
+        p3[r] = *at(in.p + t.tbf + 2 * d.np, e);
     }
     __shared__ float xq[NW + 1][64];
     __shared__ float xu[NW + 1][64];
@@ -581,49 +591,50 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
     tile_coefs<R>(d, t, f, tx, ty, w, (float)(st.tau_d * theta[0]), st.sigma, c,
                  fr);
     float u1[R], Q1[R], Q2[R], Q3[R], UB[R], UH[R], GB[R], GF[R];
-    bool inside[R];
-    size_t kk[R];
+    uint32_t ee[R];  // offsets of the lane's rows from the tile's bases (clamped)
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = t.gy0 + r;
-        inside[r] = t.col_in && gy >= 0 && gy < d.H;
-        kk[r] = inside[r] ? (size_t)gy * d.W + t.gx : 0;
-        const size_t k = kk[r];
-        u1[r] = inside[r] ? S.u[K][t.img + k] : 1.0f;
+        const bool inside = t.col_in && gy >= 0 && gy < d.H;
+        const uint32_t e = ee[r] = eoff(d, t, r);
+        u1[r] = *at(S.u[K] + t.tb, e);
         Q1[r] = Q2[r] = Q3[r] = UB[r] = UH[r] = 0.0f;
-        if (inside[r]) {
-            if (first) {
+        if (first) {
+            // the adjoints of the last state: zero outside the image
+            if (inside) {
                 if (g_p) {
-                    Q1[r] = g_p[t.fld + k];
-                    Q2[r] = g_p[t.fld + d.np + k];
-                    Q3[r] = g_p[t.fld + 2 * d.np + k];
+                    Q1[r] = *at(g_p + t.tbf, e);
+                    Q2[r] = *at(g_p + t.tbf + d.np, e);
+                    Q3[r] = *at(g_p + t.tbf + 2 * d.np, e);
                     if (st.rot)
-                        to_frame(make_basis(tx[t.img + k], ty[t.img + k]), Q1[r], Q2[r], Q3[r]);
+                        to_frame(make_basis(*at(tx + t.tb, e), *at(ty + t.tb, e)), Q1[r], Q2[r],
+                                 Q3[r]);
                 }
-                if (g_u) UH[r] = g_u[t.img + k];
-            } else {
-                Q1[r] = ain.q[t.fld + k];
-                Q2[r] = ain.q[t.fld + d.np + k];
-                Q3[r] = ain.q[t.fld + 2 * d.np + k];
-                UB[r] = ain.ub[t.img + k];
-                UH[r] = ain.uh[t.img + k];
+                if (g_u) UH[r] = *at(g_u + t.tb, e);
             }
+        } else {
+            Q1[r] = *at(ain.q + t.tbf, e);
+            Q2[r] = *at(ain.q + t.tbf + d.np, e);
+            Q3[r] = *at(ain.q + t.tbf + 2 * d.np, e);
+            UB[r] = *at(ain.ub + t.tb, e);
+            UH[r] = *at(ain.uh + t.tb, e);
         }
         const bool own = interior<R, NW>(d, g, t, r);
-        GB[r] = own ? gbeta[t.img + k] : 0.0f;
-        GF[r] = own ? gf[t.img + k] : 0.0f;
+        GB[r] = own ? *at(gbeta + t.tb, e) : 0.0f;
+        GF[r] = own ? *at(gf + t.tb, e) : 0.0f;
     }
     __shared__ float xa[NW][64], xb[NW][64], xc[NW][64], xd[NW][64];
     // the state of the next step is loaded one step ahead
     float nu[R], na[R], nb[R], nc[R];
     auto load_state = [&](int j) {
+        const float* su = S.u[j] + t.tb;
+        const float* sp = S.p[j] + t.tbf;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const size_t k = kk[r];
-            nu[r] = inside[r] ? S.u[j][t.img + k] : 1.0f;
-            na[r] = inside[r] ? S.p[j][t.fld + k] : 0.0f;
-            nb[r] = inside[r] ? S.p[j][t.fld + d.np + k] : 0.0f;
-            nc[r] = inside[r] ? S.p[j][t.fld + 2 * d.np + k] : 0.0f;
+            nu[r] = *at(su, ee[r]);
+            na[r] = *at(sp, ee[r]);
+            nb[r] = *at(sp + d.np, ee[r]);
+            nc[r] = *at(sp + 2 * d.np, ee[r]);
         }
     };
     load_state(K - 1);
@@ -723,14 +734,14 @@ __global__ __launch_bounds__(64 * NW) void k_adj_fused(
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         if (!interior<R, NW>(d, g, t, r)) continue;
-        const size_t k = kk[r];
-        aout.q[t.fld + k] = Q1[r];
-        aout.q[t.fld + d.np + k] = Q2[r];
-        aout.q[t.fld + 2 * d.np + k] = Q3[r];
-        aout.ub[t.img + k] = UB[r];
-        aout.uh[t.img + k] = UH[r];
-        gbeta[t.img + k] = GB[r];
-        gf[t.img + k] = GF[r];
+        const uint32_t e = ee[r];  // (an interior pixel's offset needs no clamping)
+        *at(aout.q + t.tbf, e) = Q1[r];
+        *at(aout.q + t.tbf + d.np, e) = Q2[r];
+        *at(aout.q + t.tbf + 2 * d.np, e) = Q3[r];
+        *at(aout.ub + t.tb, e) = UB[r];
+        *at(aout.uh + t.tb, e) = UH[r];
+        *at(gbeta + t.tb, e) = GB[r];
+        *at(gf + t.tb, e) = GF[r];
     }
 }
 

@@ -68,22 +68,6 @@ hipError_t launch(Kern kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s,
 
 inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
-// Element e of a plane addressed from a base pointer with a 32-bit offset
-// (byte offset computed in 32 bits), so that the load or store takes the
-// scalar-base + 32-bit vector-offset form.  The base passes through the
-// global address space: the planes are device memory, and pointers that a
-// kernel reads from memory (the batched launch's descriptors) would
-// otherwise be accessed with flat instructions.
-using gchar = __attribute__((address_space(1))) char;
-template <class T>
-__device__ __forceinline__ const T* at(const T* base, uint32_t e) {
-    return (const T*)((const gchar*)base + e * (uint32_t)sizeof(T));
-}
-template <class T>
-__device__ __forceinline__ T* at(T* base, uint32_t e) {
-    return (T*)((gchar*)base + e * (uint32_t)sizeof(T));
-}
-
 // Storage of the dual field p and of the time differences tx, ty.  The
 // arithmetic is FP32 in every case; 16-bit forms round on store (RNE) and
 // widen exactly on load.  tx, ty are rounded before use, so every launch

@@ -1,5 +1,6 @@
 // Register-tile building blocks shared by the fused loops: the forward
-// primal-dual iteration of a tile and the lane / XCD helpers.
+// primal-dual iteration of a tile, and the plane-addressing, lane and XCD
+// helpers.
 //
 // Tile layout: a workgroup's lanes form NV rows of CW lanes ("lane rows";
 // CW = 64: one per wavefront, CW = 32: two per wavefront) and cover CW
@@ -15,6 +16,22 @@
 #include "pd_math.h"
 
 namespace rec {
+
+// Element e of a plane addressed from a base pointer with a 32-bit offset
+// (byte offset computed in 32 bits), so that the load or store takes the
+// scalar-base + 32-bit vector-offset form.  The base passes through the
+// global address space: the planes are device memory, and pointers that a
+// kernel reads from memory (the batched launch's descriptors) would
+// otherwise be accessed with flat instructions.
+using gchar = __attribute__((address_space(1))) char;
+template <class T>
+__device__ __forceinline__ const T* at(const T* base, uint32_t e) {
+    return (const T*)((const gchar*)base + e * (uint32_t)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ T* at(T* base, uint32_t e) {
+    return (T*)((gchar*)base + e * (uint32_t)sizeof(T));
+}
 
 // blockIdx -> tile such that each of the 8 XCDs (which receive blocks
 // round-robin) works on one contiguous run of tiles, so halo rows shared by
