@@ -99,9 +99,10 @@ inline Divider make_divider(uint32_t d) {
     const uint64_t mp = (uint64_t)((num + d - 1) / d);
     return Divider{(uint32_t)(mp - (1ull << 32)), l};
 }
-__device__ __forceinline__ int divide(int n, Divider dv) {
+__host__ __device__ __forceinline__ int divide(int n, Divider dv) {
     const uint32_t un = (uint32_t)n;
-    return (int)((un + __umulhi(un, dv.m)) >> dv.l);
+    const uint32_t hi = (uint32_t)(((uint64_t)un * dv.m) >> 32);  // mulhi
+    return (int)((un + hi) >> dv.l);
 }
 
 // Device-pointer pushes not scattered yet: consumed by the first fused
