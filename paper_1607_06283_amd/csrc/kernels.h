@@ -80,6 +80,19 @@ inline BuildConsts make_build_consts(double dpos, double dneg, double ts) {
     return BuildConsts{dpos, dneg, ts, ok ? 1.0 / ts : 0.0};
 }
 
+// x / ts in FP64, rounded to nearest.  With its = RN(1 / ts), q = RN(x its)
+// is within an ulp of the quotient, the remainder x - q ts is exact in one
+// fused multiply-add, and RN(q + r its) is the correctly rounded quotient
+// (Markstein, "Computation of elementary functions on the IBM RISC
+// System/6000 processor", 1990), so this equals the IEEE division, at three
+// FP64 operations instead of the division's sequence.
+__host__ __device__ __forceinline__ double div_ts(double x, const BuildConsts& b) {
+    if (b.its == 0.0) return x / b.ts;
+    const double q = x * b.its;
+    const double r = __builtin_fma(-q, b.ts, x);
+    return __builtin_fma(r, b.its, q);
+}
+
 // Division by a launch constant d (1 <= d < 2^31) of any 0 <= n < 2^31 with
 // a multiply-high, an add and a shift (Granlund and Montgomery, "Division by
 // invariant integers using multiplication", 1994: with l = ceil(log2 d) and

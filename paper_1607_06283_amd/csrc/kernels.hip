@@ -231,19 +231,6 @@ __global__ void k_push_finalize(Planes P, Frame fr, const int64_t* t, const uint
 // tau(x+1) - tau(x) = (t_last(x) - t_last(x+1)) / T_s from the exact int64
 // difference, divided in FP64 and rounded once; 0 on the last column / row
 // and everywhere when T_s = 0 (flat manifold).
-// x / ts in FP64, rounded to nearest.  With its = RN(1 / ts), q = RN(x its)
-// is within an ulp of the quotient, the remainder x - q ts is exact in one
-// fused multiply-add, and RN(q + r its) is the correctly rounded quotient
-// (Markstein, "Computation of elementary functions on the IBM RISC
-// System/6000 processor", 1990), so this equals the IEEE division, at three
-// FP64 operations instead of the division's sequence.
-__device__ __forceinline__ double div_ts(double x, const BuildConsts& b) {
-    if (b.its == 0.0) return x / b.ts;
-    const double q = x * b.its;
-    const double r = __builtin_fma(-q, b.ts, x);
-    return __builtin_fma(r, b.its, q);
-}
-
 __device__ __forceinline__ void time_diffs(int64_t tl, int64_t tr, int64_t td, bool has_r,
                                            bool has_d, int64_t t0, const BuildConsts& b,
                                            float& dx, float& dy) {
