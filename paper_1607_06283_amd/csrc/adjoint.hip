@@ -51,6 +51,7 @@
 
 #include <rocprofiler-sdk-roctx/roctx.h>
 
+#include "kernels.h"
 #include "pd_math.h"
 #include "rec.h"
 #include "tile.h"
@@ -418,6 +419,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_reduce(const double* __restric
 struct TileGrid {
     int tiles_x, per_image, total;
     int kg;  // halo = iterations (or reverse steps) of the launch
+    Divider tiles_x_div, per_image_div;  // the same as dividers
 };
 
 // Intermediate states recorded by a forward launch: the state after
@@ -448,9 +450,9 @@ __device__ __forceinline__ TilePos tile_pos(const Dims& d, const TileGrid& g) {
     t.lane = threadIdx.x & 63;
     t.wave = threadIdx.x >> 6;
     const int tile = xcd_tile(blockIdx.x, g.total);
-    t.b = tile / g.per_image;
+    t.b = divide(tile, g.per_image_div);
     const int tt = tile - t.b * g.per_image;
-    const int tyi = tt / g.tiles_x, txi = tt - tyi * g.tiles_x;
+    const int tyi = divide(tt, g.tiles_x_div), txi = tt - tyi * g.tiles_x;
     const int OW = 64 - 2 * g.kg, OH = RH - 2 * g.kg;
     t.gx = txi * OW - g.kg + t.lane;
     t.gy0 = tyi * OH - g.kg + t.wave * R;
@@ -875,6 +877,8 @@ TileGrid tile_grid(const Ctx& x, int rh, int kg) {
     g.per_image = g.tiles_x * ty;
     g.total = g.per_image * x.d->batch;
     g.kg = kg;
+    g.tiles_x_div = make_divider((uint32_t)g.tiles_x);
+    g.per_image_div = make_divider((uint32_t)g.per_image);
     return g;
 }
 
