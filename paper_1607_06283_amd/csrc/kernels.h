@@ -106,6 +106,7 @@ struct Divider {
     uint32_t l;
 };
 inline Divider make_divider(uint32_t d) {
+    if (d <= 1) return Divider{0, 0};  // n / 1 (0 is no divisor: it maps to 1)
     uint32_t l = 0;
     while (l < 32 && (1ull << l) < d) ++l;
     const unsigned __int128 num = (unsigned __int128)1 << (32 + l);
