@@ -380,14 +380,28 @@ def cpu_baseline(ev, budget_s=8.0, W=W_, H=H_, batch=EVENTS_PER_BATCH, iters=ITE
                               "sample": f"first {n1} blocks in {el1:.1f} s"}}
 
 
-def oracle_c1_and_c5():
+def oracle_c1_c3_c5():
     """The oracle (all host cores) on the 128x128 workload in full (20 blocks
-    of 500 events, 50 iterations) and on the forward of the differentiation
-    workload (16 x 346x260, 100 iterations from u0 = exp(L_gt(t0)))."""
+    of 500 events, 50 iterations), on the first 10 blocks of the 1280x720
+    workload (20000 events, 100 iterations each) and on the forward of the
+    differentiation workload (16 x 346x260, 100 iterations from
+    u0 = exp(L_gt(t0)))."""
     import evgen
     import oracle
 
     out = {}
+    s, _, _, _ = evgen.hd720(seed=3, duration_us=11000)
+    o = oracle.Oracle(oracle.Params(1280, 720), threads=True)
+    blks = evgen.batches(s.events, 20000)[:10]
+    t0 = time.perf_counter()
+    for b in blks:
+        o.push_events(b)
+        o.solve(100)
+    el = time.perf_counter() - t0
+    o.close()
+    out["hd720_first10"] = {"s": round(el, 3), "blocks": len(blks),
+                            "PD iter*Mpix/s": round(len(blks) * 100 * 1280 * 720 / el / 1e6, 2),
+                            "events_per_s": round(len(blks) * 20000 / el, 1)}
     s, bs, nb, iters = evgen.dvs128(seed=1, n_batches=20)
     o = oracle.Oracle(oracle.Params(128, 128), threads=True)
     t0 = time.perf_counter()
@@ -712,7 +726,7 @@ def main():
         log("bench: oracle baseline (all host cores, then one thread)")
         out["cpu_baseline"] = cpu_baseline(ev, W=W, H=H, batch=B, iters=IT)
         if args.workload == "davis240" and not args.no_extras:
-            out["cpu_baseline"].update(oracle_c1_and_c5())
+            out["cpu_baseline"].update(oracle_c1_c3_c5())
     print(json.dumps(out), flush=True)
 
 
