@@ -864,6 +864,32 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     // between clearing the bins and scanning the events, so that their
     // latency overlaps the event loads (with more rows the registers they
     // hold would cost occupancy).
+    // Tile-relative 32-bit element offsets.  The tile's rows lie within RH
+    // image rows of its first row clamped into the image (yb), so an offset
+    // from the per-tile plane bases fits 32 bits for every frame size, and
+    // the loads and stores take the scalar-base + vector-offset form.
+    // Coordinates are clamped into the image: outside the image a lane reads
+    // an edge pixel's (finite) values, which never reach a pixel inside it,
+    // because the outside pixel's coefficients are zero.
+    const int yb = min(max(ry0, 0), fr.H - 1);
+    const size_t tb0 = (size_t)yb * fr.W;
+    const uint32_t gxc = (uint32_t)min(max(gx, 0), fr.W - 1);
+    auto eoff = [&](int r) -> uint32_t {  // (row offset < RH, W < 2^16: 24-bit product)
+        const int gyc = min(max(gy0 + r, 0), fr.H - 1);
+        return __umul24((uint32_t)(gyc - yb), (uint32_t)fr.W) + gxc;
+    };
+    const typename S::T* __restrict__ txb = txs + tb0;
+    const typename S::T* __restrict__ tyb = tys + tb0;
+    // The building launch also reads the latest timestamps of the right and
+    // lower neighbours (the pixel's own where the neighbour would lie
+    // outside the image: a value the time differences then do not use).
+    const int64_t* __restrict__ tlb = P.t_last + tb0;
+    auto eoff_r = [&](int r) -> uint32_t { return eoff(r) + (gxc + 1 < (uint32_t)fr.W ? 1u : 0u); };
+    auto eoff_d = [&](int r) -> uint32_t {
+        const int gyc = min(max(gy0 + r, 0), fr.H - 1);
+        return eoff(r) + (gyc + 1 < fr.H ? (uint32_t)fr.W : 0u);
+    };
+
     constexpr bool kEarly = B && R <= 2;
     float eu[R], ea[R], eb[R], ed[R];
     int64_t etl[R], etr[R], etd[R];
@@ -872,24 +898,18 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     if constexpr (kEarly) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const int gy = gy0 + r;
-            eu[r] = 1.0f;
-            ea[r] = eb[r] = ed[r] = 0.0f;
-            etl[r] = etr[r] = etd[r] = kNever;
+            const uint32_t e = eoff(r);
+            eu[r] = *at(uin + tb0, e);
+            ea[r] = S::ld(at(pin + tb0, e), 0);
+            eb[r] = S::ld(at(pin + np + tb0, e), 0);
+            ed[r] = S::ld(at(pin + 2 * np + tb0, e), 0);
+            etl[r] = *at(tlb, e);
+            etr[r] = *at(tlb, eoff_r(r));
+            etd[r] = *at(tlb, eoff_d(r));
             enp[r] = enn[r] = 0;
-            if (col_in && gy >= 0 && gy < fr.H) {
-                const size_t k = (size_t)gy * fr.W + gx;
-                eu[r] = uin[k];
-                ea[r] = S::ld(pin, k);
-                eb[r] = S::ld(pin, np + k);
-                ed[r] = S::ld(pin, 2 * np + k);
-                etl[r] = P.t_last[k];
-                if (gx < fr.W - 1) etr[r] = P.t_last[k + 1];
-                if (gy < fr.H - 1) etd[r] = P.t_last[k + fr.W];
-                if (mode & kCounts) {
-                    enp[r] = P.npos[k];
-                    enn[r] = P.nneg[k];
-                }
+            if (mode & kCounts) {
+                enp[r] = *at(P.npos + tb0, e);
+                enn[r] = *at(P.nneg + tb0, e);
             }
         }
     }
@@ -905,31 +925,15 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         }
     }
 
-    // Tile-relative 32-bit element offsets.  The tile's rows lie within RH
-    // image rows of its first row clamped into the image (yb), so an offset
-    // from the per-tile plane bases fits 32 bits for every frame size, and
-    // the loads and stores take the scalar-base + vector-offset form.  Coordinates are clamped into the image: outside the image a
-    // lane reads an edge pixel's (finite) values, which never reach a pixel
-    // inside it, because the outside pixel's coefficients are zero.
-    const int yb = min(max(ry0, 0), fr.H - 1);
-    const size_t tb0 = (size_t)yb * fr.W;
-    const uint32_t gxc = (uint32_t)min(max(gx, 0), fr.W - 1);
-    auto eoff = [&](int r) -> uint32_t {  // (row offset < RH, W < 2^16: 24-bit product)
-        const int gyc = min(max(gy0 + r, 0), fr.H - 1);
-        return __umul24((uint32_t)(gyc - yb), (uint32_t)fr.W) + gxc;
-    };
-    const typename S::T* __restrict__ txb = txs + tb0;
-    const typename S::T* __restrict__ tyb = tys + tb0;
-
     float u[R], p1[R], p2[R], p3[R], txr[R], tyr[R];
     CoefT c[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int gy = gy0 + r;
         const bool in = col_in && gy >= 0 && gy < fr.H;
-        float uu = 1.0f, a = 0.0f, b = 0.0f, d = 0.0f, f = 1.0f, tx = 0.0f, ty = 0.0f;
+        const uint32_t e = eoff(r);
+        float uu, a, b, d, f, tx, ty;
         if constexpr (!build) {
-            const uint32_t e = eoff(r);
             uu = *at(uin + tb0, e);
             a = S::ld(at(pin + tb0, e), 0);
             b = S::ld(at(pin + np + tb0, e), 0);
@@ -937,65 +941,59 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
             f = *at(P.f + tb0, e);
             tx = S::ld(at(txb, e), 0);
             ty = S::ld(at(tyb, e), 0);
-        } else if (in) {
-            const size_t k = (size_t)gy * fr.W + gx;
+        } else {
+            int32_t npos = 0, nneg = 0;
+            int64_t tl, tr, td;
             if constexpr (kEarly) {
                 uu = eu[r];
                 a = ea[r];
                 b = eb[r];
                 d = ed[r];
+                tl = etl[r];
+                tr = etr[r];
+                td = etd[r];
+                npos = enp[r];
+                nneg = enn[r];
             } else {
-                uu = uin[k];
-                a = S::ld(pin, k);
-                b = S::ld(pin, np + k);
-                d = S::ld(pin, 2 * np + k);
+                uu = *at(uin + tb0, e);
+                a = S::ld(at(pin + tb0, e), 0);
+                b = S::ld(at(pin + np + tb0, e), 0);
+                d = S::ld(at(pin + 2 * np + tb0, e), 0);
+                tl = *at(tlb, e);
+                tr = *at(tlb, eoff_r(r));
+                td = *at(tlb, eoff_d(r));
+                if (mode & kCounts) {
+                    npos = *at(P.npos + tb0, e);
+                    nneg = *at(P.nneg + tb0, e);
+                }
             }
-            if (build) {
-                const int lr = v * R + r;
-                const bool hr = gx < fr.W - 1, hd = gy < fr.H - 1;
-                int32_t npos = 0, nneg = 0;
-                int64_t tl, tr, td;
-                if constexpr (kEarly) {
-                    tl = etl[r];
-                    tr = etr[r];
-                    td = etd[r];
-                    npos = enp[r];
-                    nneg = enn[r];
-                } else {
-                    tl = P.t_last[k];
-                    tr = hr ? P.t_last[k + 1] : kNever;
-                    td = hd ? P.t_last[k + fr.W] : kNever;
-                    if (mode & kCounts) {
-                        npos = P.npos[k];
-                        nneg = P.nneg[k];
-                    }
+            const int lr = v * R + r;
+            const bool hr = in && gx < fr.W - 1, hd = in && gy < fr.H - 1;
+            if (events) {
+                npos += tb.pos[lr * CW + col];
+                nneg += tb.neg[lr * CW + col];
+                tl = max(tl, (int64_t)tb.tmax[lr * (CW + 1) + col]);
+                tr = max(tr, (int64_t)tb.tmax[lr * (CW + 1) + col + 1]);
+                td = max(td, (int64_t)tb.tmax[(lr + 1) * (CW + 1) + col]);
+            }
+            // (without events the factor is exp(0) = 1: f = u_prev exactly,
+            // and a row of lanes without events skips the FP64 exp)
+            f = (npos | nneg) != 0 ? data_image(uu, npos, nneg, bc.dpos, bc.dneg) : uu;
+            if (mode & kTimeMem) {
+                tx = S::ld(at(txb, e), 0);
+                ty = S::ld(at(tyb, e), 0);
+            } else {
+                time_diffs(tl, tr, td, hr, hd, tb.t_first, bc, tx, ty);
+                tx = S::round(tx);
+                ty = S::round(ty);
+            }
+            if (in && col_out && lr >= KG && lr < RH - KG) {
+                *at(P.f + tb0, e) = f;
+                if (!(mode & kTimeMem)) {
+                    S::st(at(txs + tb0, e), 0, tx);
+                    S::st(at(tys + tb0, e), 0, ty);
                 }
-                if (events) {
-                    npos += tb.pos[lr * CW + col];
-                    nneg += tb.neg[lr * CW + col];
-                    tl = max(tl, (int64_t)tb.tmax[lr * (CW + 1) + col]);
-                    tr = max(tr, (int64_t)tb.tmax[lr * (CW + 1) + col + 1]);
-                    td = max(td, (int64_t)tb.tmax[(lr + 1) * (CW + 1) + col]);
-                }
-                // (without events the factor is exp(0) = 1: f = u_prev exactly,
-                // and a row of lanes without events skips the FP64 exp)
-                f = (npos | nneg) != 0 ? data_image(uu, npos, nneg, bc.dpos, bc.dneg) : uu;
-                if (mode & kTimeMem) {
-                    tx = S::ld(txs, k);
-                    ty = S::ld(tys, k);
-                } else {
-                    time_diffs(tl, tr, td, hr, hd, tb.t_first, bc, tx, ty);
-                    tx = S::round(tx);
-                    ty = S::round(ty);
-                }
-                if (col_out && lr >= KG && lr < RH - KG) {
-                    P.f[k] = f;
-                    if (!(mode & kTimeMem)) {
-                        S::st(txs, k, tx);
-                        S::st(tys, k, ty);
-                    }
-                    if (events) P.t_last[k] = tl;
-                }
+                if (events) *at(P.t_last + tb0, e) = tl;
             }
         }
         // pixels outside the image get all-zero coefficients, so their q is 0
