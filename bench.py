@@ -83,6 +83,7 @@ WORKLOADS = {
     "probe": (5120, 5760, 20000, 50),
     "streams64": (0, 0, 0, 50),
     "diff16": (346, 260, 2000, 100),
+    "frame": (0, 0, 1000, 50),  # size from --frame
 }
 #   streams64  64 independent cameras: 16 each of 128x128, 240x180, 346x260 and
 #          640x480 (7.3 Mpx, ~440 MB of state: beyond the Infinity Cache);
@@ -611,7 +612,16 @@ WORKLOAD_TEXT = {
              "events, 100 FP32 primal-dual iterations per block, lambda 90, threshold 0.2",
     "probe": "5120x5760 frame (29.5 Mpx), uniform random events, blocks of 20000 events, 50 FP32 "
              "primal-dual iterations per block, lambda 90",
+    "frame": "{w}x{h} frame, uniform random events, blocks of 1000 events, 50 FP32 primal-dual "
+             "iterations per block, lambda 90",
 }
+
+
+def parse_frame(text):
+    w, h = (int(v) for v in text.lower().split("x"))
+    if not (1 <= w <= 65535 and 1 <= h <= 65535):
+        raise SystemExit(f"--frame {text}: width and height in 1..65535")
+    return w, h
 
 
 def main():
@@ -626,6 +636,8 @@ def main():
     ap.add_argument("--cols", type=int, default=0,
                     help="fused tile width, 64 or 32 (0: auto; needs --rows/--waves)")
     ap.add_argument("--workload", default="davis240", choices=sorted(WORKLOADS))
+    ap.add_argument("--frame", default="640x480",
+                    help="WxH of the 'frame' workload (uniform random events, 1000 per block)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="storage of the dual field and time differences (arithmetic is FP32)")
     ap.add_argument("--tvl1", type=int, default=0,
@@ -673,6 +685,8 @@ def main():
         return main_streams64(args)
     need = args.warmup + args.steps
     W, H, B, IT = WORKLOADS[args.workload]
+    if args.workload == "frame":
+        W, H = parse_frame(args.frame)
     log(f"bench: generating {args.workload} stream for {need} blocks")
     if args.workload == "davis240":
         ev = load_stream(need)
@@ -696,7 +710,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "storage": args.storage,
         "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
+        "config": {"workload": WORKLOAD_TEXT[args.workload].format(w=W, h=H),
                    "width": W, "height": H, "events_per_batch": B,
                    "iters_per_batch": IT, "fuse_iters": args.fuse, "tvl1_iters": args.tvl1,
                    "tile_rows": args.rows, "tile_waves": args.waves, "tile_cols": args.cols},
