@@ -860,10 +860,6 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     tb.t_first = 0;
     const bool col_in = gx >= 0 && gx < fr.W;
     const bool col_out = col_in && col >= KG && col < CW - KG;
-    // First launch with few rows per lane: the pixel loads are issued
-    // between clearing the bins and scanning the events, so that their
-    // latency overlaps the event loads (with more rows the registers they
-    // hold would cost occupancy).
     // Tile-relative 32-bit element offsets.  The tile's rows lie within RH
     // image rows of its first row clamped into the image (yb), so an offset
     // from the per-tile plane bases fits 32 bits for every frame size, and
@@ -890,6 +886,10 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
         return eoff(r) + (gyc + 1 < fr.H ? (uint32_t)fr.W : 0u);
     };
 
+    // First launch with few rows per lane: the pixel loads are issued
+    // between clearing the bins and scanning the events, so that their
+    // latency overlaps the event loads (with more rows the registers they
+    // hold would cost occupancy).
     constexpr bool kEarly = B && R <= 2;
     float eu[R], ea[R], eb[R], ed[R];
     int64_t etl[R], etr[R], etd[R];
