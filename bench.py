@@ -39,19 +39,19 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 # copy: FETCH_SIZE read 131084 KiB and WRITE_SIZE 262144 KiB for 262144 KiB
 # moved each way, so fetched bytes = 2 x 1024 x FETCH_SIZE and written bytes
 # = 1024 x WRITE_SIZE.  Each entry holds for the kernel sources it was taken
-# with (hash of kernels.hip, pd_math.h, kernels.h, tile.h, and rec_api.hip,
+# with (hash of kernels.hip, pd_math.h, kernels.h, tile.h, and shape.h,
 # which picks the default tile); after a change the bench reports traffic
 # null until the counters are taken again.
-TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "rec_api.hip")
+TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "shape.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("1b2b73eddf7becba", 2 * 1024 * 1072.6, 1024 * 820.7),
-    ("probe", "f32"): ("1b2b73eddf7becba", 2 * 1024 * 553231.0, 1024 * 546272.4),
+    ("davis240", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 1072.6, 1024 * 820.7),
+    ("probe", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 553176.2, 1024 * 546481.0),
     # the probe with one iteration per launch on 2 x 8 x 64 tiles
-    ("probe_k1", "f32"): ("1b2b73eddf7becba", 2 * 1024 * 409082.9, 1024 * 477107.3),
+    ("probe_k1", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 409107.4, 1024 * 477107.3),
     # the batched solve of all 64 cameras: bytes of one whole solve (every
     # launch of every class chain), for the class geometries below
-    ("streams64", "f32"): ("1b2b73eddf7becba", 2 * 1024 * 814299.0, 1024 * 1069552.0),
+    ("streams64", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 814292.2, 1024 * 1069606.1),
 }
 # class geometries the 64-camera counters were taken with: (width, height of
 # the class's first camera, rows, waves, columns, iterations per launch)

@@ -335,7 +335,8 @@ typedef struct {
     int32_t kiters;         /* iterations per launch K_c */
     int32_t tiles;          /* workgroups per launch of the class */
     double tuned_us;        /* autotuner's time of the whole tuned schedule for its
-                               tune_iters iterations (0 when not tuned) */
+                               tune_iters iterations, least of five runs (0 when not
+                               tuned) */
 } rec_batch_class;
 
 /* Device workspace bytes for a batch of these contexts (0 if invalid). */
@@ -346,7 +347,8 @@ size_t rec_batch_workspace_bytes(rec_ctx* const* ctxs, int32_t n);
  * contexts stay owned by the caller and must outlive the batch.  Without
  * tuning (tune_iters == 0) all sizes share the automatic geometry of a
  * frame of the batch's total pixel count (one class).  With tune_iters > 0
- * an autotuner times the whole schedule of tune_iters iterations for every
+ * an autotuner times the whole schedule of tune_iters iterations (the
+ * least of five runs after a warm-up run) for every
  * candidate geometry shared by all sizes, keeps the fastest, then runs a
  * coordinate descent over the sizes (largest first), each trying every
  * candidate (rows, waves, columns, K) with the others fixed; sizes that end

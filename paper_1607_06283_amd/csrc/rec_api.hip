@@ -21,6 +21,7 @@
 #include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "kernels.h"
+#include "shape.h"
 #include "rec.h"
 
 using rec::Planes;
@@ -213,68 +214,6 @@ int flush_deferred(rec_ctx* c) {
     return REC_OK;
 }
 
-// Fused tile shape (rows per lane, wavefronts per workgroup, columns) and
-// iterations per launch.  Small and mid-size frames are limited by the
-// latency of each iteration on a compute unit and by the fixed cost of each
-// launch, large frames by VALU issue and HBM.  Measured on MI355X, 50
-// iterations per block, pixel-iterations/s (shape = rows x waves x columns,
-// K = iterations per launch):
-//   64x64 and 128x128: 1x16x32 K 10: 5.4 and 21.4 G (2x16x64 K 13: 4.5, 17.9)
-//   240x180:           1x16x32 K 9: 49 G (2x16x64 K 13: 45 G)
-//   320x240, 346x260:  2x8x32 K 8: 69, 69 G (best of 18 shapes 74, 74 G;
-//                      2x16x64 K 13: 54, 51 G)
-//   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
-//   800x600:           2x8x32 K 8: 153 G (best 154 G)
-//   1280x720:          8x8x64 K 10: 308 G (6x8x64 K 6: 297 G, 8x8x64 K 8: 283 G)
-//   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G)
-//   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
-//                      (4x8x64 K 6: 284 G, 448 G)
-// `narrow` allows 32-column tiles (the batched launch has 64 only; it
-// takes 2x16 K 13 up to 250k pixels and the large-frame shape beyond).
-void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int* waves,
-                  int* cols, int* kiters) {
-    int r = prm->tile_rows, w = prm->tile_waves, cw = prm->tile_cols ? prm->tile_cols : 64, k;
-    const bool f32 = prm->storage == rec::kStoreF32;
-    int ar, aw, acw;  // automatic shape
-    if (!narrow) {
-        if (np <= 250000) {
-            ar = 2, aw = 16, acw = 64, k = 13;
-        } else {
-            ar = f32 ? 6 : 4, aw = 8, acw = 64, k = 6;
-        }
-    } else if (np <= 24000) {
-        ar = 1, aw = 16, acw = 32, k = 10;
-    } else if (np <= 60000) {
-        ar = 1, aw = 16, acw = 32, k = 9;
-    } else if (np <= 120000) {
-        ar = 2, aw = 8, acw = 32, k = 8;
-    } else if (np <= 400000) {
-        ar = 4, aw = 16, acw = 64, k = 13;
-    } else if (np <= 600000) {
-        ar = 2, aw = 8, acw = 32, k = 8;
-    } else if (np <= 2000000) {
-        ar = 8, aw = 8, acw = 64, k = 10;
-    } else {
-        ar = 8, aw = 8, acw = 64, k = 8;
-    }
-    if (!rec::fused_shape_supported(ar, aw, acw, prm->storage)) {
-        // 16-bit storage has 2x8 as its only 32-column tile
-        ar = 2, aw = 8, acw = 32;
-    }
-    if (!r) {
-        r = ar;
-        w = aw;
-        cw = acw;
-    }
-    if (prm->fuse_iters > 0) k = prm->fuse_iters;
-    const int rh = r * w * (64 / cw);
-    const int kmax = (rh - 1) / 2 < (cw - 1) / 2 ? (rh - 1) / 2 : (cw - 1) / 2;
-    if (k > kmax) k = kmax;
-    *rows = r;
-    *waves = w;
-    *cols = cw;
-    *kiters = k;
-}
 
 }  // namespace
 
@@ -387,7 +326,7 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     c->kc.umax = (float)prm->u_max;
     c->stream = (hipStream_t)hip_stream;
     c->cur = 0;
-    choose_shape(prm, (int64_t)prm->width * prm->height, true, &c->rows, &c->waves, &c->cols,
+    rec::choose_shape(prm, (int64_t)prm->width * prm->height, true, &c->rows, &c->waves, &c->cols,
                  &c->kmax);
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -1143,7 +1082,8 @@ int enqueue_chains(rec_batch* b, hipStream_t main, int q, int iters, unsigned fo
 }
 
 // Time `reps` side-effect-free runs of the whole schedule of the current
-// geometries (concurrent chains, `iters` iterations); microseconds per run.
+// geometries (concurrent chains, `iters` iterations): the least time of
+// a run, in microseconds.
 int time_schedule(rec_batch* b, int iters, int reps, double* us) {
     build_classes(b);
     int rc = upload_work(b);
@@ -1155,24 +1095,33 @@ int time_schedule(rec_batch* b, int iters, int reps, double* us) {
     if (hipMemcpy(b->d_desc[0], h, b->ctx.size() * sizeof(rec::StreamDesc), hipMemcpyHostToDevice) !=
         hipSuccess)
         return REC_EDEVICE;
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess) return REC_EDEVICE;
-    if (hipEventCreate(&e1) != hipSuccess) {
-        (void)hipEventDestroy(e0);
-        return REC_EDEVICE;
-    }
-    rc = enqueue_chains(b, b->stream, 0, iters, 0, true, true);  // warm-up run
-    if (!rc && hipEventRecord(e0, b->stream) != hipSuccess) rc = REC_EDEVICE;
-    for (int r = 0; r < reps && !rc; ++r)
+    // one event between runs: the time of a run is the least of `reps`
+    // (each run's chains are joined back into the stream before the next
+    // forks, so consecutive events bracket one run)
+    constexpr int kMaxReps = 8;
+    if (reps < 1 || reps > kMaxReps) return REC_EINVAL;
+    hipEvent_t ev[kMaxReps + 1];
+    int nev = 0;
+    for (; nev <= reps; ++nev)
+        if (hipEventCreate(&ev[nev]) != hipSuccess) break;
+    if (nev <= reps) rc = REC_EDEVICE;
+    if (!rc) rc = enqueue_chains(b, b->stream, 0, iters, 0, true, true);  // warm-up run
+    if (!rc && hipEventRecord(ev[0], b->stream) != hipSuccess) rc = REC_EDEVICE;
+    for (int r = 0; r < reps && !rc; ++r) {
         rc = enqueue_chains(b, b->stream, 0, iters, 0, true, true);
-    if (!rc && hipEventRecord(e1, b->stream) != hipSuccess) rc = REC_EDEVICE;
-    float ms = 0.0f;
-    if (!rc && (hipStreamSynchronize(b->stream) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
-        rc = REC_EDEVICE;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (!rc) *us = (double)ms * 1e3 / reps;
+        if (!rc && hipEventRecord(ev[r + 1], b->stream) != hipSuccess) rc = REC_EDEVICE;
+    }
+    if (!rc && hipStreamSynchronize(b->stream) != hipSuccess) rc = REC_EDEVICE;
+    float best = 0.0f;
+    for (int r = 0; r < reps && !rc; ++r) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev[r], ev[r + 1]) != hipSuccess)
+            rc = REC_EDEVICE;
+        else if (r == 0 || ms < best)
+            best = ms;
+    }
+    for (int i = 0; i < nev; ++i) (void)hipEventDestroy(ev[i]);
+    if (!rc) *us = (double)best * 1e3;
     return rc;
 }
 
@@ -1269,7 +1218,7 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
         int64_t total = 0;
         for (const BatchGroup& g : b->grp) total += g.px;
         int r, w, cw, k;
-        choose_shape(&ctxs[0]->prm, total, false, &r, &w, &cw, &k);
+        rec::choose_shape(&ctxs[0]->prm, total, false, &r, &w, &cw, &k);
         if (!rec::batch_shape_supported(r, w, cw, b->storage)) {
             r = 4;
             w = 8;
@@ -1314,7 +1263,7 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
         //     with equal geometries share one launch chain).
         const std::vector<Shape> cand = batch_candidates(b->storage);
         auto measure = [&](double* us) {
-            const int r = time_schedule(b, tune_iters, 3, us);
+            const int r = time_schedule(b, tune_iters, 5, us);
             return r == REC_ENOMEM || r == REC_EINVAL ? 1 : r;  // 1: does not fit
         };
         double best = 1e300;

@@ -1,0 +1,77 @@
+// The fused loop's automatic tile shape (a host function of the library).
+// It lives apart from the C ABI's source so that the files that decide
+// which kernels a solve launches on which tiles (this one, the kernels and
+// their headers) are separate from the rest of the library.
+#pragma once
+
+#include <stdint.h>
+
+#include "kernels.h"
+#include "rec.h"
+
+namespace rec {
+
+// Fused tile shape (rows per lane, wavefronts per workgroup, columns) and
+// iterations per launch.  Small and mid-size frames are limited by the
+// latency of each iteration on a compute unit and by the fixed cost of each
+// launch, large frames by VALU issue and HBM.  Measured on MI355X, 50
+// iterations per block, pixel-iterations/s (shape = rows x waves x columns,
+// K = iterations per launch):
+//   64x64 and 128x128: 1x16x32 K 10: 5.4 and 21.4 G (2x16x64 K 13: 4.5, 17.9)
+//   240x180:           1x16x32 K 9: 49 G (2x16x64 K 13: 45 G)
+//   320x240, 346x260:  2x8x32 K 8: 69, 69 G (best of 18 shapes 74, 74 G;
+//                      2x16x64 K 13: 54, 51 G)
+//   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
+//   800x600:           2x8x32 K 8: 153 G (best 154 G)
+//   1280x720:          8x8x64 K 10: 308 G (6x8x64 K 6: 297 G, 8x8x64 K 8: 283 G)
+//   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G)
+//   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
+//                      (4x8x64 K 6: 284 G, 448 G)
+// `narrow` allows 32-column tiles (the untuned batch keeps 64 columns: it
+// takes 2x16 K 13 up to 250k pixels and the large-frame shape beyond).
+inline void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int* waves,
+                  int* cols, int* kiters) {
+    int r = prm->tile_rows, w = prm->tile_waves, cw = prm->tile_cols ? prm->tile_cols : 64, k;
+    const bool f32 = prm->storage == kStoreF32;
+    int ar, aw, acw;  // automatic shape
+    if (!narrow) {
+        if (np <= 250000) {
+            ar = 2, aw = 16, acw = 64, k = 13;
+        } else {
+            ar = f32 ? 6 : 4, aw = 8, acw = 64, k = 6;
+        }
+    } else if (np <= 24000) {
+        ar = 1, aw = 16, acw = 32, k = 10;
+    } else if (np <= 60000) {
+        ar = 1, aw = 16, acw = 32, k = 9;
+    } else if (np <= 120000) {
+        ar = 2, aw = 8, acw = 32, k = 8;
+    } else if (np <= 400000) {
+        ar = 4, aw = 16, acw = 64, k = 13;
+    } else if (np <= 600000) {
+        ar = 2, aw = 8, acw = 32, k = 8;
+    } else if (np <= 2000000) {
+        ar = 8, aw = 8, acw = 64, k = 10;
+    } else {
+        ar = 8, aw = 8, acw = 64, k = 8;
+    }
+    if (!fused_shape_supported(ar, aw, acw, prm->storage)) {
+        // 16-bit storage has 2x8 as its only 32-column tile
+        ar = 2, aw = 8, acw = 32;
+    }
+    if (!r) {
+        r = ar;
+        w = aw;
+        cw = acw;
+    }
+    if (prm->fuse_iters > 0) k = prm->fuse_iters;
+    const int rh = r * w * (64 / cw);
+    const int kmax = (rh - 1) / 2 < (cw - 1) / 2 ? (rh - 1) / 2 : (cw - 1) / 2;
+    if (k > kmax) k = kmax;
+    *rows = r;
+    *waves = w;
+    *cols = cw;
+    *kiters = k;
+}
+
+}  // namespace rec
