@@ -148,23 +148,31 @@ def hd720_stream(n_batches):
 
 
 def run_gpu(ev, steps, warmup, fuse, profile, shape=(W_, H_), batch=EVENTS_PER_BATCH,
-            iters=ITERS, rows=0, waves=0, storage=0, tvl1=0, cols=0):
+            iters=ITERS, rows=0, waves=0, storage=0, tvl1=0, cols=0, host_events=False):
+    """Push + solve `steps` blocks after `warmup`.  The events are resident in
+    device memory and pushed as device pointers, or with host_events pushed
+    from host memory (the library stages them and copies them over PCIe)."""
     import torch
     from paper_1607_06283_amd import rec
 
     dev = torch.device("cuda", 0)
-    t = torch.from_numpy(ev.t).to(dev)
-    x = torch.from_numpy(ev.x.view(np.int16)).to(dev)
-    y = torch.from_numpy(ev.y.view(np.int16)).to(dev)
-    p = torch.from_numpy(ev.p).to(dev)
+    if host_events:
+        arrs = [np.ascontiguousarray(a) for a in (ev.t, ev.x, ev.y, ev.p)]
+        base = [a.ctypes.data for a in arrs]
+        on_dev = 0
+    else:
+        arrs = [torch.from_numpy(ev.t).to(dev), torch.from_numpy(ev.x.view(np.int16)).to(dev),
+                torch.from_numpy(ev.y.view(np.int16)).to(dev), torch.from_numpy(ev.p).to(dev)]
+        base = [a.data_ptr() for a in arrs]
+        on_dev = 1
     r = rec.Reconstructor(shape[0], shape[1], fuse_iters=fuse, tile_rows=rows, tile_waves=waves,
                           tile_cols=cols, storage=storage, tvl1_iters=tvl1)
     B = batch
 
     def step(i):
         a = i * B
-        rc = rec.rec_push_events(r.ctx, t.data_ptr() + 8 * a, x.data_ptr() + 2 * a,
-                                 y.data_ptr() + 2 * a, p.data_ptr() + a, B, 1)
+        rc = rec.rec_push_events(r.ctx, base[0] + 8 * a, base[1] + 2 * a, base[2] + 2 * a,
+                                 base[3] + a, B, on_dev)
         if rc:
             raise rec.RecError(rc, "rec_push_events")
         rc, _ = rec.rec_solve(r.ctx, iters, False)
@@ -642,6 +650,9 @@ def main():
                     help="storage of the dual field and time differences (arithmetic is FP32)")
     ap.add_argument("--tvl1", type=int, default=0,
                     help="TV-L1 timestamp-denoising iterations before each block's metric")
+    ap.add_argument("--host-events", action="store_true",
+                    help="push the events from host memory (PCIe-inclusive rate) instead of "
+                         "from device memory")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--no-extras", action="store_true",
@@ -698,7 +709,7 @@ def main():
         raise SystemExit("stream too short")
     storage = {"f32": 0, "bf16": 1, "f16": 2}[args.storage]
     kw = dict(shape=(W, H), batch=B, iters=IT, rows=args.rows, waves=args.waves, storage=storage,
-              tvl1=args.tvl1, cols=args.cols)
+              tvl1=args.tvl1, cols=args.cols, host_events=args.host_events)
     log("bench: timed pass")
     dt, _, u = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=False, **kw)
     px_iters = args.steps * IT * W * H
@@ -713,7 +724,8 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload].format(w=W, h=H),
                    "width": W, "height": H, "events_per_batch": B,
                    "iters_per_batch": IT, "fuse_iters": args.fuse, "tvl1_iters": args.tvl1,
-                   "tile_rows": args.rows, "tile_waves": args.waves, "tile_cols": args.cols},
+                   "tile_rows": args.rows, "tile_waves": args.waves, "tile_cols": args.cols,
+                   "events_from": "host" if args.host_events else "device"},
         "events_per_s": round(ev_rate, 1),
         "realtime_factor": round(ev_rate / 1e6, 3),
     }
@@ -721,7 +733,7 @@ def main():
         log("bench: per-kernel timing pass")
         _, prof, _ = run_gpu(ev, args.steps, args.warmup, args.fuse, profile=True, **kw)
         bpi = BYTES_PER_PX_ITER if storage == 0 else BYTES_PER_PX_ITER_16
-        eligible = args.fuse == -1 and not args.rows and not args.tvl1
+        eligible = args.fuse == -1 and not args.rows and not args.tvl1 and not args.host_events
         out["roofline"] = roofline(prof, bpi, "k_pd_fused" if args.fuse else "k_primal+k_dual",
                                    (args.workload, args.storage) if eligible else None)
         out["kernel_ms"] = {"push": round(prof.ms[0], 3), "build": round(prof.ms[1], 3),

@@ -51,7 +51,12 @@
  *     launch of the next rec_solve validates and bins them itself (or, for
  *     more pushes or events than it takes, they are scattered by kernels of
  *     their own at that point).  Host-pointer pushes are validated on the
- *     host, copied through the pinned staging buffer and scattered at once.
+ *     host, written to the pinned staging buffer and moved by a copy kernel on
+ *     the context's stream into the workspace's staging ring; from there
+ *     they take the same way (the unfused loop, and a push of more than
+ *     max_events events, scatter them at once).  The ring has room for two
+ *     pushes of max_events events: a push that starts a half waits on the
+ *     host for the last copy out of that half.
  *   - rec_push_events and rec_solve without stats do not synchronise.
  *     rec_solve with stats, rec_get_image, rec_gap_history, rec_get_times,
  *     rec_set_state, rec_profile_read, rec_sync and rec_destroy synchronise
@@ -132,7 +137,8 @@ typedef struct {
                                 size (default), 0 = unfused two-kernel loop, k >= 1 = at
                                 most k (also capped by the tile height) */
     int32_t max_events;      /* largest host-pointer push handled in one piece (larger
-                                pushes are split); sizes the device staging; default 65536 */
+                                pushes are split); sizes the staging ring, 26 bytes per
+                                event of workspace and of pinned memory; default 65536 */
     int32_t tile_rows;       /* fused tile: rows per lane x wavefronts per workgroup, one of */
     int32_t tile_waves;      /*   2x2 2x4 2x8 2x16 3x16 4x1 4x2 4x4 4x8 4x16 5x8 6x8 8x1
                                   8x2 8x4 8x8 16x1 16x2 16x4 (16-bit storage: 2x16 4x8 4x16

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "librec.so")
 PROBE_PATH = os.path.join(HERE, "sync_probe")
-SOURCES = ["kernels.hip", "rec_api.hip", "adjoint.hip"]
+SOURCES = ["kernels.hip", "rec_api.hip", "adjoint.hip", "staging.hip"]
 ARCH = "gfx950"
 
 # -ffp-contract=off: every fused multiply-add in the per-pixel arithmetic is

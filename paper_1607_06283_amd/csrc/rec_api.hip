@@ -22,6 +22,7 @@
 
 #include "kernels.h"
 #include "shape.h"
+#include "staging.h"
 #include "rec.h"
 
 using rec::Planes;
@@ -35,6 +36,9 @@ constexpr int64_t kFoldMaxEvents = 16384;   // events binned in the first launch
 constexpr int64_t kFoldMaxWork = 1 << 24;   // events x tiles scanned in it at most
 
 inline size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Bytes of each half of the staging ring: one packed record of ne events.
+inline size_t stage_half(size_t ne) { return align_up(ne * 13); }
 
 // Lays the workspace out (base == nullptr: only sizes it).  Returns bytes.
 size_t carve(const rec_params* prm, char* base, Planes* P) {
@@ -59,10 +63,14 @@ size_t carve(const rec_params* prm, char* base, Planes* P) {
     q.t_last = (int64_t*)take(np * 8);
     q.npos = (int32_t*)take(np * 4);
     q.nneg = (int32_t*)take(np * 4);
-    q.ev_t = (int64_t*)take(ne * 8);
-    q.ev_x = (uint16_t*)take(ne * 2);
-    q.ev_y = (uint16_t*)take(ne * 2);
-    q.ev_p = (int8_t*)take(ne);
+    // staging ring of host-pointer pushes: two halves of 13 bytes per event
+    // (a push of max_events events fills one); ev_x .. ev_p: the planes of
+    // such a push at the start of the first half
+    char* ring = take(2 * stage_half(ne));
+    q.ev_t = (int64_t*)ring;
+    q.ev_x = ring ? (uint16_t*)(ring + 8 * ne) : nullptr;
+    q.ev_y = ring ? (uint16_t*)(ring + 10 * ne) : nullptr;
+    q.ev_p = ring ? (int8_t*)(ring + 12 * ne) : nullptr;
     q.gap_part = (double*)take(rec::gap_blocks(np) * 2 * sizeof(double));
     q.gap_hist = (double*)take((size_t)rec::kGapHistCap * 2 * sizeof(double));
     const size_t nt = prm->tvl1_iters > 0 ? np : 0;  // denoising planes only when enabled
@@ -105,14 +113,17 @@ struct rec_ctx {
     int cur;                 // which ping-pong buffers hold the current (u, p)
     int rows, waves, cols;   // fused tile shape
     int kmax;                // iterations per fused launch (at most)
-    // host staging for host-pointer pushes
+    // Host-pointer pushes are staged as packed records (t, x, y, polarity of
+    // one push, back to back) in a ring of two halves: the pinned host buffer
+    // and the workspace's staging ring hold a record at the same offset, and
+    // one copy kernel moves it.  Records fill the current half (stage_cur) up
+    // to stage_used; stage_done[h]: the last copy out of half h.
     char* pinned;
-    int64_t* h_t;
-    uint16_t* h_x;
-    uint16_t* h_y;
-    int8_t* h_p;
-    hipEvent_t staging_done;
-    bool staging_busy;
+    const char* pinned_dev;  // its device address
+    size_t stage_used;
+    int stage_cur;
+    hipEvent_t stage_done[2];
+    bool stage_busy[2];
     // device-pointer pushes recorded but not scattered yet (in order)
     std::vector<Seg> deferred;
     int64_t deferred_events;
@@ -211,6 +222,55 @@ int flush_deferred(rec_ctx* c) {
     }
     c->deferred.clear();
     c->deferred_events = 0;
+    return REC_OK;
+}
+
+// Copies the n events of a host-pointer push (at most max_events) into the
+// staging ring as one packed record: written to the pinned buffer, then
+// moved by a copy kernel on the context's stream; *out gets the record's
+// four device arrays.  When the current half is full, the record starts
+// the other one: the pushes still recorded in that half are scattered
+// first (the copy, enqueued after them, then overwrites nothing still to be
+// read), and the host waits for the half's last copy before rewriting its
+// pinned bytes, so it runs at most about a half ahead of the device.
+int stage_events(rec_ctx* c, const int64_t* t, const uint16_t* x, const uint16_t* y,
+                 const int8_t* p, int64_t n, Seg* out) {
+    const size_t m = (size_t)n, need = 13 * m, half = stage_half((size_t)c->prm.max_events);
+    if (c->stage_used + need > half) {
+        const int o = c->stage_cur ^ 1;
+        const char* lo = (const char*)c->P.ev_t + (size_t)o * half;
+        for (const Seg& s : c->deferred) {
+            if ((const char*)s.t >= lo && (const char*)s.t < lo + half) {
+                const int rc = flush_deferred(c);
+                if (rc) return rc;
+                break;
+            }
+        }
+        if (c->stage_busy[o] && hipEventSynchronize(c->stage_done[o]) != hipSuccess)
+            return REC_EDEVICE;
+        c->stage_busy[o] = false;
+        c->stage_cur = o;
+        c->stage_used = 0;
+    }
+    const int hh = c->stage_cur;
+    const size_t off = (size_t)hh * half + c->stage_used;
+    char* h = c->pinned + off;
+    memcpy(h, t, m * 8);
+    memcpy(h + 8 * m, x, m * 2);
+    memcpy(h + 10 * m, y, m * 2);
+    memcpy(h + 12 * m, p, m);
+    char* d = (char*)c->P.ev_t + off;
+    // whole 16-byte words: the slot extends to the next 256-byte boundary
+    const int rc = timed(c, 0, 0, [&](rec::LaunchEv ev) {
+        return rec::launch_pull(c->pinned_dev + off, d, (need + 15) & ~(size_t)15, c->stream,
+                                ev.start, ev.stop);
+    });
+    if (rc) return rc;
+    if (hipEventRecord(c->stage_done[hh], c->stream) != hipSuccess) return REC_EDEVICE;
+    c->stage_busy[hh] = true;
+    c->stage_used = align_up(c->stage_used + need);
+    *out = Seg{(const int64_t*)d, (const uint16_t*)(d + 8 * m), (const uint16_t*)(d + 10 * m),
+               (const int8_t*)(d + 12 * m), n};
     return REC_OK;
 }
 
@@ -333,18 +393,20 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
         return REC_EDEVICE;
     }
     const size_t ne = (size_t)prm->max_events;
-    const size_t pb = align_up(ne * 8) + align_up(ne * 2) * 2 + align_up(ne);
-    if (hipHostMalloc((void**)&c->pinned, pb, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void**)&c->pinned, 2 * stage_half(ne), hipHostMallocDefault) !=
+        hipSuccess) {
         delete c;
         return REC_ENOMEM;
     }
-    c->h_t = (int64_t*)c->pinned;
-    c->h_x = (uint16_t*)(c->pinned + align_up(ne * 8));
-    c->h_y = (uint16_t*)(c->pinned + align_up(ne * 8) + align_up(ne * 2));
-    c->h_p = (int8_t*)(c->pinned + align_up(ne * 8) + 2 * align_up(ne * 2));
-    if (hipEventCreateWithFlags(&c->staging_done, hipEventDisableTiming) != hipSuccess) {
+    if (hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0) != hipSuccess) {
         rec_destroy(c);
         return REC_EDEVICE;
+    }
+    for (hipEvent_t* e : {&c->stage_done[0], &c->stage_done[1]}) {
+        if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) {
+            rec_destroy(c);
+            return REC_EDEVICE;
+        }
     }
     c->mirror_known = true;
     c->mirror_started = false;
@@ -388,10 +450,13 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
         c->deferred_events += n;
         return REC_OK;
     }
-    // host pointers: earlier device pushes go first, then validate here
-    int rc = flush_deferred(c);
-    if (rc) return rc;
+    // host pointers: validated here against the host mirror of the stream
+    // state (earlier device pushes go first, to learn their outcome), then
+    // staged as one packed record with one copy
+    int rc;
     if (!c->mirror_known) {
+        rc = flush_deferred(c);
+        if (rc) return rc;
         rec::DevState st;
         rc = read_state(c, &st);
         if (rc) return rc;
@@ -403,30 +468,33 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
                           c->mirror_started ? c->mirror_tref : INT64_MIN);
     if (rc) return rc;
     const int64_t cap = c->prm.max_events;
-    for (int64_t a = 0; a < n; a += cap) {
-        const int64_t m = (n - a < cap) ? n - a : cap;
-        if (c->staging_busy && hipEventSynchronize(c->staging_done) != hipSuccess) return REC_EDEVICE;
-        memcpy(c->h_t, t_us + a, (size_t)m * 8);
-        memcpy(c->h_x, x + a, (size_t)m * 2);
-        memcpy(c->h_y, y + a, (size_t)m * 2);
-        memcpy(c->h_p, polarity + a, (size_t)m);
-        hipError_t e = hipMemcpyAsync(c->P.ev_t, c->h_t, (size_t)m * 8, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->P.ev_x, c->h_x, (size_t)m * 2, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->P.ev_y, c->h_y, (size_t)m * 2, hipMemcpyHostToDevice, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->P.ev_p, c->h_p, (size_t)m, hipMemcpyHostToDevice, c->stream);
-        if (e != hipSuccess) return REC_EDEVICE;
-        rc = timed(c, 0, m, [&](rec::LaunchEv ev) {
-            return rec::launch_push(c->P, c->fr, c->P.ev_t, c->P.ev_x, c->P.ev_y, c->P.ev_p, m,
-                                    c->stream, ev);
-        });
+    if (c->prm.fuse_iters != 0 && n <= cap) {
+        // like a device push: binned by the next solve's first launch
+        if ((int)c->deferred.size() == rec::kMaxSegs) {
+            rc = flush_deferred(c);
+            if (rc) return rc;
+        }
+        Seg sg;
+        rc = stage_events(c, t_us, x, y, polarity, n, &sg);
         if (rc) return rc;
-        if (hipEventRecord(c->staging_done, c->stream) != hipSuccess) return REC_EDEVICE;
-        c->staging_busy = true;
+        c->deferred.push_back(sg);
+        c->deferred_events += n;
+    } else {
+        // the unfused loop, or a push beyond the staging: scattered now
+        rc = flush_deferred(c);
+        if (rc) return rc;
+        for (int64_t a = 0; a < n; a += cap) {
+            const int64_t m = (n - a < cap) ? n - a : cap;
+            Seg sg;
+            rc = stage_events(c, t_us + a, x + a, y + a, polarity + a, m, &sg);
+            if (rc) return rc;
+            rc = timed(c, 0, m, [&](rec::LaunchEv ev) {
+                return rec::launch_push(c->P, c->fr, sg.t, sg.x, sg.y, sg.p, m, c->stream, ev);
+            });
+            if (rc) return rc;
+        }
+        c->counts_dirty = true;
     }
-    c->counts_dirty = true;
     c->mirror_started = true;
     c->mirror_tref = t_us[n - 1];
     return REC_OK;
@@ -784,7 +852,8 @@ int rec_destroy(rec_ctx* c) {
     int rc = REC_OK;
     if (hipStreamSynchronize(c->stream) != hipSuccess) rc = REC_EDEVICE;
     for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
-    if (c->staging_done) (void)hipEventDestroy(c->staging_done);
+    for (hipEvent_t e : c->stage_done)
+        if (e) (void)hipEventDestroy(e);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return rc;

@@ -443,20 +443,47 @@ def test_device_push_errors_are_deferred_and_atomic():
 # --------------------------------------------------------------------------
 
 def test_folded_pushes_match_scattered_pushes(c1):
-    """Device-pointer pushes are binned by the solve's first launch; host
-    pushes are scattered by their own kernels.  Both give the same image,
-    time planes and latest timestamps, bit for bit."""
+    """Device-pointer pushes and host pushes of at most max_events events are
+    binned by the solve's first launch; host pushes larger than max_events
+    are split and scattered by kernels of their own.  All three give the
+    same image, time planes and latest timestamps, bit for bit."""
     a = rec.Reconstructor(128, 128)
     b = rec.Reconstructor(128, 128)
+    s = rec.Reconstructor(128, 128, max_events=128)
     for blk in evgen.batches(c1.events, 500)[:6]:
         a.push(*device_events(blk), on_device=True)
         b.push(blk.t, blk.x, blk.y, blk.p)
+        s.push(blk.t, blk.x, blk.y, blk.p)
         sa = a.solve(50, stats=True)
-        sb = b.solve(50, stats=True)
-        assert (sa.t_ref_us, sa.events_in_batch) == (sb.t_ref_us, sb.events_in_batch)
+        for other in (b, s):
+            so = other.solve(50, stats=True)
+            assert (sa.t_ref_us, sa.events_in_batch) == (so.t_ref_us, so.events_in_batch)
     for plane in (rec.REC_U, rec.REC_F, rec.REC_TX, rec.REC_TY, rec.REC_STATE_P, rec.REC_T_LAST,
                   rec.REC_TIME):
         assert np.array_equal(a.image(plane), b.image(plane)), plane
+        assert np.array_equal(a.image(plane), s.image(plane)), plane
+
+
+def test_host_pushes_through_the_staging_ring(c1):
+    """A small staging ring (max_events 256: two pushes of 100 events per
+    half) is reused while earlier pushes of the half are still recorded
+    (they are scattered first) and while earlier solves are still queued
+    (nothing synchronises between them); every block matches the oracle."""
+    r, o = make(128, 128, max_events=256)
+    blocks = evgen.batches(c1.events.slice(0, 2100), 100)
+    assert len(blocks) == 21
+    for i, blk in enumerate(blocks):
+        r.push(blk.t, blk.x, blk.y, blk.p)
+        o.push_events(blk)
+        if i % 7 == 6:
+            r.solve(20)
+            o.solve(20)
+    st = r.solve(20, stats=True)
+    o.solve(20)
+    assert st.events_in_batch == 0 and st.t_ref_us == o.t_ref
+    assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST))
+    assert np.array_equal(r.image(rec.REC_TX), o.get(oracle.TX32))
+    assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
 
 
 def _dev(t, x, y, p):
