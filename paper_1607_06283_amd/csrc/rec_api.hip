@@ -393,7 +393,9 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
         return REC_EDEVICE;
     }
     const size_t ne = (size_t)prm->max_events;
-    if (hipHostMalloc((void**)&c->pinned, 2 * stage_half(ne), hipHostMallocDefault) !=
+    // coherent: the copy kernel reads each byte once, and no GPU cache line
+    // of it can outlive the host's rewrite of a half
+    if (hipHostMalloc((void**)&c->pinned, 2 * stage_half(ne), hipHostMallocCoherent) !=
         hipSuccess) {
         delete c;
         return REC_ENOMEM;

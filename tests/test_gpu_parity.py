@@ -736,14 +736,18 @@ def test_batch_equals_individual_solves(mode, tune):
     buffers, folded and scattered pushes, two iteration counts) with the
     program's own eager work and readbacks between replays, and every
     replay is checked.  Untuned, all sizes share one geometry; tuned, the
-    sizes may get several."""
+    sizes may get several.  Pushes: device pointers (folded), host pushes
+    above max_events (split and scattered at once) and host pushes of 100
+    events through a staging ring of one such push per half (when the ring
+    comes back to a half whose push is still recorded, the recorded pushes
+    are scattered; the last one or two of a block are folded)."""
     rng = np.random.default_rng(4)
     steps = 6
     streams = []
     for i, (W, H) in enumerate(BATCH_SHAPES):
         n = int(rng.integers(200, 3000))
         streams.append(_random_stream(W, H, steps * n, seed=W * 31 + H + i))
-    recs = [rec.Reconstructor(W, H) for (W, H) in BATCH_SHAPES]
+    recs = [rec.Reconstructor(W, H, max_events=128) for (W, H) in BATCH_SHAPES]
     u_before = [r.image(rec.REC_U) for r in recs]
     batch = rec.Batch(recs, tune_iters=tune)
     if not tune:
@@ -764,17 +768,21 @@ def test_batch_equals_individual_solves(mode, tune):
     for r, u in zip(recs, u_before):
         assert np.array_equal(r.image(rec.REC_U), u)
     batch.set_mode(mode)
-    solo = [rec.Reconstructor(W, H) for (W, H) in BATCH_SHAPES]
+    solo = [rec.Reconstructor(W, H, max_events=128) for (W, H) in BATCH_SHAPES]
     for step in range(steps):
         iters = 50 if step == 4 else 37
-        host = step == 3  # scattered pushes: no class folds events into its first launch
         for (t, x, y, p), r, s in zip(streams, recs, solo):
             n = len(t) // steps
             sl = slice(step * n, (step + 1) * n)
             ev = evgen.Events(t[sl], x[sl], y[sl], p[sl], np.zeros(n, np.uint8))
-            if host:
+            if step == 3:
+                # scattered pushes: no class folds events into its first launch
                 r.push(ev.t, ev.x, ev.y, ev.p)
                 s.push(ev.t, ev.x, ev.y, ev.p)
+            elif step == 5:
+                for a in range(0, n, 100):
+                    r.push(ev.t[a:a + 100], ev.x[a:a + 100], ev.y[a:a + 100], ev.p[a:a + 100])
+                    s.push(ev.t[a:a + 100], ev.x[a:a + 100], ev.y[a:a + 100], ev.p[a:a + 100])
             else:
                 r.push(*device_events(ev), on_device=True)
                 s.push(*device_events(ev), on_device=True)
