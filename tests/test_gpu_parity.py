@@ -533,6 +533,31 @@ def test_folded_push_errors_all_or_nothing():
     assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL
 
 
+@pytest.mark.parametrize("fuse", [-1, 0])
+def test_host_push_sizes_at_the_staging_limit(c1, fuse):
+    """Host pushes of exactly max_events events (one record filling a half
+    of the staging ring), of max_events + 1 (split: a full record and a
+    single event, scattered at once), of single events and of max_events - 1,
+    in the fused loop (records folded into the first launch) and in the
+    unfused one (every record scattered): the oracle's result after every
+    solve."""
+    cap = 64
+    r, o = make(128, 128, max_events=cap, fuse_iters=fuse)
+    ev = c1.events.slice(0, 2000)
+    sizes = [cap, cap + 1, 1, cap - 1, 1, 1, cap, 2 * cap + 1, cap]
+    a = 0
+    for k, n in enumerate(sizes):
+        r.push(ev.t[a:a + n], ev.x[a:a + n], ev.y[a:a + n], ev.p[a:a + n])
+        o.push(ev.t[a:a + n], ev.x[a:a + n], ev.y[a:a + n], ev.p[a:a + n])
+        a += n
+        if k % 3 == 2:
+            st = r.solve(30, stats=True)
+            o.solve(30)
+            assert st.t_ref_us == o.t_ref
+            assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST)), k
+            assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL, k
+
+
 def test_many_pushes_per_solve(c1):
     """More device pushes than the first launch folds: the earlier ones are
     scattered, the rest folded; the result matches the oracle."""
