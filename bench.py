@@ -208,12 +208,14 @@ BATCH_MODES = {"serial": 0, "streams": 1, "graph": 2}
 
 
 def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph"),
-                  geometry=None, per_camera=True, profile=True):
+                  geometry=None, per_camera=True, profile=True, host_events=False):
     """Time `steps` blocks of all 64 cameras: the batched solve in each of
     `modes` (each pass after 2 warm-up blocks of its own; the first listed
-    is also profiled), then one solve per camera.  Returns per-pass seconds,
-    the profile of the first mode, the class configuration, the pixel count
-    and the events per block."""
+    is also profiled), then one solve per camera.  The events are resident
+    in device memory and pushed as device pointers, or with host_events
+    pushed from host memory.  Returns per-pass seconds, the profile of the
+    first mode, the class configuration, the pixel count and the events per
+    block."""
     import torch
     from paper_1607_06283_amd import rec
 
@@ -223,8 +225,14 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
     recs, bufs = [], []
     for W, H, bs, ev in cams:
         recs.append(rec.Reconstructor(W, H))
-        bufs.append((torch.from_numpy(ev.t).to(dev), torch.from_numpy(ev.x.view(np.int16)).to(dev),
-                     torch.from_numpy(ev.y.view(np.int16)).to(dev), torch.from_numpy(ev.p).to(dev), bs))
+        if host_events:
+            arrs = [np.ascontiguousarray(a) for a in (ev.t, ev.x, ev.y, ev.p)]
+            bufs.append((arrs, [a.ctypes.data for a in arrs], bs))
+        else:
+            arrs = [torch.from_numpy(ev.t).to(dev), torch.from_numpy(ev.x.view(np.int16)).to(dev),
+                    torch.from_numpy(ev.y.view(np.int16)).to(dev), torch.from_numpy(ev.p).to(dev)]
+            bufs.append((arrs, [a.data_ptr() for a in arrs], bs))
+    on_dev = 0 if host_events else 1
     batch = rec.Batch(recs, tune_iters=iters if tune and not geometry else 0)
     for g in geometry or ():
         batch.set_geometry(*g)
@@ -233,10 +241,10 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
     def step(batched):
         i = block[0]
         block[0] += 1
-        for r, (t, x, y, p, bs) in zip(recs, bufs):
+        for r, (_, base, bs) in zip(recs, bufs):
             a = i * bs
-            rc = rec.rec_push_events(r.ctx, t.data_ptr() + 8 * a, x.data_ptr() + 2 * a,
-                                     y.data_ptr() + 2 * a, p.data_ptr() + a, bs, 1)
+            rc = rec.rec_push_events(r.ctx, base[0] + 8 * a, base[1] + 2 * a, base[2] + 2 * a,
+                                     base[3] + a, bs, on_dev)
             if rc:
                 raise rec.RecError(rc, "rec_push_events")
         if batched:
@@ -282,13 +290,13 @@ def run_streams64(steps, warmup, iters, tune=True, modes=("streams", "serial", "
 
 
 def streams64_result(steps, warmup, iters, tune=True, modes=("streams", "serial", "graph"),
-                     geometry=None, per_camera=True, profile=True):
+                     geometry=None, per_camera=True, profile=True, host_events=False):
     """The 64-camera workload: the batched solve in its default mode (the
     first of the timed modes) with the other modes and one solve per camera
     beside it, the class geometries, and the roofline of the batched launch."""
     dts, prof, cfg, px, evs = run_streams64(steps, warmup, iters, tune=tune, modes=modes,
                                             geometry=geometry, per_camera=per_camera,
-                                            profile=profile)
+                                            profile=profile, host_events=host_events)
     dt = dts[modes[0]]
     rate = lambda d: round(steps * iters * px / d / 1e6, 2)
     res = {
@@ -483,7 +491,8 @@ def main_streams64(args):
     geometry = parse_geometry(args.batch_geometry) if args.batch_geometry else None
     modes = tuple(args.batch_modes.split(","))
     r = streams64_result(steps, warmup, IT, tune=not args.no_tune, modes=modes, geometry=geometry,
-                         per_camera=not args.no_per_camera, profile=not args.no_profile)
+                         per_camera=not args.no_per_camera, profile=not args.no_profile,
+                         host_events=args.host_events)
     out = {
         "metric": METRIC, "value": r.pop("value"), "unit": "PD iter*Mpix/s", "n_gpus": 1,
         "steps": steps, "warmup": warmup, "ms_per_step": r.pop("ms_per_step"),
@@ -491,7 +500,7 @@ def main_streams64(args):
         "storage": "f32", "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT["streams64"], "cameras": 64,
                    "iters_per_batch": IT, "autotuned": not (args.no_tune or geometry),
-                   "mode": modes[0]},
+                   "mode": modes[0], "events_from": "host" if args.host_events else "device"},
     }
     out.update(r)
     print(json.dumps(out), flush=True)

@@ -15,6 +15,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -116,14 +117,20 @@ struct rec_ctx {
     // Host-pointer pushes are staged as packed records (t, x, y, polarity of
     // one push, back to back) in a ring of two halves: the pinned host buffer
     // and the workspace's staging ring hold a record at the same offset, and
-    // one copy kernel moves it.  Records fill the current half (stage_cur) up
-    // to stage_used; stage_done[h]: the last copy out of half h.
+    // a copy kernel moves it.  Records fill the current half (stage_cur) up
+    // to stage_used; stage_done[h]: the last copy out of half h.  The copies
+    // are recorded (pulls; pull_halves: the halves they read) and launched
+    // together before anything reads the records: by the solve (a batched
+    // solve launches the copies of all its contexts at once), or by a call
+    // that scatters the records.
     char* pinned;
     const char* pinned_dev;  // its device address
     size_t stage_used;
     int stage_cur;
     hipEvent_t stage_done[2];
     bool stage_busy[2];
+    std::vector<rec::PullDesc> pulls;
+    unsigned pull_halves;
     // device-pointer pushes recorded but not scattered yet (in order)
     std::vector<Seg> deferred;
     int64_t deferred_events;
@@ -211,8 +218,37 @@ int read_state(rec_ctx* c, rec::DevState* out) {
     return REC_OK;
 }
 
-// Scatters the recorded device-pointer pushes with their own kernels.
+// Marks the copies recorded for c as launched: the host may rewrite the
+// pinned bytes of a half they read once stage_done of that half has passed.
+int pulls_launched(rec_ctx* c) {
+    for (int h = 0; h < 2; ++h) {
+        if (!((c->pull_halves >> h) & 1u)) continue;
+        if (hipEventRecord(c->stage_done[h], c->stream) != hipSuccess) return REC_EDEVICE;
+        c->stage_busy[h] = true;
+    }
+    c->pulls.clear();
+    c->pull_halves = 0;
+    return REC_OK;
+}
+
+// Launches the recorded copies of host-pointer pushes (one launch per
+// kMaxPulls copies) on the context's stream.
+int flush_pulls(rec_ctx* c) {
+    for (size_t a = 0; a < c->pulls.size(); a += rec::kMaxPulls) {
+        const int m = (int)std::min(c->pulls.size() - a, (size_t)rec::kMaxPulls);
+        const int rc = timed(c, 0, 0, [&](rec::LaunchEv ev) {
+            return rec::launch_pulls(c->pulls.data() + a, m, c->stream, ev.start, ev.stop);
+        });
+        if (rc) return rc;
+    }
+    return pulls_launched(c);
+}
+
+// Scatters the recorded pushes with their own kernels (the copies of host
+// pushes first).
 int flush_deferred(rec_ctx* c) {
+    const int rc0 = flush_pulls(c);
+    if (rc0) return rc0;
     for (const Seg& s : c->deferred) {
         const int rc = timed(c, 0, s.n, [&](rec::LaunchEv ev) {
             return rec::launch_push(c->P, c->fr, s.t, s.x, s.y, s.p, s.n, c->stream, ev);
@@ -226,13 +262,14 @@ int flush_deferred(rec_ctx* c) {
 }
 
 // Copies the n events of a host-pointer push (at most max_events) into the
-// staging ring as one packed record: written to the pinned buffer, then
-// moved by a copy kernel on the context's stream; *out gets the record's
-// four device arrays.  When the current half is full, the record starts
-// the other one: the pushes still recorded in that half are scattered
-// first (the copy, enqueued after them, then overwrites nothing still to be
-// read), and the host waits for the half's last copy before rewriting its
-// pinned bytes, so it runs at most about a half ahead of the device.
+// staging ring as one packed record: written to the pinned buffer, with its
+// copy to the device recorded (launched later, with the others, by
+// flush_pulls or a batched solve); *out gets the record's four device
+// arrays.  When the current half is full, the record starts the other one:
+// the pushes still recorded in that half are scattered first (the copy,
+// enqueued after them, then overwrites nothing still to be read), and the
+// host waits for the half's last copy before rewriting its pinned bytes, so
+// it runs at most about a half ahead of the device.
 int stage_events(rec_ctx* c, const int64_t* t, const uint16_t* x, const uint16_t* y,
                  const int8_t* p, int64_t n, Seg* out) {
     const size_t m = (size_t)n, need = 13 * m, half = stage_half((size_t)c->prm.max_events);
@@ -245,6 +282,10 @@ int stage_events(rec_ctx* c, const int64_t* t, const uint16_t* x, const uint16_t
                 if (rc) return rc;
                 break;
             }
+        }
+        if ((c->pull_halves >> o) & 1u) {  // its last copy is still to be launched
+            const int rc = flush_pulls(c);
+            if (rc) return rc;
         }
         if (c->stage_busy[o] && hipEventSynchronize(c->stage_done[o]) != hipSuccess)
             return REC_EDEVICE;
@@ -261,13 +302,8 @@ int stage_events(rec_ctx* c, const int64_t* t, const uint16_t* x, const uint16_t
     memcpy(h + 12 * m, p, m);
     char* d = (char*)c->P.ev_t + off;
     // whole 16-byte words: the slot extends to the next 256-byte boundary
-    const int rc = timed(c, 0, 0, [&](rec::LaunchEv ev) {
-        return rec::launch_pull(c->pinned_dev + off, d, (need + 15) & ~(size_t)15, c->stream,
-                                ev.start, ev.stop);
-    });
-    if (rc) return rc;
-    if (hipEventRecord(c->stage_done[hh], c->stream) != hipSuccess) return REC_EDEVICE;
-    c->stage_busy[hh] = true;
+    c->pulls.push_back(rec::PullDesc{c->pinned_dev + off, d, (need + 15) & ~(size_t)15});
+    c->pull_halves |= 1u << hh;
     c->stage_used = align_up(c->stage_used + need);
     *out = Seg{(const int64_t*)d, (const uint16_t*)(d + 8 * m), (const uint16_t*)(d + 10 * m),
                (const int8_t*)(d + 12 * m), n};
@@ -349,12 +385,34 @@ int rec_check_events(const int64_t* t_us, const uint16_t* x, const uint16_t* y,
     if (n < 0 || width < 1 || height < 1) return REC_EINVAL;
     if (n == 0) return REC_OK;
     if (!t_us || !x || !y || !polarity) return REC_EINVAL;
+    // Blocks of events are checked with branch-free flags (a loop the
+    // compiler vectorises); a block with a failing event is checked again
+    // in order, which gives the code of the first failing check of the
+    // first failing event.
+    constexpr int64_t kBlock = 512;
     int64_t prev = t_prev;
-    for (int64_t i = 0; i < n; ++i) {
-        if (polarity[i] != 1 && polarity[i] != -1) return REC_EINVAL;
-        if (x[i] >= width || y[i] >= height) return REC_ERANGE;
-        if (t_us[i] < prev) return REC_EORDER;
-        prev = t_us[i];
+    for (int64_t a = 0; a < n; a += kBlock) {
+        const int64_t m = n - a < kBlock ? n - a : kBlock;
+        const int64_t* t = t_us + a;
+        const uint16_t* xs = x + a;
+        const uint16_t* ys = y + a;
+        const int8_t* ps = polarity + a;
+        unsigned bad = t[0] < prev;
+        for (int64_t i = 1; i < m; ++i) bad |= (unsigned)(t[i] < t[i - 1]);
+        for (int64_t i = 0; i < m; ++i) {
+            // polarity +-1: (p + 1) is 0 or 2
+            bad |= (unsigned)((((int)ps[i] + 1) & ~2) != 0);
+            bad |= (unsigned)(xs[i] >= width) | (unsigned)(ys[i] >= height);
+        }
+        if (bad) {
+            for (int64_t i = 0; i < m; ++i) {
+                if (ps[i] != 1 && ps[i] != -1) return REC_EINVAL;
+                if (xs[i] >= width || ys[i] >= height) return REC_ERANGE;
+                if (t[i] < prev) return REC_EORDER;
+                prev = t[i];
+            }
+        }
+        prev = t[m - 1];
     }
     return REC_OK;
 }
@@ -394,7 +452,8 @@ int rec_init(const rec_params* prm, void* dev_workspace, size_t ws_bytes, void* 
     }
     const size_t ne = (size_t)prm->max_events;
     // coherent: the copy kernel reads each byte once, and no GPU cache line
-    // of it can outlive the host's rewrite of a half
+    // of it can outlive the host's rewrite of a half (non-coherent memory
+    // measured the same)
     if (hipHostMalloc((void**)&c->pinned, 2 * stage_half(ne), hipHostMallocCoherent) !=
         hipSuccess) {
         delete c;
@@ -489,6 +548,7 @@ int rec_push_events(rec_ctx* c, const int64_t* t_us, const uint16_t* x, const ui
             const int64_t m = (n - a < cap) ? n - a : cap;
             Seg sg;
             rc = stage_events(c, t_us + a, x + a, y + a, polarity + a, m, &sg);
+            if (!rc) rc = flush_pulls(c);
             if (rc) return rc;
             rc = timed(c, 0, m, [&](rec::LaunchEv ev) {
                 return rec::launch_push(c->P, c->fr, sg.t, sg.x, sg.y, sg.p, m, c->stream, ev);
@@ -526,6 +586,9 @@ int rec_solve(rec_ctx* c, int32_t iters, rec_stats* stats) {
                c->deferred_events * (tiles > dn_tiles ? tiles : dn_tiles) <= kFoldMaxWork;
     }
     if (fold) {
+        // the copies of the host pushes' records go first
+        rc = flush_pulls(c);
+        if (rc) return rc;
         for (size_t s = 0; s < c->deferred.size(); ++s) {
             segs.t[s] = c->deferred[s].t;
             segs.x[s] = c->deferred[s].x;
@@ -966,8 +1029,9 @@ struct rec_batch {
     rec::StreamDesc* d_desc[2];  // alternating per solve
     int2* d_work;
     int64_t work_cap;
-    // pinned staging of the descriptors
+    // pinned staging of the descriptors (h_desc_dev: their device addresses)
     rec::StreamDesc* h_desc[2];
+    const void* h_desc_dev[2];
     hipEvent_t copied[2];
     bool copy_used[2];
     int parity;
@@ -1306,10 +1370,14 @@ int rec_batch_init(rec_ctx* const* ctxs, int32_t n, void* dev_workspace, size_t 
     b->work_cap = (int64_t)((ws_bytes - 2 * batch_desc_bytes(n)) / sizeof(int2));
     int rc = REC_OK;
     for (int q = 0; q < 2 && !rc; ++q) {
-        if (hipHostMalloc((void**)&b->h_desc[q], (size_t)n * sizeof(rec::StreamDesc),
-                          hipHostMallocDefault) != hipSuccess)
+        // as long as the device buffer (the copy kernel reads whole 16-byte
+        // words); coherent, like the push staging
+        if (hipHostMalloc((void**)&b->h_desc[q], batch_desc_bytes(n), hipHostMallocCoherent) !=
+            hipSuccess)
             rc = REC_ENOMEM;
-        else if (hipEventCreateWithFlags(&b->copied[q], hipEventDisableTiming) != hipSuccess)
+        else if (hipHostGetDevicePointer((void**)&b->h_desc_dev[q], b->h_desc[q], 0) !=
+                     hipSuccess ||
+                 hipEventCreateWithFlags(&b->copied[q], hipEventDisableTiming) != hipSuccess)
             rc = REC_EDEVICE;
     }
     if (!rc && (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
@@ -1410,10 +1478,24 @@ int rec_batch_solve(rec_batch* b, int32_t iters) {
     unsigned fold = 0;
     fill_desc(b, b->h_desc[q], &fold);
     const size_t n = b->ctx.size();
-    if (hipMemcpyAsync(b->d_desc[q], b->h_desc[q], n * sizeof(rec::StreamDesc),
-                       hipMemcpyHostToDevice, b->stream) != hipSuccess ||
-        hipEventRecord(b->copied[q], b->stream) != hipSuccess)
-        return REC_EDEVICE;
+    // one copy kernel (per kMaxPulls copies) moves the descriptors and the
+    // records of every context's host pushes
+    std::vector<rec::PullDesc> pl;
+    pl.push_back(rec::PullDesc{b->h_desc_dev[q], b->d_desc[q],
+                               (n * sizeof(rec::StreamDesc) + 15) & ~(size_t)15});
+    for (rec_ctx* c : b->ctx) pl.insert(pl.end(), c->pulls.begin(), c->pulls.end());
+    for (size_t a = 0; a < pl.size(); a += rec::kMaxPulls) {
+        const int m = (int)std::min(pl.size() - a, (size_t)rec::kMaxPulls);
+        rc = timed(b->lead, 0, 0, [&](rec::LaunchEv ev) {
+            return rec::launch_pulls(pl.data() + a, m, b->stream, ev.start, ev.stop);
+        });
+        if (rc) return rc;
+    }
+    for (rec_ctx* c : b->ctx) {
+        rc = pulls_launched(c);
+        if (rc) return rc;
+    }
+    if (hipEventRecord(b->copied[q], b->stream) != hipSuccess) return REC_EDEVICE;
     b->copy_used[q] = true;
     b->parity ^= 1;
     if (b->mode == REC_BATCH_GRAPH && !b->lead->prof_on) {

@@ -145,6 +145,61 @@ def test_event_validation_codes():
     assert rec.rec_check_events(t[:0], x[:0], y[:0], p[:0], 4, 3) == rec.REC_OK
 
 
+def _check_events_reference(t, x, y, p, W, H, t_prev):
+    """The validation rule event by event: the first event that fails a check
+    decides, with its first failing check (polarity, then position, then
+    order against the previous timestamp)."""
+    prev = t_prev
+    for i in range(len(t)):
+        if p[i] not in (1, -1):
+            return rec.REC_EINVAL
+        if x[i] >= W or y[i] >= H:
+            return rec.REC_ERANGE
+        if t[i] < prev:
+            return rec.REC_EORDER
+        prev = t[i]
+    return rec.REC_OK
+
+
+def test_event_validation_matches_the_sequential_rule():
+    """Streams spanning several of the validator's 512-event blocks, with one
+    or two planted faults (at block boundaries among other places, an event
+    failing several checks at once, an order fault across two blocks): the
+    code of the sequential rule every time."""
+    rng = np.random.default_rng(11)
+    W, H = 70, 40
+    sizes = [1, 511, 512, 513, 1024, 1500, 2049]
+    cases = 0
+    for n in sizes:
+        for trial in range(12):
+            t = np.sort(rng.integers(0, 10 * n, n)).astype(np.int64)
+            x = rng.integers(0, W, n).astype(np.uint16)
+            y = rng.integers(0, H, n).astype(np.uint16)
+            p = np.where(rng.random(n) < 0.5, 1, -1).astype(np.int8)
+            assert rec.rec_check_events(t, x, y, p, W, H) == rec.REC_OK
+            picks = [int(i) for i in rng.integers(0, n, 2)] + [min(n - 1, 511), min(n - 1, 512)]
+            for i in rng.choice(picks, size=1 + trial % 2, replace=False):
+                kind = (trial + int(i)) % 5
+                if kind == 0:
+                    p[i] = (0, 2, -2, 127, -128)[trial % 5]
+                elif kind == 1:
+                    x[i] = W + trial
+                elif kind == 2:
+                    y[i] = H
+                elif kind == 3 and i > 0:
+                    t[i] = t[i - 1] - 1
+                else:  # several checks fail at once
+                    p[i] = 0
+                    x[i] = W
+                    if i > 0:
+                        t[i] = t[i - 1] - 5
+            for t_prev in (-(2 ** 63), int(t[0]), int(t[0]) + 1):
+                want = _check_events_reference(t, x, y, p, W, H, t_prev)
+                assert rec.rec_check_events(t, x, y, p, W, H, t_prev=t_prev) == want, (n, trial)
+                cases += 1
+    assert cases == len(sizes) * 12 * 3
+
+
 def test_strerror_covers_codes():
     for c in range(0, -8, -1):
         assert rec.rec_strerror(c) != "unknown status code"
