@@ -51,12 +51,14 @@
  *     launch of the next rec_solve validates and bins them itself (or, for
  *     more pushes or events than it takes, they are scattered by kernels of
  *     their own at that point).  Host-pointer pushes are validated on the
- *     host, written to the pinned staging buffer and moved by a copy kernel on
- *     the context's stream into the workspace's staging ring; from there
- *     they take the same way (the unfused loop, and a push of more than
- *     max_events events, scatter them at once).  The ring has room for two
- *     pushes of max_events events: a push that starts a half waits on the
- *     host for the last copy out of that half.
+ *     host and written to the pinned staging buffer; one copy kernel on the
+ *     context's stream moves all such records pending into the workspace's
+ *     staging ring when they are first needed (by the next solve -- for a
+ *     batch, one launch for all its contexts -- or a call that scatters
+ *     them); from there they take the same way (the unfused loop, and a
+ *     push of more than max_events events, scatter them at once).  The
+ *     ring has room for two pushes of max_events events: a push that starts
+ *     a half waits on the host for the last copy out of that half.
  *   - rec_push_events and rec_solve without stats do not synchronise.
  *     rec_solve with stats, rec_get_image, rec_gap_history, rec_get_times,
  *     rec_set_state, rec_profile_read, rec_sync and rec_destroy synchronise
