@@ -841,6 +841,10 @@ State at(State s0, size_t stride, int k) {
 // launch.  Measured on 16 x 346x260 (forward+backward, 100 iterations):
 // reverse 4x8 with 5 steps 2.73 ms; 2x16 with 3/4/5/6/8 steps 3.07/2.96/
 // 2.94/2.87/3.23 ms; forward 8x4 or 2x16 instead of 4x16: 3.63, 3.27 ms.
+// With the current kernels (2.41 ms): reverse 4x16 with 5 or 8 steps 2.50,
+// 2.47 ms (one 1024-lane workgroup per compute unit); 4x8 with up to 7
+// steps (7 + 3 per checkpoint segment) 2.39-2.40 ms, within run-to-run
+// spread of the 5 + 5 split.
 struct FusedShape {
     int fr, fw, fk;  // forward rows, waves, max iterations per launch
     int rr, rw, rk;  // reverse rows, waves, max steps per launch
