@@ -310,7 +310,6 @@ int stage_events(rec_ctx* c, const int64_t* t, const uint16_t* x, const uint16_t
     return REC_OK;
 }
 
-
 }  // namespace
 
 extern "C" {
