@@ -821,6 +821,32 @@ def test_batch_equals_individual_solves(mode, tune):
     batch.close()
 
 
+@pytest.mark.parametrize("mode", [rec.REC_BATCH_STREAMS, rec.REC_BATCH_GRAPH])
+def test_batch_host_pushes_beyond_one_copy_launch(mode):
+    """16 cameras, each with four host pushes per block: with the descriptor
+    upload that is 65 copies, more than one copy launch takes, so a batched
+    solve launches two.  Every camera gets the same bits as its own solve."""
+    shapes = [(48 + 3 * i, 40 - i) for i in range(16)]
+    streams = [_random_stream(W, H, 3 * 4 * 30, seed=5 * W + H) for (W, H) in shapes]
+    recs = [rec.Reconstructor(W, H) for (W, H) in shapes]
+    solo = [rec.Reconstructor(W, H) for (W, H) in shapes]
+    batch = rec.Batch(recs, tune_iters=0)
+    batch.set_mode(mode)
+    for blk in range(3):
+        for (t, x, y, p), r, o in zip(streams, recs, solo):
+            for k in range(4):
+                sl = slice((4 * blk + k) * 30, (4 * blk + k + 1) * 30)
+                r.push(t[sl], x[sl], y[sl], p[sl])
+                o.push(t[sl], x[sl], y[sl], p[sl])
+        batch.solve(25)
+        for o in solo:
+            o.solve(25)
+        for i, (r, o) in enumerate(zip(recs, solo)):
+            assert np.array_equal(r.image(rec.REC_U), o.image(rec.REC_U)), (blk, i)
+            assert np.array_equal(r.image(rec.REC_T_LAST), o.image(rec.REC_T_LAST)), (blk, i)
+    batch.close()
+
+
 @pytest.mark.parametrize("storage", [rec.REC_STORE_F16, rec.REC_STORE_BF16])
 def test_batch_16bit_storage_equals_individual_solves(storage):
     """16-bit storage of p and tx, ty in a batch (64- and 32-column classes):
