@@ -558,6 +558,32 @@ def test_host_push_sizes_at_the_staging_limit(c1, fuse):
             assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL, k
 
 
+def test_mixed_device_and_host_pushes(c1):
+    """Device and host pushes alternating within blocks (a host push after a
+    device push first learns the stream state, which scatters the recorded
+    device push; the pushes after it are recorded in order, host records
+    beside device arrays): the oracle's result after every solve."""
+    r, o = make(128, 128)
+    ev = c1.events.slice(0, 2400)
+    a = 0
+    for blk in range(4):
+        for k, n in enumerate((150, 90, 160, 200)):
+            sl = slice(a, a + n)
+            a += n
+            part = evgen.Events(ev.t[sl], ev.x[sl], ev.y[sl], ev.p[sl], np.zeros(n, np.uint8))
+            if (k + blk) % 2 == 0:
+                r.push(*device_events(part), on_device=True)
+            else:
+                r.push(part.t, part.x, part.y, part.p)
+            o.push_events(part)
+        st = r.solve(40, stats=True)
+        o.solve(40)
+        assert st.t_ref_us == o.t_ref and st.events_in_batch == 600
+        assert np.array_equal(r.image(rec.REC_T_LAST), o.get(oracle.TLAST)), blk
+        assert np.array_equal(r.image(rec.REC_TX), o.get(oracle.TX32)), blk
+        assert np.abs(r.image(rec.REC_U).astype(np.float64) - o.u).max() <= U_TOL, blk
+
+
 def test_many_pushes_per_solve(c1):
     """More device pushes than the first launch folds: the earlier ones are
     scattered, the rest folded; the result matches the oracle."""
