@@ -700,6 +700,8 @@ def main():
     if args.sync_probe:
         return sync_probe()
     if args.workload == "diff16":
+        if args.host_events:
+            raise SystemExit("--host-events: the diff16 workload takes its events as device tensors")
         return main_diff16(args)
     if args.workload == "streams64":
         return main_streams64(args)
