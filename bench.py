@@ -45,13 +45,13 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "shape.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 1072.6, 1024 * 820.7),
-    ("probe", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 553176.2, 1024 * 546481.0),
+    ("davis240", "f32"): ("370653f4c5f231ad", 2 * 1024 * 1071.9, 1024 * 820.7),
+    ("probe", "f32"): ("370653f4c5f231ad", 2 * 1024 * 553172.1, 1024 * 545404.9),
     # the probe with one iteration per launch on 2 x 8 x 64 tiles
-    ("probe_k1", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 409107.4, 1024 * 477107.3),
+    ("probe_k1", "f32"): ("370653f4c5f231ad", 2 * 1024 * 409070.1, 1024 * 477090.7),
     # the batched solve of all 64 cameras: bytes of one whole solve (every
     # launch of every class chain), for the class geometries below
-    ("streams64", "f32"): ("a88ac079a7e809d7", 2 * 1024 * 814292.2, 1024 * 1069606.1),
+    ("streams64", "f32"): ("370653f4c5f231ad", 2 * 1024 * 814282.2, 1024 * 1070065.4),
 }
 # class geometries the 64-camera counters were taken with: (width, height of
 # the class's first camera, rows, waves, columns, iterations per launch)

@@ -1035,10 +1035,11 @@ __device__ __forceinline__ void pd_tile(const Planes& P, Frame fr, const IterCon
     // u alternating between two register sets, so that passing u from one
     // iteration to the next needs no register copies (8 rows: 31 instead of
     // 32 VALU instructions per pixel-iteration in the same 120 VGPRs; with
-    // 16 rows the register pressure undoes the gain).  With 2 rows per lane (many
-    // wavefronts) a wavefront skips the iterations that cannot reach the
-    // exact interior (about a third of them at K = 13).
-    constexpr bool kSkip = R <= 2 && NW > 1;
+    // 16 rows the register pressure undoes the gain).  A wavefront skips the
+    // iterations that cannot reach the exact interior: with 2 rows per lane
+    // about a third of them at K = 13, with 4 rows a seventh (640x480 at
+    // K = 13: +3.5 %), with 8 rows none up to K = 8.
+    constexpr bool kSkip = NW > 1;
     const int wv = __builtin_amdgcn_readfirstlane(wave);
     // med3 takes one scalar operand (umin): umax is held in a vector
     // register once, instead of being copied into one every iteration.
