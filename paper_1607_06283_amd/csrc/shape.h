@@ -23,7 +23,11 @@ namespace rec {
 //                      2x16x64 K 13: 54, 51 G)
 //   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
 //   800x600:           2x8x32 K 8: 153 G (best 154 G)
-//   1280x720:          8x8x64 K 10: 308 G (6x8x64 K 6: 297 G, 8x8x64 K 8: 283 G)
+//   1280x720:          4x16x64 K 10: 360 G, BF16 380 G, FP16 377 G (since a
+//                      wavefront of a 4-row tile skips the iterations that
+//                      cannot reach the exact interior; 8x8x64 K 10: 331 G;
+//                      4x16x64 K 9 / 12: 335 / 286 G); 1024x768 and 960x720
+//                      +6 % over 8x8x64, 1920x1080 -2 %
 //   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G)
 //   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
 //                      (4x8x64 K 6: 284 G, 448 G)
@@ -51,7 +55,7 @@ inline void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* ro
     } else if (np <= 600000) {
         ar = 2, aw = 8, acw = 32, k = 8;
     } else if (np <= 2000000) {
-        ar = 8, aw = 8, acw = 64, k = 10;
+        ar = 4, aw = 16, acw = 64, k = 10;
     } else {
         ar = 8, aw = 8, acw = 64, k = 8;
     }
