@@ -23,12 +23,19 @@ namespace rec {
 //                      2x16x64 K 13: 54, 51 G)
 //   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
 //   800x600:           2x8x32 K 8: 153 G (best 154 G)
-//   1280x720:          4x16x64 K 10: 360 G, BF16 380 G, FP16 377 G (since a
-//                      wavefront of a 4-row tile skips the iterations that
-//                      cannot reach the exact interior; 8x8x64 K 10: 331 G;
-//                      4x16x64 K 9 / 12: 335 / 286 G); 1024x768 and 960x720
-//                      +6 % over 8x8x64, 1920x1080 -2 %
-//   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G)
+//   0.6-16 Mpx:        4x16x64 (since a wavefront of a 4-row tile skips the
+//                      iterations that cannot reach the exact interior),
+//                      K 10 up to 1 Mpx, K 8 beyond: 960x720 267 G,
+//                      1024x768 298 G, 1280x720 360 G (BF16 380, FP16
+//                      377; 8x8x64 K 10: 252, 280, 331 G); 1600x1200
+//                      414 G (K 9 / 10: 380 / 343 G); 1920x1080 388 G
+//                      (K 9: 407-410 G, K 10: 371 G; 8x8x64 K 8: 379 G);
+//                      2560x1440 459 G (448 G); 3840x2160 464 G (455 G).
+//                      Which K wins depends on how the tiles fall on the
+//                      256 compute units, which no simple count predicted
+//                      on all of these frames
+//   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G;
+//                      later 508 G against 503 G for 4x16x64 K 8)
 //   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
 //                      (4x8x64 K 6: 284 G, 448 G)
 // `narrow` allows 32-column tiles (the untuned batch keeps 64 columns: it
@@ -54,8 +61,10 @@ inline void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* ro
         ar = 4, aw = 16, acw = 64, k = 13;
     } else if (np <= 600000) {
         ar = 2, aw = 8, acw = 32, k = 8;
-    } else if (np <= 2000000) {
+    } else if (np <= 1000000) {
         ar = 4, aw = 16, acw = 64, k = 10;
+    } else if (np <= 16000000) {
+        ar = 4, aw = 16, acw = 64, k = 8;
     } else {
         ar = 8, aw = 8, acw = 64, k = 8;
     }
