@@ -45,13 +45,13 @@ BYTES_PER_PX_ITER_16 = 28  # same with p and tx/ty stored in 16 bits
 TRAFFIC_SOURCES = ("kernels.hip", "pd_math.h", "kernels.h", "tile.h", "shape.h")
 MEASURED_TRAFFIC = {
     # (workload, storage): (source hash, fetched bytes, written bytes) per launch
-    ("davis240", "f32"): ("b59f3f0a9268b33e", 2 * 1024 * 1071.9, 1024 * 820.7),
-    ("probe", "f32"): ("b59f3f0a9268b33e", 2 * 1024 * 553215.4, 1024 * 545478.1),
+    ("davis240", "f32"): ("cdb8079d22c58ad3", 2 * 1024 * 1071.9, 1024 * 820.7),
+    ("probe", "f32"): ("cdb8079d22c58ad3", 2 * 1024 * 553205.9, 1024 * 545699.2),
     # the probe with one iteration per launch on 2 x 8 x 64 tiles
-    ("probe_k1", "f32"): ("b59f3f0a9268b33e", 2 * 1024 * 409078.0, 1024 * 477085.7),
+    ("probe_k1", "f32"): ("cdb8079d22c58ad3", 2 * 1024 * 409075.7, 1024 * 477091.9),
     # the batched solve of all 64 cameras: bytes of one whole solve (every
     # launch of every class chain), for the class geometries below
-    ("streams64", "f32"): ("b59f3f0a9268b33e", 2 * 1024 * 814264.0, 1024 * 1070030.2),
+    ("streams64", "f32"): ("cdb8079d22c58ad3", 2 * 1024 * 814279.2, 1024 * 1070089.7),
 }
 # class geometries the 64-camera counters were taken with: (width, height of
 # the class's first camera, rows, waves, columns, iterations per launch)

@@ -21,25 +21,52 @@ namespace rec {
 //   240x180:           1x16x32 K 9: 49 G (2x16x64 K 13: 45 G)
 //   320x240, 346x260:  2x8x32 K 8: 69, 69 G (best of 18 shapes 74, 74 G;
 //                      2x16x64 K 13: 54, 51 G)
-//   480x360, 640x480:  4x16x64 K 13: 97, 162 G (best 103, 162 G)
-//   800x600:           2x8x32 K 8: 153 G (best 154 G)
-//   0.6-16 Mpx:        4x16x64 (since a wavefront of a 4-row tile skips the
+//   0.12-1 Mpx:        4x16x64 (since a wavefront of a 4-row tile skips the
 //                      iterations that cannot reach the exact interior),
-//                      K 10 up to 1 Mpx, K 8 beyond: 960x720 267 G,
-//                      1024x768 298 G, 1280x720 360 G (BF16 380, FP16
-//                      377; 8x8x64 K 10: 252, 280, 331 G); 1600x1200
-//                      414 G (K 9 / 10: 380 / 343 G); 1920x1080 388 G
-//                      (K 9: 407-410 G, K 10: 371 G; 8x8x64 K 8: 379 G);
-//                      2560x1440 459 G (448 G); 3840x2160 464 G (455 G).
-//                      Which K wins depends on how the tiles fall on the
-//                      256 compute units, which no simple count predicted
-//                      on all of these frames
+//                      K by the count below: 640x480 K 13 215 G (K 11:
+//                      203 G), 720x576 K 10 265 G (K 9: 247 G; 2x8x32
+//                      K 8: 203 G), 800x600 K 9 280 G (K 8 / 10 / 13:
+//                      266 / 195 / 208 G; 2x8x32 K 8: 211 G), 960x720
+//                      K 13 291 G (K 10: 272 G), 1024x768 K 10 298 G,
+//                      1280x720 K 10 360 G (BF16 380, FP16 377; 8x8x64
+//                      K 10: 331 G)
+//   1-16 Mpx:          4x16x64 K 8: 1600x1200 417 G (K 9 / 10: 380 /
+//                      343 G; 8x8x64: 332 G), 1920x1080 392 G (K 9:
+//                      407-410 G; 8x8x64: 380 G), 2560x1440 468 G (455 G),
+//                      3840x2160 469 G (461 G); with many tiles a compute
+//                      unit's share of them no longer decides, and no
+//                      simple count picked the best K on all of these
 //   5120x5760:         8x8x64 K 8: 484 G (6x8x64 K 6: 440 G, 8x8x64 K 10: 432 G;
 //                      later 508 G against 503 G for 4x16x64 K 8)
 //   with BF16 storage: 1280x720 8x8x64 K 10 304 G, 5120x5760 8x8x64 K 8 478 G
 //                      (4x8x64 K 6: 284 G, 448 G)
 // `narrow` allows 32-column tiles (the untuned batch keeps 64 columns: it
 // takes 2x16 K 13 up to 250k pixels and the large-frame shape beyond).
+//
+// Iterations per launch K (8..13) of the 4x16x64 tile (64 x 64 pixels, one
+// 1024-lane workgroup; a compute unit holds two) on a W x H frame solved
+// `iters` iterations at a time: the least launches x rounds, launches =
+// ceil(iters / K), rounds = ceil(tiles / 256) (the compute units that hold
+// one tile more than others set the pace of every iteration); on a tie the
+// fewer tiles.  Measured to pick the best K on the frames of 0.12-1 Mpx
+// listed above.
+inline int tile4x16_k(int W, int H, int iters) {
+    if (iters <= 0) iters = 50;
+    int best = 13;
+    long best_cost = 0, best_tiles = 0;
+    for (int K = 8; K <= 13; ++K) {
+        const int ow = 64 - 2 * K;
+        const long tiles = (long)((W + ow - 1) / ow) * (long)((H + ow - 1) / ow);
+        const long cost = (long)((iters + K - 1) / K) * ((tiles + 255) / 256);
+        if (K == 8 || cost < best_cost || (cost == best_cost && tiles < best_tiles)) {
+            best = K;
+            best_cost = cost;
+            best_tiles = tiles;
+        }
+    }
+    return best;
+}
+
 inline void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* rows, int* waves,
                   int* cols, int* kiters) {
     int r = prm->tile_rows, w = prm->tile_waves, cw = prm->tile_cols ? prm->tile_cols : 64, k;
@@ -57,12 +84,8 @@ inline void choose_shape(const rec_params* prm, int64_t np, bool narrow, int* ro
         ar = 1, aw = 16, acw = 32, k = 9;
     } else if (np <= 120000) {
         ar = 2, aw = 8, acw = 32, k = 8;
-    } else if (np <= 400000) {
-        ar = 4, aw = 16, acw = 64, k = 13;
-    } else if (np <= 600000) {
-        ar = 2, aw = 8, acw = 32, k = 8;
     } else if (np <= 1000000) {
-        ar = 4, aw = 16, acw = 64, k = 10;
+        ar = 4, aw = 16, acw = 64, k = tile4x16_k(prm->width, prm->height, prm->iters);
     } else if (np <= 16000000) {
         ar = 4, aw = 16, acw = 64, k = 8;
     } else {
